@@ -1,0 +1,120 @@
+/*
+ * cholgrad.h -- C ABI of libcholgrad: blocked Cholesky factorisation and blocked forward- and
+ * reverse-mode propagation of Cholesky derivatives on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: I. Murray, "Differentiation of the Cholesky decomposition", arXiv:1602.07527 (2016).
+ * The computation chain is x -> Sigma -> L -> f (Sec. 2, eqn (computation)):
+ *   chol_factor : Sigma -> L          lower-triangular L, positive diagonal, L L^T = Sigma (Sec. 1)
+ *   chol_fwd    : (L, Sigma-dot) -> L-dot      forward propagator (Sec. 2; eqn (symfwd))
+ *   chol_rev    : (L, L-bar)     -> Sigma-bar  reverse propagator (Sec. 2; eqns (symrev), (symrevtril))
+ * computed with Level-3 block algorithms derived from the blocked factorisation (Sec. 4.2).
+ *
+ * Conventions for every entry point
+ *   - Matrices are DEVICE pointers, row-major: element (i, j) of an n x n matrix lives at
+ *     A[i * ld + j], with ld >= max(1, n).  Storage type is double for the CHOL_PREC_F64* modes.
+ *   - Only the lower triangle (i >= j) of each input matrix is read (Sec. 4.1: the algorithms only
+ *     inspect the lower triangle).  Sigma-dot is symmetric; its lower triangle defines it (Sec. 3).
+ *   - Outputs overwrite the array in place, as the paper's algorithms do.  The strict upper
+ *     triangle of an output is written as documented per call (never left as garbage).
+ *   - The caller owns all memory, including the workspace (size from chol_workspace_bytes, base
+ *     aligned to 256 bytes).  The library never allocates, frees or synchronises inside these calls;
+ *     all work is enqueued on `stream` (a hipStream_t; NULL means the default stream) in order.
+ *     Calls on distinct (stream, workspace) pairs may run concurrently.
+ *   - Return value: CHOL_SUCCESS (0), or a negative status checked synchronously on the host
+ *     before anything is enqueued:  -i  means argument i (1-based) is invalid;  CHOL_ERR_* below.
+ *     Numerical breakdown of chol_factor is reported asynchronously through `info`.
+ *   - n == 0 is a no-op that returns CHOL_SUCCESS.
+ *   - nb is the block size of the Level-3 sweep (Sec. 4.2, N_b): 0 selects the default (128);
+ *     otherwise 32 <= nb <= 128 and nb % 32 == 0.  The result does not depend on nb beyond
+ *     rounding (the column partition is arbitrary, Sec. 4.2).
+ */
+#ifndef CHOLGRAD_H
+#define CHOLGRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHOLGRAD_VERSION 100
+
+/* Status codes (negative small integers -i name the invalid argument instead). */
+#define CHOL_SUCCESS 0
+#define CHOL_ERR_HIP (-101)          /* a HIP runtime call or kernel launch failed           */
+#define CHOL_ERR_WORKSPACE (-102)    /* workspace NULL, too small, or not 256-byte aligned    */
+#define CHOL_ERR_UNSUPPORTED (-103)  /* precision / form / size combination not implemented */
+
+/* Arithmetic of the call.  Storage is double for all CHOL_PREC_F64* modes. */
+#define CHOL_PREC_F64 0              /* every step in FP64 (FP64 MFMA for the contractions)   */
+
+/* Which reverse-mode output (Sec. 3, eqns (symrev) and (symrevtril); S = L^-T Phi(L^T Lbar) L^-1):
+ *   CHOL_SBAR_SYM  : (S + S^T)/2 in both triangles -- the symmetric gradient, for which
+ *                    Tr(Lbar^T Ldot) = sum_ij Sbar_ij Sdot_ij holds for any symmetric Sigma-dot.
+ *   CHOL_SBAR_TRIL : T = Phi(S + S^T), the paper's lower-triangular in-place output; the strict
+ *                    upper triangle is set to 0.  T + T^T - diag(T) is eqn (symrev)'s form.     */
+#define CHOL_SBAR_SYM 0
+#define CHOL_SBAR_TRIL 1
+
+/* Operation codes for chol_workspace_bytes. */
+#define CHOL_OP_FACTOR 0
+#define CHOL_OP_REV 1
+#define CHOL_OP_FWD 2
+
+/* Bytes of device workspace that a call with these parameters needs (0 for n == 0).  Returns 0
+ * as well for invalid parameters; the call itself then reports the error. */
+size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb);
+
+/*
+ * chol_factor -- blocked Cholesky factorisation, Sec. 4.2 chol_blocked (left-looking DPOTRF):
+ *   per block column: D <- D - tril(R R^T);  D <- chol_unblocked(D);  C <- C - B R^T;
+ *   C <- C tril(D)^-T.
+ *   A     in : tril(A) = tril(Sigma), Sigma symmetric positive definite (n x n, lda).
+ *        out : tril(A) = L; the strict upper triangle is set to 0.
+ *   info  device pointer to one int, written by the call: 0 on success, or k > 0 when the leading
+ *         minor of order k is not positive definite (first non-positive pivot, 1-based, as
+ *         LAPACK); L is then undefined from column k on.  May not be NULL.
+ *   Arguments: 1 precision, 2 n, 3 A, 4 lda, 5 nb, 6 info, 7 workspace, 8 workspace_bytes, 9 stream.
+ */
+int chol_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int *info,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * chol_rev -- reverse-mode propagation Sigma-bar(L, L-bar), Sec. 4.2 chol_blocked_rev, with the
+ * Level-2 adjoint of Sec. 4.1 (chol_unblocked_rev, including the final Phi halving of the
+ * diagonal) on each diagonal block.
+ *   L     in : lower-triangular factor with positive diagonal (n x n, ldl); not modified.
+ *   A     in : tril(A) = L-bar.   out: Sigma-bar in the form selected by sbar_form.
+ *   L and A must not overlap.  A non-positive diagonal in L gives Inf/NaN, never a hang.
+ *   Arguments: 1 precision, 2 n, 3 L, 4 ldl, 5 A, 6 lda, 7 sbar_form, 8 nb, 9 workspace,
+ *              10 workspace_bytes, 11 stream.
+ */
+int chol_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda,
+             int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * chol_fwd -- forward-mode propagation L-dot(L, Sigma-dot), Sec. 4.2 chol_blocked_fwd, with the
+ * Level-2 chol_unblocked_fwd of Sec. 4.1 on each diagonal block:
+ *   D-dot <- D-dot - tril(R-dot R^T + R R-dot^T); D-dot <- chol_unblocked_fwd(D, D-dot);
+ *   C-dot <- C-dot - B-dot R^T - B R-dot^T;  C-dot <- (C-dot - C D-dot^T) D^-T.
+ *   L     in : lower-triangular factor with positive diagonal (n x n, ldl); not modified.
+ *   A     in : tril(A) = tril(Sigma-dot).  out: tril(A) = L-dot; strict upper triangle set to 0.
+ *   L and A must not overlap.
+ *   Arguments: 1 precision, 2 n, 3 L, 4 ldl, 5 A, 6 lda, 7 nb, 8 workspace, 9 workspace_bytes,
+ *              10 stream.
+ */
+int chol_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb,
+             void *workspace, size_t workspace_bytes, void *stream);
+
+/* Human-readable text for a status code (static storage; never NULL). */
+const char *chol_status_string(int status);
+
+/* CHOLGRAD_VERSION of the built library. */
+int chol_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHOLGRAD_H */

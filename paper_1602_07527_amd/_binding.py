@@ -1,0 +1,129 @@
+"""ctypes binding of libcholgrad (argument marshalling only: every step runs in the HIP kernels).
+
+Tensors are torch CUDA (ROCm) tensors used as device memory; calls are enqueued on torch's current
+stream of the tensors' device.  Errors from the C ABI raise CholError.  There is no CPU path: if
+the library is not built, every entry point raises.
+"""
+import ctypes
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcholgrad.so")
+
+PREC_F64 = 0
+SBAR_SYM, SBAR_TRIL = 0, 1
+OP_FACTOR, OP_REV, OP_FWD = 0, 1, 2
+_FORMS = {"sym": SBAR_SYM, "tril": SBAR_TRIL}
+_OPS = {"factor": OP_FACTOR, "rev": OP_REV, "fwd": OP_FWD}
+
+_lib = None
+
+
+class CholError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} returned {status}: {msg}")
+        self.status = status
+
+
+def load_library():
+    """Load libcholgrad.so from the package folder (raises ImportError when it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; "
+                          "g.build()'` from the repository root")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, vp, i32, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    lib.chol_workspace_bytes.argtypes = [i32, i32, i64, i32]
+    lib.chol_workspace_bytes.restype = sz
+    lib.chol_factor.argtypes = [i32, i64, vp, i64, i32, vp, vp, sz, vp]
+    lib.chol_factor.restype = i32
+    lib.chol_rev.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, vp, sz, vp]
+    lib.chol_rev.restype = i32
+    lib.chol_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, sz, vp]
+    lib.chol_fwd.restype = i32
+    lib.chol_status_string.argtypes = [i32]
+    lib.chol_status_string.restype = ctypes.c_char_p
+    lib.chol_version.argtypes = []
+    lib.chol_version.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(fn, status):
+    if status != 0:
+        lib = load_library()
+        raise CholError(fn, status, lib.chol_status_string(status).decode())
+
+
+def _square(name, t):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise ValueError(f"{name} must be square 2-D, got {tuple(t.shape)}")
+    n = t.shape[0]
+    if n > 0 and (t.stride(1) != 1 or t.stride(0) < n):
+        raise ValueError(f"{name} must be row-major with unit column stride")
+    return n
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace_bytes(op, n, nb=0):
+    """Device workspace bytes for op in {'factor', 'rev', 'fwd'} at size n and block size nb."""
+    return int(load_library().chol_workspace_bytes(_OPS[op], PREC_F64, int(n), int(nb)))
+
+
+def _workspace(op, n, nb, device, workspace):
+    need = workspace_bytes(op, n, nb)
+    if workspace is None:
+        return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    if workspace.device != device or workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace must hold {need} bytes on {device}")
+    return workspace
+
+
+def chol_factor(A, nb=0, workspace=None, info=None):
+    """In place: tril(A) = Sigma -> tril(A) = L, strict upper set to 0.  Returns (A, info) where
+    info is a device int32 tensor (0, or the 1-based column of the first non-positive pivot)."""
+    lib = load_library()
+    n = _square("A", A)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    ws = _workspace("factor", n, nb, A.device, workspace)
+    _check("chol_factor", lib.chol_factor(PREC_F64, n, A.data_ptr(), A.stride(0) if n else 1, nb,
+                                          info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return A, info
+
+
+def chol_rev(L, A, form="sym", nb=0, workspace=None):
+    """In place: tril(A) = L-bar -> A = Sigma-bar in the chosen form ('sym' or 'tril')."""
+    lib = load_library()
+    n = _square("L", L)
+    if _square("A", A) != n or A.device != L.device:
+        raise ValueError("L and A must have the same size and device")
+    ws = _workspace("rev", n, nb, A.device, workspace)
+    _check("chol_rev", lib.chol_rev(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1, A.data_ptr(),
+                                    A.stride(0) if n else 1, _FORMS[form], nb, ws.data_ptr(), ws.numel(),
+                                    _stream(A.device)))
+    return A
+
+
+def chol_fwd(L, A, nb=0, workspace=None):
+    """In place: tril(A) = tril(Sigma-dot) -> tril(A) = L-dot, strict upper set to 0."""
+    lib = load_library()
+    n = _square("L", L)
+    if _square("A", A) != n or A.device != L.device:
+        raise ValueError("L and A must have the same size and device")
+    ws = _workspace("fwd", n, nb, A.device, workspace)
+    _check("chol_fwd", lib.chol_fwd(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1, A.data_ptr(),
+                                    A.stride(0) if n else 1, nb, ws.data_ptr(), ws.numel(),
+                                    _stream(A.device)))
+    return A

@@ -1,0 +1,185 @@
+// FP64 MFMA contraction kernels for the Level-3 updates (Sec. 4.2 of Murray 2016: the GEMM-,
+// SYRK- and TRSM-shaped steps of the blocked factorisation and its derivatives).
+//
+//   C[m, n] = alpha * sum_k A(m, k) B(k, n) + beta * Cin[m, n]        (m < M, n < N, k < K)
+//
+// A(m, k) is read from A[m*lda + k] (AT = false) or A[k*lda + m] (AT = true); B(k, n) from
+// B[k*ldb + n] (BT = false) or B[n*ldb + k] (BT = true).  All matrices are row-major doubles.
+//
+// Tiling for gfx950: a 256-thread workgroup (four wave64s in a 2 x 2 arrangement) owns a
+// 128 x 128 output tile; each wave owns 64 x 64 as a 4 x 4 grid of 16 x 16 accumulators fed by
+// v_mfma_f64_16x16x4_f64.  K is staged through LDS 16 deep, double-buffered, so one barrier per
+// K-step.  Tall-skinny products are split over K (grid.z); each split writes a private partial
+// tile and a separate kernel sums the partials in a fixed order, so results are bitwise
+// reproducible (no floating-point atomics).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cg {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int GEMM_BM = 128;
+constexpr int GEMM_BN = 128;
+constexpr int GEMM_BK = 16;
+constexpr int GEMM_PAD = 4;
+constexpr int GEMM_THREADS = 256;
+
+struct GemmArgs {
+  int M, N, K;
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  double *C;            // output (or the partial buffer when splits > 1)
+  int64_t ldc;
+  const double *Cin;    // read when beta != 0 (may alias C)
+  int64_t ldcin;
+  double alpha, beta;
+  double *Cm;           // optional transposed copy: Cm[n*ldcm + m] = C[m, n]
+  int64_t ldcm;
+  int kchunk;           // K extent of one split (multiple of GEMM_BK)
+  int64_t split_stride; // elements between the partial tiles of consecutive splits
+  int lower_only;       // skip output tiles lying strictly above the diagonal (m < n throughout)
+};
+
+template <bool AT, bool BT>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
+  constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK, LDA_S = BM + GEMM_PAD,
+                LDB_S = BN + GEMM_PAD;
+  __shared__ double As[2][BK * LDA_S];
+  __shared__ double Bs[2][BK * LDB_S];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  if (p.lower_only && m0 + BM - 1 < n0) return;  // whole tile strictly above the diagonal
+
+  const int z = blockIdx.z;
+  const int kbeg = z * p.kchunk;
+  const int kend = min(p.K, kbeg + p.kchunk);
+  double *Cout = p.C + (int64_t)z * p.split_stride;
+
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[8], rb[8];
+  // Global -> registers for the K-tile starting at k0.
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int e = it * GEMM_THREADS + tid;
+      int m, k;
+      if (!AT) { m = e >> 4; k = e & 15; }      // contiguous along k
+      else     { k = e >> 7; m = e & 127; }     // contiguous along m
+      const int gm = m0 + m, gk = k0 + k;
+      double v = 0.0;
+      if (gm < p.M && gk < kend) v = AT ? p.A[(int64_t)gk * p.lda + gm] : p.A[(int64_t)gm * p.lda + gk];
+      ra[it] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int e = it * GEMM_THREADS + tid;
+      int n, k;
+      if (!BT) { k = e >> 7; n = e & 127; }     // contiguous along n
+      else     { n = e >> 4; k = e & 15; }      // contiguous along k
+      const int gn = n0 + n, gk = k0 + k;
+      double v = 0.0;
+      if (gn < p.N && gk < kend) v = BT ? p.B[(int64_t)gn * p.ldb + gk] : p.B[(int64_t)gk * p.ldb + gn];
+      rb[it] = v;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int e = it * GEMM_THREADS + tid;
+      int m, k;
+      if (!AT) { m = e >> 4; k = e & 15; } else { k = e >> 7; m = e & 127; }
+      As[buf][k * LDA_S + m] = ra[it];
+    }
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int e = it * GEMM_THREADS + tid;
+      int n, k;
+      if (!BT) { k = e >> 7; n = e & 127; } else { n = e >> 4; k = e & 15; }
+      Bs[buf][k * LDB_S + n] = rb[it];
+    }
+  };
+
+  const int nkt = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nkt > 0) {
+    load_tile(kbeg);
+    store_tile(0);
+  }
+  __syncthreads();
+  const int frag_k = lane >> 4, frag_i = lane & 15;
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nkt) load_tile(kbeg + (kt + 1) * BK);
+    const double *as = As[buf];
+    const double *bs = Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) af[t] = as[(kk + frag_k) * LDA_S + wm * 64 + t * 16 + frag_i];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bf[t] = bs[(kk + frag_k) * LDB_S + wn * 64 + t * 16 + frag_i];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nkt) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue.  MFMA f64 16x16 output layout: lane l, element i holds row 4*i + l/16, column l%16.
+  const double alpha = p.alpha, beta = p.beta;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + wm * 64 + a * 16 + 4 * i + (lane >> 4);
+        const int gn = n0 + wn * 64 + b * 16 + (lane & 15);
+        if (gm < p.M && gn < p.N) {
+          double v = alpha * acc[a][b][i];
+          if (beta != 0.0) v += beta * p.Cin[(int64_t)gm * p.ldcin + gn];
+          Cout[(int64_t)gm * p.ldc + gn] = v;
+          if (p.Cm) p.Cm[(int64_t)gn * p.ldcm + gm] = v;
+        }
+      }
+}
+
+// C[m, n] = alpha * sum_{s < S} P[s*sstride + m*ldp + n] + beta * Cin[m, n], summed in split order;
+// lower_only restricts the writes to n <= m.  Optional transposed copy Cm as in the GEMM.
+__global__ __launch_bounds__(256) void reduce_splits_kernel(int M, int N, const double *P, int64_t ldp,
+                                                            int64_t sstride, int S, double alpha,
+                                                            const double *Cin, int64_t ldcin,
+                                                            double beta, double *C, int64_t ldc,
+                                                            double *Cm, int64_t ldcm, int lower_only) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(e / N), n = (int)(e % N);
+    if (lower_only && n > m) continue;
+    double s = 0.0;
+    for (int z = 0; z < S; ++z) s += P[(int64_t)z * sstride + (int64_t)m * ldp + n];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * Cin[(int64_t)m * ldcin + n];
+    C[(int64_t)m * ldc + n] = v;
+    if (Cm) Cm[(int64_t)n * ldcm + m] = v;
+  }
+}
+
+}  // namespace cg

@@ -1,0 +1,309 @@
+// libcholgrad: C ABI and host-side enqueuer for blocked Cholesky factorisation and blocked
+// forward/reverse propagation of Cholesky derivatives on gfx950 (Murray 2016, Sec. 4.2).
+//
+// The host code only validates arguments, carves the caller's workspace and enqueues kernels on
+// the caller's stream; every arithmetic step runs on the GPU.  Block columns are tile-aligned
+// ([b*nb, min(n, (b+1)*nb))), so a short block, if any, is the last one in both sweeps; the
+// column partition is arbitrary (Sec. 4.2), so this does not change the result beyond rounding.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include <algorithm>
+
+#include "cholgrad.h"
+#include "cg_diag.hpp"
+#include "cg_gemm.hpp"
+
+namespace {
+
+constexpr size_t WS_ALIGN = 256;
+constexpr int DEFAULT_NB = 128;
+constexpr int TARGET_WGS = 512;  // two 256-thread workgroups per compute unit on 256 CUs
+constexpr int64_t PART_ELEMS = (int64_t)TARGET_WGS * cg::GEMM_BM * cg::GEMM_BN;
+
+inline size_t align_up(size_t x) { return (x + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Workspace carving: the same function sizes (base == nullptr) and assigns.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  double *take(size_t n_doubles) {
+    const size_t o = off;
+    off = align_up(off + n_doubles * sizeof(double));
+    return base ? reinterpret_cast<double *>(base + o) : nullptr;
+  }
+};
+
+struct SweepWs {
+  double *dinv = nullptr;   // inverses of the diagonal blocks of L: nblk x nb x nb
+  double *panel = nullptr;  // one block column: n x nb
+  double *dblk = nullptr;   // one diagonal block: nb x nb
+  double *part = nullptr;   // split-K partial tiles: PART_ELEMS
+};
+
+size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
+  Carver c(base);
+  const int64_t nblk = cdiv(n, nb);
+  w->dinv = c.take((size_t)nblk * nb * nb);
+  w->panel = c.take((size_t)n * nb);
+  w->dblk = c.take((size_t)nb * nb);
+  w->part = c.take((size_t)PART_ELEMS);
+  return c.off;
+}
+
+bool nb_ok(int nb) { return nb == 0 || (nb >= 32 && nb <= cg::DIAG_MAX && nb % 32 == 0); }
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// C = alpha * op(A) op(B) + beta * Cin on the MFMA kernel; splits K when the output has too few
+// tiles to fill the GPU, then sums the partial tiles in split order.  part == nullptr forbids
+// splitting.
+hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t lda,
+                const double *B, int64_t ldb, double alpha, const double *Cin, int64_t ldcin,
+                double beta, double *C, int64_t ldc, double *Cm, int64_t ldcm, int lower_only,
+                double *part, int min_kchunk, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, cg::GEMM_BN);
+  int tiles = tm * tn;
+  if (lower_only && tm == tn) tiles = (tm * (tm + 1)) / 2;
+  int S = 1;
+  int kchunk = (int)(cdiv(K > 0 ? K : 1, cg::GEMM_BK) * cg::GEMM_BK);
+  if (part && K > 0) {
+    int64_t s_want = TARGET_WGS / tiles;
+    s_want = std::min<int64_t>(s_want, cdiv(K, min_kchunk));
+    s_want = std::min<int64_t>(s_want, PART_ELEMS / ((int64_t)M * N));
+    if (s_want > 1) {
+      kchunk = (int)(cdiv(cdiv(K, s_want), cg::GEMM_BK) * cg::GEMM_BK);
+      S = (int)cdiv(K, kchunk);
+    }
+  }
+  cg::GemmArgs p;
+  p.M = M; p.N = N; p.K = K;
+  p.A = A; p.lda = lda; p.B = B; p.ldb = ldb;
+  p.kchunk = kchunk;
+  p.lower_only = lower_only;
+  const dim3 grid(tm, tn, S);
+  if (S == 1) {
+    p.C = C; p.ldc = ldc; p.Cin = Cin; p.ldcin = ldcin; p.alpha = alpha; p.beta = beta;
+    p.Cm = Cm; p.ldcm = ldcm; p.split_stride = 0;
+  } else {
+    p.C = part; p.ldc = N; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
+    p.Cm = nullptr; p.ldcm = 0; p.split_stride = (int64_t)M * N;
+  }
+  if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<true, false>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
+  else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, true>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
+  else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, false>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
+  else hipLaunchKernelGGL((cg::gemm_f64_kernel<true, true>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 1) return e;
+  const int64_t total = (int64_t)M * N;
+  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 2048);
+  hipLaunchKernelGGL(cg::reduce_splits_kernel, dim3(blocks), dim3(256), 0, s, M, N, part, (int64_t)N,
+                     (int64_t)M * N, S, alpha, Cin, ldcin, beta, C, ldc, Cm, ldcm, lower_only);
+  return hipGetLastError();
+}
+
+// dst[0:M, 0:N] = beta * src (lower triangle only when lower_only), as a split-free reduce.
+hipError_t copy_scaled(int M, int N, const double *src, int64_t lds, double beta, double *dst,
+                       int64_t ldd, int lower_only, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(cdiv((int64_t)M * N, 256), 2048);
+  hipLaunchKernelGGL(cg::reduce_splits_kernel, dim3(blocks), dim3(256), 0, s, M, N,
+                     (const double *)nullptr, (int64_t)0, (int64_t)0, 0, 0.0, src, lds, beta, dst,
+                     ldd, (double *)nullptr, (int64_t)0, lower_only);
+  return hipGetLastError();
+}
+
+#define CG_TRY(expr)                          \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return CHOL_ERR_HIP; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int chol_version(void) { return CHOLGRAD_VERSION; }
+
+const char *chol_status_string(int status) {
+  switch (status) {
+    case CHOL_SUCCESS: return "success";
+    case CHOL_ERR_HIP: return "a HIP runtime call or kernel launch failed";
+    case CHOL_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case CHOL_ERR_UNSUPPORTED: return "unsupported precision, form or size";
+    default: break;
+  }
+  if (status < 0 && status > -32) return "invalid argument (status -i names argument i)";
+  return "unknown status";
+}
+
+size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
+  if (n <= 0 || precision != CHOL_PREC_F64 || !nb_ok(nb)) return 0;
+  if (op != CHOL_OP_FACTOR && op != CHOL_OP_REV && op != CHOL_OP_FWD) return 0;
+  if (nb == 0) nb = DEFAULT_NB;
+  SweepWs w;
+  return carve(n, nb, nullptr, &w);
+}
+
+int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
+             int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
+  if (precision != CHOL_PREC_F64) return -1;
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!Lv || !aligned8(Lv)) return -3;
+  if (ldl < n) return -4;
+  if (!Av || !aligned8(Av)) return -5;
+  if (lda < n) return -6;
+  if (sbar_form != CHOL_SBAR_SYM && sbar_form != CHOL_SBAR_TRIL) return -7;
+  if (!nb_ok(nb)) return -8;
+  if (nb == 0) nb = DEFAULT_NB;
+  SweepWs ws;
+  const size_t need = carve(n, nb, nullptr, &ws);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
+    return CHOL_ERR_WORKSPACE;
+  carve(n, nb, workspace, &ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double *L = static_cast<const double *>(Lv);
+  double *A = static_cast<double *>(Av);
+  const int64_t nblk = cdiv(n, nb);
+
+  hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
+                     ldl, ws.dinv);
+  CG_TRY(hipGetLastError());
+
+  // Reverse sweep over block columns, right to left, in left-looking ("lazy") order: when block
+  // [j, k) is reached, everything right of it is final and is stored as the symmetric gradient
+  // S_sym in both triangles of A[k:, k:].  The accumulated knock-on terms of Sec. 4.2's
+  // B-bar / R-bar updates then collapse to one product:
+  //   C-bar = L-bar_C - (T + T^T)[k:, k:] L[k:, j:k] = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k].
+  for (int64_t b = nblk - 1; b >= 0; --b) {
+    const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
+    const int w = (int)(k - j);
+    const int m = (int)(n - k);
+    if (m > 0) {
+      // X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k]                   -> panel (m x w)
+      CG_TRY(gemm(false, false, m, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 128, s));
+      // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
+      // triangles.
+      CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0,
+                  0.0, A + k * lda + j, lda, A + j * lda + k, lda, 0, nullptr, 128, s));
+      // D-bar = tril(L-bar_D) - tril(C-bar^T C), C-bar = 2 * A[k:, j:k]   -> dblk (w x w)
+      CG_TRY(gemm(true, false, w, w, m, A + k * lda + j, lda, L + k * ldl + j, ldl, -2.0,
+                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part, 64, s));
+    } else {
+      CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s));
+    }
+    hipLaunchKernelGGL(cg::diag_rev_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w,
+                       L + j * ldl + j, ldl, (const double *)ws.dblk, (int64_t)nb, A + j * lda + j, lda);
+    CG_TRY(hipGetLastError());
+  }
+  if (sbar_form == CHOL_SBAR_TRIL) {
+    const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
+    hipLaunchKernelGGL(cg::sym_to_tril_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
+    CG_TRY(hipGetLastError());
+  }
+  return CHOL_SUCCESS;
+}
+
+int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *info,
+                void *workspace, size_t workspace_bytes, void *stream) {
+  if (precision != CHOL_PREC_F64) return -1;
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!Av || !aligned8(Av)) return -3;
+  if (lda < n) return -4;
+  if (!nb_ok(nb)) return -5;
+  if (!info) return -6;
+  if (nb == 0) nb = DEFAULT_NB;
+  SweepWs ws;
+  const size_t need = carve(n, nb, nullptr, &ws);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
+    return CHOL_ERR_WORKSPACE;
+  carve(n, nb, workspace, &ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *A = static_cast<double *>(Av);
+  const int64_t nblk = cdiv(n, nb);
+  hipLaunchKernelGGL(cg::set_int_kernel, dim3(1), dim3(1), 0, s, info, 0);
+  CG_TRY(hipGetLastError());
+  // Sec. 4.2 chol_blocked, left to right.
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
+    const int w = (int)(k - j);
+    const int m = (int)(n - k);
+    // [D; C] <- [D; C] - [R; B] R^T   (D - tril(R R^T) and C - B R^T in one product, K = j)
+    if (j > 0)
+      CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, A + j * lda, lda, -1.0,
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s));
+    // D <- chol_unblocked(D); D^-1 for the panel solve
+    hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w, A + j * lda + j, lda,
+                       ws.dblk, nb, info, j);
+    CG_TRY(hipGetLastError());
+    // C <- C tril(D)^-T   (every output tile spans all w <= 128 columns, so in place is safe)
+    if (m > 0)
+      CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
+                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s));
+  }
+  const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
+  hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
+  CG_TRY(hipGetLastError());
+  return CHOL_SUCCESS;
+}
+
+int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
+             void *workspace, size_t workspace_bytes, void *stream) {
+  if (precision != CHOL_PREC_F64) return -1;
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!Lv || !aligned8(Lv)) return -3;
+  if (ldl < n) return -4;
+  if (!Av || !aligned8(Av)) return -5;
+  if (lda < n) return -6;
+  if (!nb_ok(nb)) return -7;
+  if (nb == 0) nb = DEFAULT_NB;
+  SweepWs ws;
+  const size_t need = carve(n, nb, nullptr, &ws);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
+    return CHOL_ERR_WORKSPACE;
+  carve(n, nb, workspace, &ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double *L = static_cast<const double *>(Lv);
+  double *A = static_cast<double *>(Av);
+  const int64_t nblk = cdiv(n, nb);
+  hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
+                     ldl, ws.dinv);
+  CG_TRY(hipGetLastError());
+  // Sec. 4.2 chol_blocked_fwd, left to right.
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
+    const int w = (int)(k - j);
+    const int m = (int)(n - k);
+    if (j > 0) {
+      // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T   (K = j each)
+      CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0,
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s));
+      CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, L + j * ldl, ldl, A + j * lda, lda, -1.0,
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s));
+    }
+    // D-dot <- chol_unblocked_fwd(D, D-dot)   (strict upper triangle of the block set to 0)
+    hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w, L + j * ldl + j,
+                       ldl, A + j * lda + j, lda);
+    CG_TRY(hipGetLastError());
+    if (m > 0) {
+      // C-dot <- (C-dot - C D-dot^T) D^-T
+      CG_TRY(gemm(false, true, m, w, w, L + k * ldl + j, ldl, A + j * lda + j, lda, -1.0,
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, nullptr, 128, s));
+      CG_TRY(gemm(false, true, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 1.0, nullptr, 0, 0.0,
+                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s));
+    }
+  }
+  const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
+  hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
+  CG_TRY(hipGetLastError());
+  return CHOL_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+"""The C ABI library loads, exports every function include/cholgrad.h declares, and rejects bad
+arguments on the host before touching a GPU (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cholgrad.h")
+LIB = os.path.join(ROOT, "paper_1602_07527_amd", "libcholgrad.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libcholgrad.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("chol_factor", "chol_rev", "chol_fwd", "chol_workspace_bytes",
+                 "chol_status_string", "chol_version"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _lib():
+    from paper_1602_07527_amd import load_library
+    return load_library()
+
+
+def test_host_only_queries():
+    lib = _lib()
+    assert lib.chol_version() == 100
+    assert lib.chol_status_string(0) == b"success"
+    assert lib.chol_workspace_bytes(1, 0, 0, 0) == 0
+    assert lib.chol_workspace_bytes(1, 0, 1000, 0) > 0
+    assert lib.chol_workspace_bytes(1, 0, 1000, 48) == 0     # nb not a multiple of 32
+    assert lib.chol_workspace_bytes(1, 9, 1000, 0) == 0      # unknown precision
+
+
+def test_invalid_arguments_rejected_on_host():
+    lib = _lib()
+    fake = ctypes.c_void_p(4096)        # never dereferenced: validation fails first
+    ws = ctypes.c_void_p(1 << 20)
+    big = 1 << 40
+    assert lib.chol_rev(7, 10, fake, 10, fake, 10, 0, 0, ws, big, None) == -1
+    assert lib.chol_rev(0, -1, fake, 10, fake, 10, 0, 0, ws, big, None) == -2
+    assert lib.chol_rev(0, 10, None, 10, fake, 10, 0, 0, ws, big, None) == -3
+    assert lib.chol_rev(0, 10, fake, 9, fake, 10, 0, 0, ws, big, None) == -4
+    assert lib.chol_rev(0, 10, fake, 10, ctypes.c_void_p(4097), 10, 0, 0, ws, big, None) == -5
+    assert lib.chol_rev(0, 10, fake, 10, fake, 3, 0, 0, ws, big, None) == -6
+    assert lib.chol_rev(0, 10, fake, 10, fake, 10, 5, 0, ws, big, None) == -7
+    assert lib.chol_rev(0, 10, fake, 10, fake, 10, 0, 200, ws, big, None) == -8
+    assert lib.chol_rev(0, 10, fake, 10, fake, 10, 0, 0, ws, 16, None) == -102
+    assert lib.chol_rev(0, 10, fake, 10, fake, 10, 0, 0, ctypes.c_void_p((1 << 20) + 8), big, None) == -102
+    assert lib.chol_rev(0, 0, None, 0, None, 0, 0, 0, None, 0, None) == 0   # n == 0 is a no-op
+    assert lib.chol_fwd(0, 10, fake, 10, fake, 10, 33, ws, big, None) == -7
+    assert lib.chol_fwd(0, 10, fake, 10, fake, 10, 0, None, big, None) == -102
+    assert lib.chol_factor(0, 10, fake, 10, 0, None, ws, big, None) == -6
+    assert lib.chol_factor(0, 10, fake, 5, 0, fake, ws, big, None) == -4
+    assert lib.chol_factor(0, 0, None, 0, 0, None, None, 0, None) == 0

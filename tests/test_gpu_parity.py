@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle, element by element.
+
+Tolerance (relative Frobenius, FP64 path): 1e-10 for chol_rev / chol_fwd run on the SAME L as the
+oracle, and for chol_factor on L itself.  Both sides are backward-stable FP64 computations of the
+same quantity; their difference is rounding amplified by conditioning, measured at <= 3e-14 between
+independent CPU routes on these inputs (kappa up to 8e6), so 1e-10 leaves >= 1000x headroom while
+any indexing or algebra mistake gives O(1) errors.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+import workloads as W
+from _golden import load
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    import paper_1602_07527_amd as pkg
+    pkg.load_library()            # fails loudly when the HIP library is missing
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def dev(cg):
+    import torch
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def to_dev(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def spd_case(N, seed):
+    S, rng = W.dense_spd(N, seed)
+    L = sla.cholesky(S, lower=True) if N > 0 else np.zeros((0, 0))
+    Lb = W.lower_normal(N, rng)
+    Sd = W.sym_normal(N, rng)
+    junk = np.triu(rng.standard_normal((N, N)) * 1e3, 1)     # must be ignored
+    return S, L, Lb, Sd, junk
+
+
+SIZES = [1, 2, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256, 257, 383, 513]
+NBS = [32, 64, 128]
+
+
+@pytest.mark.parametrize("nb", NBS)
+@pytest.mark.parametrize("N", SIZES)
+def test_rev_matches_oracle(cg, dev, N, nb):
+    S, L, Lb, Sd, junk = spd_case(N, 1000 + N)
+    A = cg.chol_rev(to_dev(L, dev), to_dev(Lb + junk, dev), form="sym", nb=nb).cpu().numpy()
+    want = O.chol_rev(L, Lb, "sym")
+    assert rel(A, want) <= TOL
+    assert np.array_equal(A, A.T)
+
+
+@pytest.mark.parametrize("N,nb", [(1, 32), (65, 32), (257, 64), (300, 128)])
+def test_rev_tril_form(cg, dev, N, nb):
+    S, L, Lb, Sd, junk = spd_case(N, 2000 + N)
+    A = cg.chol_rev(to_dev(L, dev), to_dev(Lb + junk, dev), form="tril", nb=nb).cpu().numpy()
+    assert rel(A, O.chol_rev(L, Lb, "tril")) <= TOL
+    assert np.all(np.triu(A, 1) == 0)
+
+
+@pytest.mark.parametrize("nb", NBS)
+@pytest.mark.parametrize("N", SIZES)
+def test_fwd_matches_oracle(cg, dev, N, nb):
+    S, L, Lb, Sd, junk = spd_case(N, 3000 + N)
+    A = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd) + junk, dev), nb=nb).cpu().numpy()
+    assert rel(A, O.chol_fwd(L, Sd)) <= TOL
+    assert np.all(np.triu(A, 1) == 0)
+
+
+@pytest.mark.parametrize("nb", NBS)
+@pytest.mark.parametrize("N", SIZES)
+def test_factor_matches_oracle(cg, dev, N, nb):
+    S, L, Lb, Sd, junk = spd_case(N, 4000 + N)
+    A, info = cg.chol_factor(to_dev(S + junk, dev), nb=nb)
+    Lg = A.cpu().numpy()
+    Lo, info_o = O.chol(S)
+    assert int(info.item()) == 0 == info_o
+    assert rel(Lg, Lo) <= TOL
+    assert np.all(np.triu(Lg, 1) == 0)
+
+
+@pytest.mark.parametrize("N,bad,nb", [(40, 0, 32), (40, 5, 32), (200, 64, 64), (200, 127, 64),
+                                      (300, 299, 128), (300, 130, 128)])
+def test_factor_reports_first_bad_pivot(cg, dev, N, bad, nb):
+    S, *_ = spd_case(N, 5000 + N)
+    S[bad, bad] = -1.0
+    _, info_o = O.chol(S)
+    A, info = cg.chol_factor(to_dev(S, dev), nb=nb)
+    import torch
+    torch.cuda.synchronize()
+    assert info_o == bad + 1
+    assert int(info.item()) == info_o
+
+
+def test_empty_is_noop(cg, dev):
+    import torch
+    e = torch.zeros((0, 0), dtype=torch.float64, device=dev)
+    cg.chol_rev(e, e.clone())
+    cg.chol_fwd(e, e.clone())
+    cg.chol_factor(e.clone())
+
+
+def test_golden_integer_cases(cg, dev):
+    g = load("chol_int.txt")
+    A, info = cg.chol_factor(to_dev(g["Sigma"], dev), nb=32)
+    assert int(info.item()) == 0
+    assert np.abs(A.cpu().numpy() - g["L"]).max() <= 1e-14
+    g = load("rev_closed.txt")
+    A = cg.chol_rev(to_dev(g["L"], dev), to_dev(g["Lbar"], dev), nb=32).cpu().numpy()
+    assert np.abs(A - g["Sbar_sym"]).max() <= 1e-13
+    g = load("fwd_closed.txt")
+    A = cg.chol_fwd(to_dev(g["L"], dev), to_dev(g["Sdot"], dev), nb=32).cpu().numpy()
+    assert np.abs(A - g["Ldot"]).max() <= 1e-13
+
+
+def test_small_case_identities(cg, dev):
+    """N = 256 dense case: adjoint identity between the GPU's own rev and fwd, and central finite
+    differences of the GPU factorisation against the GPU forward mode."""
+    c = W.small_case()
+    S, Lb, Sd = c["Sigma"], c["Lbar"], c["Sdot"]
+    A, info = cg.chol_factor(to_dev(S, dev), nb=64)
+    L = A.cpu().numpy()
+    Sb = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=64).cpu().numpy()
+    Ld = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=64).cpu().numpy()
+    lhs = np.sum(Lb * Ld)
+    assert np.sum(Sb * Sd) == pytest.approx(lhs, rel=1e-12)
+    h = 1e-6
+    Lp = cg.chol_factor(to_dev(S + h / 2 * Sd, dev), nb=64)[0].cpu().numpy()
+    Lm = cg.chol_factor(to_dev(S - h / 2 * Sd, dev), nb=64)[0].cpu().numpy()
+    assert rel((Lp - Lm) / h, Ld) <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def medium():
+    c = W.medium_case()
+    L, info = O.chol(c["Sigma"])
+    assert info == 0
+    c["L"] = L
+    c["rev"] = O.chol_rev(L, c["Lbar"], "sym")
+    c["fwd"] = O.chol_fwd(L, c["Sdot"])
+    return c
+
+
+@pytest.mark.parametrize("nb", NBS)
+def test_medium_case(cg, dev, medium, nb):
+    """N = 4096 squared-exponential kernel (kappa ~ 8e6): factor, and rev/fwd on the oracle's L."""
+    A, info = cg.chol_factor(to_dev(medium["Sigma"], dev), nb=nb)
+    assert int(info.item()) == 0
+    assert rel(A.cpu().numpy(), medium["L"]) <= TOL
+    Lt = to_dev(medium["L"], dev)
+    assert rel(cg.chol_rev(Lt, to_dev(medium["Lbar"], dev), nb=nb).cpu().numpy(), medium["rev"]) <= TOL
+    assert rel(cg.chol_fwd(Lt, to_dev(np.tril(medium["Sdot"]), dev), nb=nb).cpu().numpy(),
+               medium["fwd"]) <= TOL
+
+
+def test_repeatable_bitwise(cg, dev):
+    S, L, Lb, Sd, junk = spd_case(700, 77)
+    Lt = to_dev(L, dev)
+    a = cg.chol_rev(Lt, to_dev(Lb, dev)).cpu().numpy()
+    b = cg.chol_rev(Lt, to_dev(Lb, dev)).cpu().numpy()
+    assert np.array_equal(a, b)
