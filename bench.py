@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the blocked Cholesky derivative path on one MI355X.
+
+Workload: the N = 16384 squared-exponential kernel matrix (3-D inputs, lengthscale 0.2,
+nugget 1e-2), built on the device from a fixed seed.  One step is the whole path on it:
+    L = chol_factor(Sigma);  Sigma-bar = chol_rev(L, L-bar);  L-dot = chol_fwd(L, Sigma-dot)
+(each preceded by a device copy of its input, since the calls work in place).  The reported value
+is chol_rev's throughput, (2/3) N^3 flops per call over the event-timed duration of the chol_rev
+calls inside the timed steps; per-call figures for all three sweeps are reported beside it.
+
+Output: one JSON line on stdout.  `--gpus` above 1 is refused (single-GPU build).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "chol_rev TFLOP/s at N=16384 (% MFMA peak); batched solves/s + p99 latency"
+FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 matrix (MFMA) peak
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_rev_panel_contraction.json")
+GEMM_SOURCE = os.path.join(ROOT, "paper_1602_07527_amd", "csrc", "cg_gemm.hpp")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def traffic_for(kernel_hash):
+    """HBM bytes per launch of the reverse-sweep contraction from the committed rocprofv3 PMC
+    record, or None when there is none or the kernel source has changed since it was taken."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(Sigma_dev, Lbar_dev, n_sample):
+    """The oracle's chol_rev (eqn (symrev), host LAPACK) on the leading n_sample block of the same
+    workload: the leading block of a Cholesky factor is the factor of the leading block."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()
+                       if p.get("user_api") == "blas"] or [1])
+    except Exception:      # threadpoolctl missing: fall back to the affinity mask
+        threads = len(os.sched_getaffinity(0))
+    S = Sigma_dev[:n_sample, :n_sample].cpu().numpy()
+    Lb = Lbar_dev[:n_sample, :n_sample].cpu().numpy()
+    L, info = oracle.chol(S)
+    assert info == 0
+    t0 = time.perf_counter()
+    oracle.chol_rev(L, Lb)
+    dt = time.perf_counter() - t0
+    flops = 2.0 / 3.0 * n_sample ** 3
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle chol_rev (eqn symrev, FP64, host LAPACK) on the leading "
+                      f"{n_sample}x{n_sample} block of the same N=16384 workload, one call, "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=10240,
+                    help="leading-block size for the CPU oracle baseline (0 skips it)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1602_07527_amd as cg
+    import workloads
+
+    cg.load_library()
+    dev = torch.device("cuda:0")
+    n, nb = args.n, args.nb
+    log(f"[bench] building the N={n} workload on the device")
+    inp = workloads.large_case_device(dev, N=n)
+    Sigma, Lbar, Sdot = inp["Sigma"], inp["Lbar"], inp["Sdot"]
+    A = torch.empty_like(Sigma)
+    Ab = torch.empty_like(Sigma)
+    Ad = torch.empty_like(Sigma)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws_bytes = max(cg.workspace_bytes(op, n, nb) for op in ("factor", "rev", "fwd"))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d")}
+    times = {"f": 0.0, "r": 0.0, "d": 0.0}
+
+    def step(record):
+        A.copy_(Sigma)
+        if record: ev["f"][0].record()
+        cg.chol_factor(A, nb=nb, workspace=ws, info=info)
+        if record: ev["f"][1].record()
+        Ab.copy_(Lbar)
+        if record: ev["r"][0].record()
+        cg.chol_rev(A, Ab, nb=nb, workspace=ws)
+        if record: ev["r"][1].record()
+        Ad.copy_(Sdot)
+        if record: ev["d"][0].record()
+        cg.chol_fwd(A, Ad, nb=nb, workspace=ws)
+        if record: ev["d"][1].record()
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    if int(info.item()) != 0:
+        raise RuntimeError(f"chol_factor reported info={int(info.item())}")
+
+    cg.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        for k in times:
+            times[k] += ev[k][0].elapsed_time(ev[k][1])
+        log(f"[bench] timed step {i + 1}/{args.steps}: rev {ev['r'][0].elapsed_time(ev['r'][1]):.1f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = cg.profile_end()
+    if int(info.item()) != 0:
+        raise RuntimeError(f"chol_factor reported info={int(info.item())}")
+    if not bool(torch.isfinite(Ab).all()) or not bool(torch.isfinite(Ad).all()):
+        raise RuntimeError("non-finite result")
+
+    K = args.steps
+    ms_step = (t1 - t0) * 1e3 / K
+    f_rev = 2.0 / 3.0 * n ** 3
+    f_fac = n ** 3 / 3.0
+    rev_ms = times["r"] / K
+    fac_ms = times["f"] / K
+    fwd_ms = times["d"] / K
+    rev_tflops = f_rev / (rev_ms * 1e-3) / 1e12
+
+    k_ms, k_flops, k_launch = prof["rev"]
+    achieved = k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+    kernel_hash = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    traffic = traffic_for(kernel_hash)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": traffic,
+                "kernel": "gemm_f64_kernel<false,false,1> (reverse-sweep panel contraction)",
+                "kernel_avg_us": round(k_ms * 1e3 / max(k_launch, 1), 2),
+                "launches_per_step": k_launch // K}
+
+    out = {
+        "metric": METRIC, "value": round(rev_tflops, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"squared-exponential kernel matrix N={n} (3-D inputs, lengthscale "
+                               f"0.2, nugget 1e-2); step = chol_factor + chol_rev + chol_fwd",
+                   "n": n, "nb": nb},
+        "pct_fp64_peak": round(100 * rev_tflops / FP64_PEAK_TFLOPS, 2),
+        "chol_rev_ms": round(rev_ms, 3), "chol_factor_ms": round(fac_ms, 3),
+        "chol_fwd_ms": round(fwd_ms, 3),
+        "chol_factor_tflops": round(f_fac / (fac_ms * 1e-3) / 1e12, 3),
+        "chol_fwd_tflops": round(f_rev / (fwd_ms * 1e-3) / 1e12, 3),
+        "roofline": roofline,
+    }
+    if args.cpu_sample > 0:
+        log(f"[bench] timing the CPU oracle on a {args.cpu_sample} sample")
+        out["cpu_baseline"] = cpu_baseline(Sigma, Lbar, min(args.cpu_sample, n))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

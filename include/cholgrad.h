@@ -107,6 +107,21 @@ int chol_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int6
 int chol_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * Benchmark instrumentation (creates HIP events, so not for allocation-free paths).
+ * chol_profile_begin: until chol_profile_end, each launch of a sweep's panel contraction -- the
+ *   kernel that carries nearly all of a sweep's flops -- is bracketed by a pair of hipEvents on the
+ *   call's stream, for at most max_launches launches in total.  Returns 0, or -1 when already
+ *   active or max_launches is not in [1, 2^20].
+ * chol_profile_end: waits for the recorded events and returns, per sweep (index 0 chol_rev,
+ *   1 chol_factor, 2 chol_fwd), the summed kernel time in ms, the summed flops of the
+ *   contractions (2*M*N*K per launch) and the number of launches; then releases the events.
+ *   ms, flops and launches must each point to 3 elements.  Returns 0, -1 (not active / NULL
+ *   argument) or CHOL_ERR_HIP.  Process-global; not thread-safe.
+ */
+int chol_profile_begin(int max_launches);
+int chol_profile_end(double *ms, double *flops, int64_t *launches);
+
 /* Human-readable text for a status code (static storage; never NULL). */
 const char *chol_status_string(int status);
 

@@ -6,7 +6,7 @@ Public calls (torch tensors as device memory, work on the current stream):
   chol_fwd(L, A)     Sigma-dot -> L-dot       (Sec. 4.2 chol_blocked_fwd)
 """
 from ._binding import (CholError, LIB_PATH, chol_factor, chol_fwd, chol_rev, load_library,
-                       workspace_bytes)
+                       profile_begin, profile_end, workspace_bytes)
 
 __all__ = ["CholError", "LIB_PATH", "chol_factor", "chol_fwd", "chol_rev", "load_library",
-           "workspace_bytes"]
+           "profile_begin", "profile_end", "workspace_bytes"]

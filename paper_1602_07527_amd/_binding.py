@@ -49,6 +49,11 @@ def load_library():
     lib.chol_status_string.restype = ctypes.c_char_p
     lib.chol_version.argtypes = []
     lib.chol_version.restype = i32
+    lib.chol_profile_begin.argtypes = [i32]
+    lib.chol_profile_begin.restype = i32
+    lib.chol_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.chol_profile_end.restype = i32
     _lib = lib
     return lib
 
@@ -127,3 +132,17 @@ def chol_fwd(L, A, nb=0, workspace=None):
                                     A.stride(0) if n else 1, nb, ws.data_ptr(), ws.numel(),
                                     _stream(A.device)))
     return A
+
+
+def profile_begin(max_launches=1 << 16):
+    """Start bracketing every sweep's panel-contraction launch with HIP events."""
+    _check("chol_profile_begin", load_library().chol_profile_begin(int(max_launches)))
+
+
+def profile_end():
+    """Stop and return {'rev'|'factor'|'fwd': (kernel_ms, flops, launches)}."""
+    ms = (ctypes.c_double * 3)()
+    fl = (ctypes.c_double * 3)()
+    nl = (ctypes.c_int64 * 3)()
+    _check("chol_profile_end", load_library().chol_profile_end(ms, fl, nl))
+    return {k: (ms[i], fl[i], int(nl[i])) for i, k in enumerate(("rev", "factor", "fwd"))}

@@ -44,7 +44,9 @@ struct GemmArgs {
   int lower_only;       // skip output tiles lying strictly above the diagonal (m < n throughout)
 };
 
-template <bool AT, bool BT>
+// TAG only separates kernel names for profiling (1: reverse-sweep panel contraction,
+// 2: factor-sweep panel contraction, 3: forward-sweep panel contraction, 0: other products).
+template <bool AT, bool BT, int TAG>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
   constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK, LDA_S = BM + GEMM_PAD,
                 LDB_S = BN + GEMM_PAD;

@@ -10,6 +10,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "cholgrad.h"
 #include "cg_diag.hpp"
@@ -21,6 +22,18 @@ constexpr size_t WS_ALIGN = 256;
 constexpr int DEFAULT_NB = 128;
 constexpr int TARGET_WGS = 512;  // two 256-thread workgroups per compute unit on 256 CUs
 constexpr int64_t PART_ELEMS = (int64_t)TARGET_WGS * cg::GEMM_BM * cg::GEMM_BN;
+
+// Benchmark instrumentation: event pairs around the panel contractions, per sweep (see
+// chol_profile_begin).  Process-global and not thread-safe; off unless a benchmark enables it.
+struct Profile {
+  bool on = false;
+  int cap = 0;
+  std::vector<hipEvent_t> ev;   // 2 per launch
+  std::vector<int> klass;
+  std::vector<double> flops;
+  int used = 0;
+};
+Profile g_prof;
 
 inline size_t align_up(size_t x) { return (x + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -57,13 +70,31 @@ size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
 bool nb_ok(int nb) { return nb == 0 || (nb >= 32 && nb <= cg::DIAG_MAX && nb % 32 == 0); }
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
+template <int TAG>
+void launch_gemm_tag(bool at, bool bt, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+  const dim3 block(cg::GEMM_THREADS);
+  if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<true, false, TAG>), grid, block, 0, s, p);
+  else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, true, TAG>), grid, block, 0, s, p);
+  else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, false, TAG>), grid, block, 0, s, p);
+  else hipLaunchKernelGGL((cg::gemm_f64_kernel<true, true, TAG>), grid, block, 0, s, p);
+}
+
+void launch_gemm(bool at, bool bt, int tag, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+  switch (tag) {
+    case 1: launch_gemm_tag<1>(at, bt, grid, p, s); break;
+    case 2: launch_gemm_tag<2>(at, bt, grid, p, s); break;
+    case 3: launch_gemm_tag<3>(at, bt, grid, p, s); break;
+    default: launch_gemm_tag<0>(at, bt, grid, p, s); break;
+  }
+}
+
 // C = alpha * op(A) op(B) + beta * Cin on the MFMA kernel; splits K when the output has too few
 // tiles to fill the GPU, then sums the partial tiles in split order.  part == nullptr forbids
 // splitting.
 hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t lda,
                 const double *B, int64_t ldb, double alpha, const double *Cin, int64_t ldcin,
                 double beta, double *C, int64_t ldc, double *Cm, int64_t ldcm, int lower_only,
-                double *part, int min_kchunk, hipStream_t s) {
+                double *part, int min_kchunk, hipStream_t s, int tag = 0) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, cg::GEMM_BN);
   int tiles = tm * tn;
@@ -92,10 +123,18 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
     p.C = part; p.ldc = N; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
     p.Cm = nullptr; p.ldcm = 0; p.split_stride = (int64_t)M * N;
   }
-  if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<true, false>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
-  else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, true>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
-  else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, false>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
-  else hipLaunchKernelGGL((cg::gemm_f64_kernel<true, true>), grid, dim3(cg::GEMM_THREADS), 0, s, p);
+  const bool timed = g_prof.on && tag > 0 && g_prof.used < g_prof.cap;
+  if (timed) {
+    const int u = g_prof.used;
+    if (hipEventRecord(g_prof.ev[2 * u], s) != hipSuccess) return hipErrorUnknown;
+    g_prof.klass[u] = tag;
+    g_prof.flops[u] = 2.0 * (double)M * (double)N * (double)K;
+  }
+  launch_gemm(at, bt, tag, grid, p, s);
+  if (timed) {
+    if (hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s) != hipSuccess) return hipErrorUnknown;
+    ++g_prof.used;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || S == 1) return e;
   const int64_t total = (int64_t)M * N;
@@ -127,6 +166,44 @@ hipError_t copy_scaled(int M, int N, const double *src, int64_t lds, double beta
 extern "C" {
 
 int chol_version(void) { return CHOLGRAD_VERSION; }
+
+int chol_profile_begin(int max_launches) {
+  if (g_prof.on) return -1;
+  if (max_launches <= 0 || max_launches > (1 << 20)) return -1;
+  g_prof.ev.assign(2 * (size_t)max_launches, nullptr);
+  for (auto &e : g_prof.ev)
+    if (hipEventCreate(&e) != hipSuccess) return CHOL_ERR_HIP;
+  g_prof.klass.assign(max_launches, 0);
+  g_prof.flops.assign(max_launches, 0.0);
+  g_prof.cap = max_launches;
+  g_prof.used = 0;
+  g_prof.on = true;
+  return CHOL_SUCCESS;
+}
+
+int chol_profile_end(double *ms, double *flops, int64_t *launches) {
+  if (!g_prof.on) return -1;
+  if (!ms || !flops || !launches) return -1;
+  int rc = CHOL_SUCCESS;
+  for (int c = 0; c < 3; ++c) { ms[c] = 0.0; flops[c] = 0.0; launches[c] = 0; }
+  for (int u = 0; u < g_prof.used; ++u) {
+    float t = 0.0f;
+    if (hipEventSynchronize(g_prof.ev[2 * u + 1]) != hipSuccess ||
+        hipEventElapsedTime(&t, g_prof.ev[2 * u], g_prof.ev[2 * u + 1]) != hipSuccess) {
+      rc = CHOL_ERR_HIP;
+      continue;
+    }
+    const int c = g_prof.klass[u] - 1;
+    if (c < 0 || c > 2) continue;
+    ms[c] += t;
+    flops[c] += g_prof.flops[u];
+    launches[c] += 1;
+  }
+  for (auto &e : g_prof.ev)
+    if (e) (void)hipEventDestroy(e);
+  g_prof = Profile();
+  return rc;
+}
 
 const char *chol_status_string(int status) {
   switch (status) {
@@ -186,7 +263,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     if (m > 0) {
       // X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k]                   -> panel (m x w)
       CG_TRY(gemm(false, false, m, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
-                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 128, s));
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 128, s, 1));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
       // triangles.
       CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0,
@@ -237,7 +314,7 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
     // [D; C] <- [D; C] - [R; B] R^T   (D - tril(R R^T) and C - B R^T in one product, K = j)
     if (j > 0)
       CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, A + j * lda, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s));
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s, 2));
     // D <- chol_unblocked(D); D^-1 for the panel solve
     hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w, A + j * lda + j, lda,
                        ws.dblk, nb, info, j);
@@ -284,9 +361,9 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     if (j > 0) {
       // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T   (K = j each)
       CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s));
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s, 3));
       CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, L + j * ldl, ldl, A + j * lda, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s));
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s, 3));
     }
     // D-dot <- chol_unblocked_fwd(D, D-dot)   (strict upper triangle of the block set to 0)
     hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w, L + j * ldl + j,

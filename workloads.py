@@ -119,3 +119,37 @@ def batch_case(batch=2048, lo=16, hi=512, seed=SEED_BATCH, shift=0.1):
         Sig.append(S)
         ys.append(rng.standard_normal(n))
     return {"sizes": sizes, "Sigma": Sig, "y": ys}
+
+
+def se_case_device(N, seed, lengthscale, nugget, device, dim=3, with_sdot=True):
+    """Device-resident squared-exponential case for timing runs at large N (building a
+    16384 x 16384 kernel on the host takes minutes).  X comes from the same NumPy stream as
+    se_case; the kernel matrix is assembled on the device in float64 with the same formula;
+    L-bar (lower) and Sigma-dot (lower triangle; symmetric by convention) are N(0,1) draws from a
+    torch generator on the device seeded with `seed`.  Values equal se_case's only up to the
+    rounding of the device's exp, and the normal draws differ: use it for timing and for
+    property checks, not for element-wise comparison with se_case."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    X = torch.from_numpy(rng.random((N, dim))).to(device)
+    sq = (X * X).sum(dim=1)
+    S = torch.empty((N, N), dtype=torch.float64, device=device)
+    inv2l2 = 1.0 / (2.0 * lengthscale * lengthscale)
+    for r0 in range(0, N, 4096):
+        r1 = min(N, r0 + 4096)
+        d2 = sq[r0:r1, None] + sq[None, :] - 2.0 * (X[r0:r1] @ X.T)
+        S[r0:r1] = torch.exp(d2.clamp_(min=0.0).mul_(-inv2l2))
+    S.diagonal().add_(nugget)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Lbar = torch.randn((N, N), dtype=torch.float64, device=device, generator=g).tril_()
+    out = {"Sigma": S, "Lbar": Lbar}
+    if with_sdot:
+        out["Sdot"] = torch.randn((N, N), dtype=torch.float64, device=device, generator=g).tril_()
+    return out
+
+
+def large_case_device(device, N=16384, seed=SEED_LARGE, with_sdot=True):
+    """N = 16384 squared-exponential kernel (3-D, lengthscale 0.2, nugget 1e-2), built on device."""
+    return se_case_device(N, seed, 0.2, 1e-2, device, with_sdot=with_sdot)
