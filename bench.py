@@ -157,7 +157,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": "gemm_f64_kernel<false,false,1> (reverse-sweep panel contraction)",
+                "kernel": "gemm_f64_dma_kernel<false,false,1> (reverse-sweep panel contraction)",
                 "kernel_avg_us": round(k_ms * 1e3 / max(k_launch, 1), 2),
                 "launches_per_step": k_launch // K}
 

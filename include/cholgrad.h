@@ -19,7 +19,10 @@
  *   - The caller owns all memory, including the workspace (size from chol_workspace_bytes, base
  *     aligned to 256 bytes).  The library never allocates, frees or synchronises inside these calls;
  *     all work is enqueued on `stream` (a hipStream_t; NULL means the default stream) in order.
- *     Calls on distinct (stream, workspace) pairs may run concurrently.
+ *     Calls on distinct (stream, workspace) pairs may run concurrently.  The device of `stream`
+ *     must be the current device.  chol_rev additionally runs part of its work on one auxiliary
+ *     stream per device (default priority), ordered against `stream` with events; that stream and
+ *     its three events are created by the first call on a device and kept for the process.
  *   - Return value: CHOL_SUCCESS (0), or a negative status checked synchronously on the host
  *     before anything is enqueued:  -i  means argument i (1-based) is invalid;  CHOL_ERR_* below.
  *     Numerical breakdown of chol_factor is reported asynchronously through `info`.

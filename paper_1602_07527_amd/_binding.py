@@ -103,8 +103,10 @@ def chol_factor(A, nb=0, workspace=None, info=None):
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
     ws = _workspace("factor", n, nb, A.device, workspace)
-    _check("chol_factor", lib.chol_factor(PREC_F64, n, A.data_ptr(), A.stride(0) if n else 1, nb,
-                                          info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(A.device)))
+    with torch.cuda.device(A.device):
+        _check("chol_factor", lib.chol_factor(PREC_F64, n, A.data_ptr(), A.stride(0) if n else 1, nb,
+                                              info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                              _stream(A.device)))
     return A, info
 
 
@@ -115,9 +117,10 @@ def chol_rev(L, A, form="sym", nb=0, workspace=None):
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("rev", n, nb, A.device, workspace)
-    _check("chol_rev", lib.chol_rev(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1, A.data_ptr(),
-                                    A.stride(0) if n else 1, _FORMS[form], nb, ws.data_ptr(), ws.numel(),
-                                    _stream(A.device)))
+    with torch.cuda.device(A.device):
+        _check("chol_rev", lib.chol_rev(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1,
+                                        A.data_ptr(), A.stride(0) if n else 1, _FORMS[form], nb,
+                                        ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
 
@@ -128,9 +131,10 @@ def chol_fwd(L, A, nb=0, workspace=None):
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("fwd", n, nb, A.device, workspace)
-    _check("chol_fwd", lib.chol_fwd(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1, A.data_ptr(),
-                                    A.stride(0) if n else 1, nb, ws.data_ptr(), ws.numel(),
-                                    _stream(A.device)))
+    with torch.cuda.device(A.device):
+        _check("chol_fwd", lib.chol_fwd(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1,
+                                        A.data_ptr(), A.stride(0) if n else 1, nb, ws.data_ptr(),
+                                        ws.numel(), _stream(A.device)))
     return A
 
 

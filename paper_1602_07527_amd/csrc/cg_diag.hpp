@@ -1,20 +1,26 @@
 // Diagonal-block kernels of the blocked sweeps (Sec. 4.2 of Murray 2016).  Each works on one
-// w x w diagonal block (w <= 128) held entirely in LDS as packed lower triangles, one workgroup
-// of 256 threads per block:
-//   trinv_kernel    : D^-1 of every diagonal block of L (the TRSM steps then run as MFMA products)
-//   diag_rev_kernel : D-bar <- chol_unblocked_rev(D, D-bar) (Sec. 4.1), organised as the blocked
-//                     reverse sweep of Sec. 4.2 with 32-column inner blocks whose Level-2 adjoint
-//                     runs in one wave64 out of registers (Phi's halving of the diagonal included).
+// w x w diagonal block (w <= 128) held in LDS as packed lower triangles, one 256-thread workgroup
+// (four wave64s) per block, organised exactly like the outer sweeps: 32-column inner blocks whose
+// Level-2 step (Sec. 4.1) runs in ONE wave out of registers, with the Level-3 updates between them
+// done as 16 x 16 v_mfma_f64_16x16x4_f64 tiles shared out over the four waves.
+//   trinv_kernel    : D^-1 of every diagonal block of L (the panel solves are MFMA products)
+//   diag_rev_kernel : D-bar <- chol_unblocked_rev(D, D-bar)     (Sec. 4.1, Phi halving included)
+//   diag_fwd_kernel : D-dot <- chol_unblocked_fwd(D, D-dot)     (Sec. 4.1, eqns (dub1), (dub2))
+//   potf2_kernel    : D <- chol_unblocked(D) (Sec. 4.1, DPOTF2) and D^-1
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace cg {
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 constexpr int DIAG_MAX = 128;
 constexpr int DIAG_PACKED = DIAG_MAX * (DIAG_MAX + 1) / 2;  // 8256 doubles
 constexpr int DIAG_THREADS = 256;
+constexpr int DIAG_WAVES = DIAG_THREADS / 64;
 constexpr int INNER = 32;
+constexpr int XLD = INNER + 1;  // leading dimension of a staged 32 x 32 inverse block
 
 __device__ __forceinline__ int pidx(int r, int c) { return (r * (r + 1)) / 2 + c; }  // r >= c
 
@@ -25,52 +31,70 @@ __device__ __forceinline__ double wave_bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// Packed-lower load of a w x w block (row-major source, leading dimension ld).
+// Packed-lower load of a w x w block (w <= 128; row-major source, leading dimension ld).  The
+// block is walked as a 128-wide grid so that row/column come from shifts, and each thread keeps
+// 16 global loads in flight before it writes them to LDS.
 __device__ __forceinline__ void load_packed(double *dst, const double *src, int64_t ld, int w) {
-  for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    if (c <= r) dst[pidx(r, c)] = src[(int64_t)r * ld + c];
-  }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Inverse of each lower-triangular diagonal block: block b covers rows/cols [b*nb, min(n,(b+1)nb)).
-// Row recurrence of D X = I:  X[i][c] = (delta_ic - sum_{c<=l<i} D[i][l] X[l][c]) / D[i][i].
-// Output Dinv + b*nb*nb, row-major with leading dimension nb, zero above the diagonal and outside
-// the w x w block.
-__global__ __launch_bounds__(DIAG_THREADS) void trinv_kernel(int64_t n, int nb, const double *L,
-                                                             int64_t ldl, double *Dinv) {
-  __shared__ double Dp[DIAG_PACKED];
-  __shared__ double Xp[DIAG_PACKED];
-  const int64_t j = (int64_t)blockIdx.x * nb;
-  const int w = (int)min<int64_t>(nb, n - j);
-  load_packed(Dp, L + j * ldl + j, ldl, w);
-  __syncthreads();
-  for (int i = 0; i < w; ++i) {
-    const double dii = Dp[pidx(i, i)];
-    for (int c = threadIdx.x; c <= i; c += blockDim.x) {
-      double s = (c == i) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) s -= Dp[pidx(i, l)] * Xp[pidx(l, c)];
-      Xp[pidx(i, c)] = s / dii;
+  constexpr int BATCH = 16;
+  for (int e0 = 0; e0 < w * DIAG_MAX; e0 += BATCH * DIAG_THREADS) {
+    double v[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + u * DIAG_THREADS + (int)threadIdx.x;
+      const int r = e >> 7, c = e & (DIAG_MAX - 1);
+      v[u] = (r < w && c <= r) ? src[(int64_t)r * ld + c] : 0.0;
     }
-    __syncthreads();
-  }
-  double *out = Dinv + (int64_t)blockIdx.x * nb * nb;
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int r = e / nb, c = e - r * nb;
-    out[e] = (r < w && c <= r) ? Xp[pidx(r, c)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + u * DIAG_THREADS + (int)threadIdx.x;
+      const int r = e >> 7, c = e & (DIAG_MAX - 1);
+      if (r < w && c <= r) dst[pidx(r, c)] = v[u];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Level-2 reverse sweep (Sec. 4.1 chol_unblocked_rev) on the ib x ib block at offset a of the
-// packed matrices, by ONE wave: lane c < 32 owns column c of D and D-bar in registers.  For
-// j = 31 .. 0:  d-bar <- d-bar - c^T c-bar / d;  [d-bar; c-bar] /= d;
+// One wave's 16 x 16 MFMA tile:  acc += sum_{k < K} A(i, k) B(k, j)  for i, j < 16.  A and B are
+// accessors returning 0 outside their valid range; K need not be a multiple of 4.
+// The accumulator layout is that of v_mfma_f64_16x16x4_f64: lane l, element e holds
+// (row 4e + l/16, column l%16).
+template <class FA, class FB>
+__device__ __forceinline__ dbl4 tile_mma(dbl4 acc, FA A, FB B, int K) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  int k0 = 0;
+  for (; k0 + 16 <= K; k0 += 16) {  // four k-steps per round: eight LDS reads in flight
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A(i, k0 + 4 * u + kq);
+      b[u] = B(k0 + 4 * u + kq, i);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+  for (; k0 < K; k0 += 4) {
+    const int k = k0 + kq;
+    const double a = (k < K) ? A(i, k) : 0.0;
+    const double b = (k < K) ? B(k, i) : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ int tile_row(int e) { return 4 * e + ((threadIdx.x & 63) >> 4); }
+__device__ __forceinline__ int tile_col() { return threadIdx.x & 15; }
+
+// ---------------------------------------------------------------------------------------------
+// Per-wave 32 x 32 Level-2 cores.  A ragged inner block (ib < 32) is padded with the identity
+// (and zero sensitivities), which leaves the leading ib x ib result unchanged, so all loop bounds
+// are compile-time constants and every lane index is static.
+
+// Sec. 4.1 chol_unblocked_rev on the block at offset a: lane c < 32 owns column c of D and D-bar.
+// For j = 31 .. 0:  d-bar <- d-bar - c^T c-bar / d;  [d-bar; c-bar] /= d;
 // r-bar <- r-bar - [d-bar c-bar^T][r; B];  B-bar <- B-bar - c-bar r;  d-bar <- d-bar / 2.
-// Lane j owns (d, c, d-bar, c-bar); the lanes l < j own the entries of r, B, r-bar, B-bar.
-// A ragged block (ib < 32) is padded with D = I and D-bar = 0, which leaves the leading ib x ib
-// result unchanged (the padded columns carry zero sensitivities and zero couplings), so every loop
-// bound is a compile-time constant.
+// Lane j owns (d, c, d-bar, c-bar); the lanes l < j own the entries of r, B, r-bar, B-bar and take
+// lane j's column with v_readlane.
 __device__ void level2_rev_wave(const double *Dp, double *Bp, int a, int ib) {
   const int c = threadIdx.x & 63;
   double Dc[INNER], Bc[INNER];
@@ -80,109 +104,41 @@ __device__ void level2_rev_wave(const double *Dp, double *Bp, int a, int ib) {
     Dc[i] = ok ? Dp[pidx(a + i, a + c)] : (i == c ? 1.0 : 0.0);
     Bc[i] = ok ? Bp[pidx(a + i, a + c)] : 0.0;
   }
+  double own = 1.0;
+#pragma unroll
+  for (int i = 0; i < INNER; ++i) own = (i == c) ? Dc[i] : own;
+  const double inv_own = 1.0 / own;
 #pragma unroll
   for (int j = INNER - 1; j >= 0; --j) {
-    double dot = 0.0;
+    double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-    for (int i = j + 1; i < INNER; ++i) dot = fma(Dc[i], Bc[i], dot);
-    const double inv_d = 1.0 / wave_bcast(Dc[j], j);
-    const double dbar = wave_bcast((Bc[j] - dot * inv_d) * inv_d, j);
+    for (int i = j + 1; i < INNER; ++i) {
+      if ((i - j) & 1) p0 = fma(Dc[i], Bc[i], p0);
+      else p1 = fma(Dc[i], Bc[i], p1);
+    }
+    const double inv_d = wave_bcast(inv_own, j);
+    const double dbar = wave_bcast((Bc[j] - (p0 + p1) * inv_d) * inv_d, j);
     const bool below = c < j, owner = c == j;
     const double r = Dc[j];  // D[j][c] on the lanes below
-    double acc = dbar * r;
+    double q0 = dbar * r, q1 = 0.0;
 #pragma unroll
     for (int i = j + 1; i < INNER; ++i) {
       const double cbi = wave_bcast(Bc[i], j) * inv_d;
-      acc = fma(cbi, Dc[i], acc);
+      if ((i - j) & 1) q1 = fma(cbi, Dc[i], q1);
+      else q0 = fma(cbi, Dc[i], q0);
       const double upd = fma(-cbi, r, Bc[i]);
       Bc[i] = owner ? cbi : (below ? upd : Bc[i]);
     }
-    Bc[j] = owner ? 0.5 * dbar : (below ? Bc[j] - acc : Bc[j]);
+    Bc[j] = owner ? 0.5 * dbar : (below ? Bc[j] - (q0 + q1) : Bc[j]);
   }
 #pragma unroll
   for (int i = 0; i < INNER; ++i)
     if ((c < ib) && (i < ib) && (i >= c)) Bp[pidx(a + i, a + c)] = Bc[i];
 }
 
-// D-bar <- chol_unblocked_rev(D, D-bar) for one w x w diagonal block (w <= 128), run as the
-// blocked reverse sweep of Sec. 4.2 over 32-column inner blocks [a, b) from the bottom-right:
-//   C-bar <- C-bar D_i^-1;  B-bar <- B-bar - C-bar R;  D-bar_i <- D-bar_i - tril(C-bar^T C);
-//   D-bar_i <- Level-2 adjoint (one wave);  R-bar <- R-bar - C-bar^T B - (D-bar_i + D-bar_i^T) R.
-// In: L + (j, j) with ldl (only the block's lower triangle is read); Dbar (w x w, ld ldd, lower).
-// Out: the block of the symmetric gradient, written to both triangles of A + (j, j):
-//   A[r][c] = A[c][r] = T[r][c] / 2 (r > c),  A[r][r] = T[r][r],   T = final D-bar.
-__global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const double *Ld, int64_t ldl,
-                                                                const double *Dbar, int64_t ldd,
-                                                                double *Aout, int64_t lda) {
-  __shared__ double Dp[DIAG_PACKED];
-  __shared__ double Bp[DIAG_PACKED];
-  const int tid = threadIdx.x;
-  load_packed(Dp, Ld, ldl, w);
-  load_packed(Bp, Dbar, ldd, w);
-  __syncthreads();
-
-  for (int a = ((w - 1) / INNER) * INNER; a >= 0; a -= INNER) {
-    const int b = min(w, a + INNER);
-    const int ib = b - a;
-    const int rest = w - b;  // rows below the inner block; when > 0, ib == INNER
-    if (rest > 0) {
-      // C-bar <- C-bar D_i^-1, one row per thread: x D_i = c-bar by back substitution in place.
-      for (int r = b + tid; r < w; r += blockDim.x) {
-        for (int q = INNER - 1; q >= 0; --q) {
-          double s = Bp[pidx(r, a + q)];
-          for (int p = q + 1; p < INNER; ++p) s = fma(-Bp[pidx(r, a + p)], Dp[pidx(a + p, a + q)], s);
-          Bp[pidx(r, a + q)] = s / Dp[pidx(a + q, a + q)];
-        }
-      }
-      __syncthreads();
-      // B-bar <- B-bar - C-bar R   (rows [b, w), columns [0, a))
-      for (int e = tid; e < rest * a; e += blockDim.x) {
-        const int r = b + e / a, cc = e % a;
-        double s = Bp[pidx(r, cc)];
-#pragma unroll 8
-        for (int q = 0; q < INNER; ++q) s = fma(-Bp[pidx(r, a + q)], Dp[pidx(a + q, cc)], s);
-        Bp[pidx(r, cc)] = s;
-      }
-      // D-bar_i <- D-bar_i - tril(C-bar^T C)
-      for (int e = tid; e < INNER * INNER; e += blockDim.x) {
-        const int p = e / INNER, q = e % INNER;
-        if (q <= p) {
-          double s = 0.0;
-          for (int r = b; r < w; ++r) s = fma(Bp[pidx(r, a + p)], Dp[pidx(r, a + q)], s);
-          Bp[pidx(a + p, a + q)] -= s;
-        }
-      }
-      __syncthreads();
-    }
-    if ((tid >> 6) == 0) level2_rev_wave(Dp, Bp, a, ib);
-    __syncthreads();
-    // R-bar <- R-bar - C-bar^T B - (D-bar_i + D-bar_i^T) R   (rows [a, b), columns [0, a))
-    for (int e = tid; e < ib * a; e += blockDim.x) {
-      const int p = e / a, cc = e % a;
-      double s = 0.0;
-      for (int r = b; r < w; ++r) s = fma(Bp[pidx(r, a + p)], Dp[pidx(r, cc)], s);
-      for (int q = 0; q < ib; ++q) {
-        const double dsym = (q < p) ? Bp[pidx(a + p, a + q)]
-                          : (q > p) ? Bp[pidx(a + q, a + p)] : 2.0 * Bp[pidx(a + p, a + p)];
-        s = fma(dsym, Dp[pidx(a + q, cc)], s);
-      }
-      Bp[pidx(a + p, cc)] -= s;
-    }
-    __syncthreads();
-  }
-
-  for (int e = tid; e < w * w; e += blockDim.x) {
-    const int r = e / w, cc = e - r * w;
-    const double v = (r > cc) ? 0.5 * Bp[pidx(r, cc)] : (r == cc ? Bp[pidx(r, r)] : 0.5 * Bp[pidx(cc, r)]);
-    Aout[(int64_t)r * lda + cc] = v;
-  }
-}
-
-// Level-2 forward sweep (Sec. 4.1 chol_unblocked_fwd) on the ib x ib block at offset a, by ONE
-// wave: lane i < 32 owns row i of D and D-dot in registers.  For j = 0 .. 31 (eqns (dub1),(dub2)):
-//   d-dot <- (d-dot/2 - r r-dot^T) / d;   c-dot <- (c-dot - B-dot r^T - B r-dot^T - c d-dot) / d.
-// Lane j owns (r, d, r-dot, d-dot); lanes i > j own the rows of (B, c, B-dot, c-dot).  A ragged
-// block is padded with D = I, D-dot = 0 (rows past ib never feed the leading rows).
+// Sec. 4.1 chol_unblocked_fwd on the block at offset a: lane i < 32 owns row i of D and D-dot.
+// For j = 0 .. 31:  d-dot <- (d-dot/2 - r r-dot^T) / d;
+// c-dot <- (c-dot - B-dot r^T - B r-dot^T - c d-dot) / d.
 __device__ void level2_fwd_wave(const double *Dp, double *Ap, int a, int ib) {
   const int i = threadIdx.x & 63;
   double Dr[INNER], Ar[INNER];
@@ -194,81 +150,406 @@ __device__ void level2_fwd_wave(const double *Dp, double *Ap, int a, int ib) {
   }
 #pragma unroll
   for (int j = 0; j < INNER; ++j) {
-    double dot = 0.0;
-#pragma unroll
-    for (int l = 0; l < j; ++l) dot = fma(Dr[l], Ar[l], dot);
-    const double d = wave_bcast(Dr[j], j);
-    const double ddot = wave_bcast((0.5 * Ar[j] - dot) / Dr[j], j);
-    double acc = Ar[j];
+    double p0 = 0.0, p1 = 0.0;
 #pragma unroll
     for (int l = 0; l < j; ++l) {
-      acc = fma(-Ar[l], wave_bcast(Dr[l], j), acc);
-      acc = fma(-Dr[l], wave_bcast(Ar[l], j), acc);
+      if (l & 1) p1 = fma(Dr[l], Ar[l], p1);
+      else p0 = fma(Dr[l], Ar[l], p0);
     }
-    acc = fma(-Dr[j], ddot, acc);
-    Ar[j] = (i > j) ? acc / d : ((i == j) ? ddot : Ar[j]);
+    const double d = wave_bcast(Dr[j], j);
+    const double ddot = wave_bcast((0.5 * Ar[j] - (p0 + p1)) / Dr[j], j);
+    double q0 = Ar[j], q1 = 0.0;
+#pragma unroll
+    for (int l = 0; l < j; ++l) {
+      const double r = wave_bcast(Dr[l], j), rd = wave_bcast(Ar[l], j);
+      if (l & 1) { q1 = fma(-Ar[l], r, q1); q1 = fma(-Dr[l], rd, q1); }
+      else       { q0 = fma(-Ar[l], r, q0); q0 = fma(-Dr[l], rd, q0); }
+    }
+    const double num = fma(-Dr[j], ddot, q0 + q1);
+    Ar[j] = (i > j) ? num / d : ((i == j) ? ddot : Ar[j]);
   }
 #pragma unroll
   for (int l = 0; l < INNER; ++l)
     if ((i < ib) && (l <= i)) Ap[pidx(a + i, a + l)] = Ar[l];
 }
 
+// Sec. 4.1 chol_unblocked (DPOTF2) on the block at offset a, in place: lane i < 32 owns row i.
+// Column j: d <- sqrt(d - r r^T); c <- (c - B r^T) / d.  Returns (uniformly) the first column
+// with a non-positive or NaN pivot, or -1.
+__device__ int level2_potf2_wave(double *Dp, int a, int ib) {
+  const int i = threadIdx.x & 63;
+  double Dr[INNER];
+#pragma unroll
+  for (int l = 0; l < INNER; ++l) {
+    const bool ok = (i < ib) && (l <= i);
+    Dr[l] = ok ? Dp[pidx(a + i, a + l)] : (l == i ? 1.0 : 0.0);
+  }
+  int bad = -1;
+#pragma unroll
+  for (int j = 0; j < INNER; ++j) {
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int l = 0; l < j; ++l) {
+      const double r = wave_bcast(Dr[l], j);
+      if (l & 1) p1 = fma(Dr[l], r, p1);
+      else p0 = fma(Dr[l], r, p0);
+    }
+    const double s = Dr[j] - (p0 + p1);
+    const double piv = wave_bcast(s, j);
+    if (bad < 0 && !(piv > 0.0) && j < ib) bad = j;
+    const double d = sqrt(piv);
+    Dr[j] = (i > j) ? s / d : ((i == j) ? d : Dr[j]);
+  }
+#pragma unroll
+  for (int l = 0; l < INNER; ++l)
+    if ((i < ib) && (l <= i)) Dp[pidx(a + i, a + l)] = Dr[l];
+  return bad;
+}
+
+// Inverse of the lower-triangular 32 x 32 block of Dp at offset a, by ONE wave (D X = I by
+// forward substitution).  Lane i < 32 holds row i of D; lane c < 32 builds column c of X, taking
+// D[i][l] from lane i with v_readlane.  Writes the lower triangle of X into packed Xp at offset a.
+__device__ void wave_trinv32(const double *Dp, double *Xp, int a, int ib) {
+  const int lane = threadIdx.x & 63;
+  double Dr[INNER], Xc[INNER];
+#pragma unroll
+  for (int l = 0; l < INNER; ++l) {
+    const bool ok = (lane < ib) && (l <= lane);
+    Dr[l] = ok ? Dp[pidx(a + lane, a + l)] : (l == lane ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < INNER; ++i) {
+    double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+    for (int l = 0; l < i; ++l) {
+      const double dil = wave_bcast(Dr[l], i);
+      if (l & 1) s1 = fma(-dil, Xc[l], s1);
+      else s0 = fma(-dil, Xc[l], s0);
+    }
+    const double inv_dii = 1.0 / wave_bcast(Dr[i], i);
+    Xc[i] = (i >= lane) ? (s0 + s1) * inv_dii : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < INNER; ++i)
+    if ((lane < ib) && (i < ib) && (i >= lane)) Xp[pidx(a + i, a + lane)] = Xc[i];
+}
+
+// X = D^-1 for the whole w x w block (packed; the workgroup cooperates).  The 32 x 32 diagonal
+// blocks are inverted one per wave; block row p then follows from the rows above it:
+//   X_pq = -X_pp (sum_{q <= l < p} D_pl X_lq)      (q < p),
+// each product as MFMA tiles.  Ends with a barrier.
+__device__ void block_inverse(const double *Dp, double *Xp, int w) {
+  const int wave = threadIdx.x >> 6;
+  const int nI = (w + INNER - 1) / INNER;
+  for (int p = wave; p < nI; p += DIAG_WAVES) {
+    const int a = p * INNER;
+    wave_trinv32(Dp, Xp, a, min(INNER, w - a));
+  }
+  __syncthreads();
+  for (int p = 1; p < nI; ++p) {
+    const int ap = p * INNER, bp = min(w, ap + INNER);
+    // Y_pq = sum_l D_pl X_lq over columns [0, ap): 16 x 16 tiles of rows [ap, bp) x cols [0, ap)
+    const int tr = (bp - ap + 15) / 16, tc = ap / 16;
+    dbl4 acc[3];
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = ap + (t / tc) * 16, c0 = (t % tc) * 16;
+      auto A = [&](int i, int k) { const int r = r0 + i, cc = c0 + k; return (r < w) ? Dp[pidx(r, cc)] : 0.0; };
+      auto B = [&](int k, int j) { const int r = c0 + k, cc = c0 + j; return (r >= cc) ? Xp[pidx(r, cc)] : 0.0; };
+      acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, ap - c0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = ap + (t / tc) * 16, c0 = (t % tc) * 16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + tile_row(e), cc = c0 + tile_col();
+        if (r < w) Xp[pidx(r, cc)] = acc[sl][e];
+      }
+    }
+    __syncthreads();
+    // X_pq = -X_pp Y_pq   (Y_pq now held in the X_pq slots)
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = ap + (t / tc) * 16, c0 = (t % tc) * 16;
+      auto A = [&](int i, int k) { const int r = r0 + i, cc = ap + k; return (r < w && r >= cc) ? Xp[pidx(r, cc)] : 0.0; };
+      auto B = [&](int k, int j) { const int r = ap + k; return (r < w) ? Xp[pidx(r, c0 + j)] : 0.0; };
+      acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, bp - ap);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = ap + (t / tc) * 16, c0 = (t % tc) * 16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + tile_row(e), cc = c0 + tile_col();
+        if (r < w) Xp[pidx(r, cc)] = -acc[sl][e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Write the packed lower triangle of a w x w block to a row-major nb x nb buffer, zero elsewhere.
+__device__ __forceinline__ void store_lower_square(double *dst, int nb, const double *Xp, int w) {
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int r = e / nb, c = e - r * nb;
+    dst[e] = (r < w && c <= r) ? Xp[pidx(r, c)] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Inverse of each lower-triangular diagonal block: block b covers rows/cols [b*nb, min(n,(b+1)nb)).
+// Output Dinv + b*nb*nb, row-major with leading dimension nb, zero above the diagonal and outside
+// the w x w block.
+__global__ __launch_bounds__(DIAG_THREADS) void trinv_kernel(int64_t n, int nb, const double *L,
+                                                             int64_t ldl, double *Dinv) {
+  __shared__ double Dp[DIAG_PACKED];
+  __shared__ double Xp[DIAG_PACKED];
+  const int64_t j = (int64_t)blockIdx.x * nb;
+  const int w = (int)min<int64_t>(nb, n - j);
+  load_packed(Dp, L + j * ldl + j, ldl, w);
+  __syncthreads();
+  block_inverse(Dp, Xp, w);
+  store_lower_square(Dinv + (int64_t)blockIdx.x * nb * nb, nb, Xp, w);
+}
+
+// Stage the 32 x 32 diagonal sub-block [a, a+32)^2 of a block inverse (row-major, ld nb) in LDS.
+__device__ __forceinline__ void stage_inverse32(double *Xi, const double *Dinv, int nb, int a) {
+  for (int e = threadIdx.x; e < INNER * INNER; e += blockDim.x) {
+    const int r = e / INNER, c = e % INNER;
+    Xi[r * XLD + c] = Dinv[(int64_t)(a + r) * nb + a + c];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// D-bar <- chol_unblocked_rev(D, D-bar) for one w x w diagonal block (w <= 128), run as the
+// blocked reverse sweep of Sec. 4.2 over 32-column inner blocks [a, b) from the bottom-right:
+//   C-bar <- C-bar D_i^-1;  B-bar <- B-bar - C-bar R;  D-bar_i <- D-bar_i - tril(C-bar^T C);
+//   D-bar_i <- Level-2 adjoint (one wave);  R-bar <- R-bar - C-bar^T B - (D-bar_i + D-bar_i^T) R.
+// In: L + (j, j) with ldl (only the block's lower triangle is read); Dbar (w x w, ld ldd, lower);
+// Dinv: this block's inverse (ld nb).
+// Out: the block of the symmetric gradient, written to both triangles of A + (j, j):
+//   A[r][c] = A[c][r] = T[r][c] / 2 (r > c),  A[r][r] = T[r][r],   T = final D-bar.
+__global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const double *Ld, int64_t ldl,
+                                                                const double *Dbar, int64_t ldd,
+                                                                const double *Dinv, int nb,
+                                                                double *Aout, int64_t lda) {
+  __shared__ double Dp[DIAG_PACKED];
+  __shared__ double Bp[DIAG_PACKED];
+  __shared__ double Xi[INNER * XLD];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  load_packed(Dp, Ld, ldl, w);
+  load_packed(Bp, Dbar, ldd, w);
+  __syncthreads();
+
+  for (int a = ((w - 1) / INNER) * INNER; a >= 0; a -= INNER) {
+    const int b = min(w, a + INNER);
+    const int ib = b - a;
+    const int rest = w - b;  // rows below the inner block; when > 0, ib == INNER
+    const int trr = (rest + 15) / 16;
+    if (rest > 0) {
+      stage_inverse32(Xi, Dinv, nb, a);
+      __syncthreads();
+      // C-bar <- C-bar D_i^-1  (rows [b, w) x cols [a, b), K = 32)
+      dbl4 acc[3];
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+        auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Bp[pidx(r, a + k)] : 0.0; };
+        auto B = [&](int k, int j) { return Xi[k * XLD + c0 + j]; };
+        acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, INNER);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tile_row(e);
+          if (r < w) Bp[pidx(r, a + c0 + tile_col())] = acc[sl][e];
+        }
+      }
+      __syncthreads();
+      // B-bar -= C-bar R  (rows [b, w) x cols [0, a), K = 32)   and
+      // D-bar_i -= tril(C-bar^T C)  (the three lower 16 x 16 tiles of the 32 x 32 block, K = rest)
+      const int tca = a / 16;
+      const int n2 = trr * tca;
+      for (int t = wave; t < n2 + 3; t += DIAG_WAVES) {
+        if (t < n2) {
+          const int r0 = b + (t / tca) * 16, c0 = (t % tca) * 16;
+          auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Bp[pidx(r, a + k)] : 0.0; };
+          auto B = [&](int k, int j) { return Dp[pidx(a + k, c0 + j)]; };
+          const dbl4 s = tile_mma(dbl4{0, 0, 0, 0}, A, B, INNER);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = r0 + tile_row(e);
+            if (r < w) Bp[pidx(r, c0 + tile_col())] -= s[e];
+          }
+        } else {
+          const int u = t - n2;  // 0: (0,0), 1: (1,0), 2: (1,1)
+          const int r0 = (u == 0) ? 0 : 16, c0 = (u == 2) ? 16 : 0;
+          auto A = [&](int i, int k) { return Bp[pidx(b + k, a + r0 + i)]; };
+          auto B = [&](int k, int j) { return Dp[pidx(b + k, a + c0 + j)]; };
+          const dbl4 s = tile_mma(dbl4{0, 0, 0, 0}, A, B, rest);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = r0 + tile_row(e), cc = c0 + tile_col();
+            if (cc <= r) Bp[pidx(a + r, a + cc)] -= s[e];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (wave == 0) level2_rev_wave(Dp, Bp, a, ib);
+    __syncthreads();
+    if (a > 0) {
+      // R-bar -= C-bar^T B + (D-bar_i + D-bar_i^T) R   (rows [a, b) x cols [0, a))
+      const int tri = (ib + 15) / 16, tca = a / 16;
+      for (int t = wave; t < tri * tca; t += DIAG_WAVES) {
+        const int r0 = (t / tca) * 16, c0 = (t % tca) * 16;
+        dbl4 s = dbl4{0, 0, 0, 0};
+        if (rest > 0) {
+          auto A1 = [&](int i, int k) { return (r0 + i < ib) ? Bp[pidx(b + k, a + r0 + i)] : 0.0; };
+          auto B1 = [&](int k, int j) { return Dp[pidx(b + k, c0 + j)]; };
+          s = tile_mma(s, A1, B1, rest);
+        }
+        auto A2 = [&](int i, int k) {
+          const int m = r0 + i;
+          if (m >= ib || k >= ib) return 0.0;
+          return (k < m) ? Bp[pidx(a + m, a + k)]
+                         : (k > m) ? Bp[pidx(a + k, a + m)] : 2.0 * Bp[pidx(a + m, a + m)];
+        };
+        auto B2 = [&](int k, int j) { return (k < ib) ? Dp[pidx(a + k, c0 + j)] : 0.0; };
+        s = tile_mma(s, A2, B2, ib);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int m = r0 + tile_row(e);
+          if (m < ib) Bp[pidx(a + m, c0 + tile_col())] -= s[e];
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+#pragma unroll 8
+  for (int e = tid; e < w * DIAG_MAX; e += DIAG_THREADS) {
+    const int r = e >> 7, cc = e & (DIAG_MAX - 1);
+    if (cc < w) {
+      const double v = (r > cc) ? 0.5 * Bp[pidx(r, cc)] : (r == cc ? Bp[pidx(r, r)] : 0.5 * Bp[pidx(cc, r)]);
+      Aout[(int64_t)r * lda + cc] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // D-dot <- chol_unblocked_fwd(D, D-dot) for one w x w diagonal block (w <= 128), run as Sec. 4.2's
 // blocked forward sweep over 32-column inner blocks [a, b), left to right:
-//   D-dot_i <- D-dot_i - tril(R-dot R^T + R R-dot^T);  C-dot <- C-dot - B-dot R^T - B R-dot^T;
+//   [D-dot_i; C-dot] <- [D-dot_i; C-dot] - [R-dot; B-dot] R^T - [R; B] R-dot^T;
 //   D-dot_i <- Level-2 forward (one wave);  C-dot <- (C-dot - C D-dot_i^T) D_i^-T.
-// In: L + (j, j) (ldl), A + (j, j) holding tril of the updated Sigma-dot block.  Out: the block's
-// L-dot in the lower triangle of A + (j, j); its strict upper triangle is set to 0.
+// In: L + (j, j) (ldl), A + (j, j) holding tril of the updated Sigma-dot block, Dinv: this
+// block's inverse (ld nb).  Out: the block's L-dot in the lower triangle of A + (j, j); its strict
+// upper triangle is set to 0.
 __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const double *Ld, int64_t ldl,
+                                                                const double *Dinv, int nb,
                                                                 double *Ad, int64_t lda) {
   __shared__ double Dp[DIAG_PACKED];
   __shared__ double Ap[DIAG_PACKED];
-  const int tid = threadIdx.x;
+  __shared__ double Xi[INNER * XLD];
+  const int tid = threadIdx.x, wave = tid >> 6;
   load_packed(Dp, Ld, ldl, w);
   load_packed(Ap, Ad, lda, w);
   __syncthreads();
   for (int a = 0; a < w; a += INNER) {
     const int b = min(w, a + INNER);
     const int ib = b - a;
+    const int rest = w - b;
     if (a > 0) {
-      // D-dot_i -= tril(R-dot R^T + R R-dot^T)   (K = a)
-      for (int e = tid; e < ib * ib; e += blockDim.x) {
-        const int p = e / ib, q = e % ib;
-        if (q <= p) {
-          double s = 0.0;
-          for (int l = 0; l < a; ++l)
-            s = fma(Ap[pidx(a + p, l)], Dp[pidx(a + q, l)], fma(Dp[pidx(a + p, l)], Ap[pidx(a + q, l)], s));
-          Ap[pidx(a + p, a + q)] -= s;
+      // rows [a, w) x cols [a, b): subtract [R-dot; B-dot] R^T + [R; B] R-dot^T  (K = a each);
+      // tiles of the diagonal 32 x 32 block keep only their lower part.
+      const int tr = (w - a + 15) / 16, tc = (ib + 15) / 16;
+      for (int t = wave; t < tr * tc; t += DIAG_WAVES) {
+        const int r0 = a + (t / tc) * 16, c0 = (t % tc) * 16;
+        if (r0 - a + 15 < c0) continue;  // tile strictly above the diagonal
+        auto A1 = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Ap[pidx(r, k)] : 0.0; };
+        auto B1 = [&](int k, int j) { return (c0 + j < ib) ? Dp[pidx(a + c0 + j, k)] : 0.0; };
+        auto A2 = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Dp[pidx(r, k)] : 0.0; };
+        auto B2 = [&](int k, int j) { return (c0 + j < ib) ? Ap[pidx(a + c0 + j, k)] : 0.0; };
+        dbl4 s = tile_mma(dbl4{0, 0, 0, 0}, A1, B1, a);
+        s = tile_mma(s, A2, B2, a);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tile_row(e), cc = a + c0 + tile_col();
+          if (r < w && cc < b && cc <= r) Ap[pidx(r, cc)] -= s[e];
         }
-      }
-      // C-dot -= B-dot R^T + B R-dot^T   (rows [b, w), K = a)
-      for (int e = tid; e < (w - b) * ib; e += blockDim.x) {
-        const int r = b + e / ib, q = e % ib;
-        double s = 0.0;
-        for (int l = 0; l < a; ++l)
-          s = fma(Ap[pidx(r, l)], Dp[pidx(a + q, l)], fma(Dp[pidx(r, l)], Ap[pidx(a + q, l)], s));
-        Ap[pidx(r, a + q)] -= s;
       }
       __syncthreads();
     }
-    if ((tid >> 6) == 0) level2_fwd_wave(Dp, Ap, a, ib);
+    if (wave == 0) level2_fwd_wave(Dp, Ap, a, ib);
     __syncthreads();
-    // C-dot <- (C-dot - C D-dot_i^T) D_i^-T, one row per thread in place (ib == INNER whenever
-    // b < w): first y = C-dot - C D-dot_i^T (right to left, so unread entries stay original),
-    // then x D_i^T = y by forward substitution.
-    for (int r = b + tid; r < w; r += blockDim.x) {
-      for (int q = INNER - 1; q >= 0; --q) {
-        double s = Ap[pidx(r, a + q)];
-        for (int p = 0; p <= q; ++p) s = fma(-Dp[pidx(r, a + p)], Ap[pidx(a + q, a + p)], s);
-        Ap[pidx(r, a + q)] = s;
+    if (rest > 0) {
+      // Y = C-dot - C D-dot_i^T  (rows [b, w) x cols [a, b), K = 32), then C-dot = Y D_i^-T
+      stage_inverse32(Xi, Dinv, nb, a);
+      const int trr = (rest + 15) / 16;
+      dbl4 acc[3];
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+        auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Dp[pidx(r, a + k)] : 0.0; };
+        auto B = [&](int k, int j) { return (c0 + j >= k) ? Ap[pidx(a + c0 + j, a + k)] : 0.0; };
+        acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, INNER);
       }
-      for (int q = 0; q < INNER; ++q) {
-        double s = Ap[pidx(r, a + q)];
-        for (int p = 0; p < q; ++p) s = fma(-Ap[pidx(r, a + p)], Dp[pidx(a + q, a + p)], s);
-        Ap[pidx(r, a + q)] = s / Dp[pidx(a + q, a + q)];
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tile_row(e);
+          if (r < w) Ap[pidx(r, a + c0 + tile_col())] -= acc[sl][e];
+        }
       }
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+        auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Ap[pidx(r, a + k)] : 0.0; };
+        auto B = [&](int k, int j) { return Xi[(c0 + j) * XLD + k]; };   // (D_i^-1)^T
+        acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, INNER);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tile_row(e);
+          if (r < w) Ap[pidx(r, a + c0 + tile_col())] = acc[sl][e];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   for (int e = tid; e < w * w; e += blockDim.x) {
     const int r = e / w, c = e - r * w;
@@ -276,61 +557,87 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const dou
   }
 }
 
-// D <- chol_unblocked(D) (Sec. 4.1, DPOTF2) for one w x w diagonal block (w <= 128) in LDS,
-// followed by the block's inverse for the panel solve.  Column j: d <- sqrt(d - r r^T) and
-// c <- (c - B r^T) / d, applied right-looking.  The first non-positive (or NaN) pivot sets
-// *info = col0 + j + 1 unless an earlier block already set it; the sweep then continues with
-// NaN so that every kernel still exits normally.
-// In/out: A + (j, j) (lower triangle in, factor out, strict upper set to 0).  Out: Dinv (w x w,
-// ld nb, zero above the diagonal).
+// ---------------------------------------------------------------------------------------------
+// D <- chol_unblocked(D) (Sec. 4.1, DPOTF2) for one w x w diagonal block (w <= 128), left-looking
+// over 32-column inner blocks [a, b):  [D_i; C] -= [R; B] R^T;  D_i <- Level-2 factor (one wave);
+// C <- C D_i^-T.  Then D^-1 for the panel solve.  The first non-positive (or NaN) pivot sets
+// *info = col0 + column + 1 unless an earlier block already set it; the sweep then continues
+// with NaN so that every kernel still exits normally.
+// In/out: A + (j, j) (lower triangle in, factor out, strict upper set to 0).  Out: Dinv (w x w
+// inverse, ld nb, zero above the diagonal).
 __global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, int64_t lda,
                                                              double *Dinv, int nb, int *info,
                                                              int64_t col0) {
   __shared__ double Dp[DIAG_PACKED];
   __shared__ double Xp[DIAG_PACKED];
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6;
   load_packed(Dp, Ad, lda, w);
-  if (tid == 0) bad = 0;
+  if (tid == 0) bad = -1;
   __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    const double piv = Dp[pidx(j, j)];
-    const double d = sqrt(piv);
-    if (tid == 0) {
-      if (!(piv > 0.0) && bad == 0) {
-        bad = 1;
-        if (*info == 0) *info = (int)(col0 + j + 1);
+  for (int a = 0; a < w; a += INNER) {
+    const int b = min(w, a + INNER);
+    const int ib = b - a;
+    const int rest = w - b;
+    if (a > 0) {
+      // rows [a, w) x cols [a, b) -= [R; B] R^T  (K = a)
+      const int tr = (w - a + 15) / 16, tc = (ib + 15) / 16;
+      for (int t = wave; t < tr * tc; t += DIAG_WAVES) {
+        const int r0 = a + (t / tc) * 16, c0 = (t % tc) * 16;
+        if (r0 - a + 15 < c0) continue;
+        auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Dp[pidx(r, k)] : 0.0; };
+        auto B = [&](int k, int j) { return (c0 + j < ib) ? Dp[pidx(a + c0 + j, k)] : 0.0; };
+        const dbl4 s = tile_mma(dbl4{0, 0, 0, 0}, A, B, a);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tile_row(e), cc = a + c0 + tile_col();
+          if (r < w && cc < b && cc <= r) Dp[pidx(r, cc)] -= s[e];
+        }
       }
+      __syncthreads();
     }
-    for (int r = j + 1 + tid; r < w; r += blockDim.x) Dp[pidx(r, j)] /= d;
-    __syncthreads();
-    if (tid == 0) Dp[pidx(j, j)] = d;
-    // trailing update of the lower triangle: D[r][c] -= D[r][j] D[c][j], j < c <= r
-    const int t = w - j - 1;
-    for (int e = tid; e < t * t; e += blockDim.x) {
-      const int r = j + 1 + e / t, c = j + 1 + e % t;
-      if (c <= r) Dp[pidx(r, c)] = fma(-Dp[pidx(r, j)], Dp[pidx(c, j)], Dp[pidx(r, c)]);
+    if (wave == 0) {
+      const int f = level2_potf2_wave(Dp, a, ib);
+      if ((tid & 63) == 0 && f >= 0 && bad < 0) bad = a + f;
     }
     __syncthreads();
+    if (rest > 0) {
+      // C <- C D_i^-T  with D_i^-1 from one wave's 32 x 32 inverse
+      if (wave == 0) wave_trinv32(Dp, Xp, a, ib);
+      __syncthreads();
+      const int trr = (rest + 15) / 16;
+      dbl4 acc[3];
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+        auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Dp[pidx(r, a + k)] : 0.0; };
+        auto B = [&](int k, int j) { return (c0 + j >= k) ? Xp[pidx(a + c0 + j, a + k)] : 0.0; };
+        acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, INNER);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) {
+        const int t = wave + DIAG_WAVES * sl;
+        if (t >= trr * 2) continue;
+        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tile_row(e);
+          if (r < w) Dp[pidx(r, a + c0 + tile_col())] = acc[sl][e];
+        }
+      }
+      __syncthreads();
+    }
   }
-  // inverse by the row recurrence of D X = I
-  for (int i = 0; i < w; ++i) {
-    const double dii = Dp[pidx(i, i)];
-    for (int c = tid; c <= i; c += blockDim.x) {
-      double s = (c == i) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) s -= Dp[pidx(i, l)] * Xp[pidx(l, c)];
-      Xp[pidx(i, c)] = s / dii;
-    }
-    __syncthreads();
-  }
+  if (tid == 0 && bad >= 0 && *info == 0) *info = (int)(col0 + bad + 1);
+  block_inverse(Dp, Xp, w);
   for (int e = tid; e < w * w; e += blockDim.x) {
     const int r = e / w, c = e - r * w;
     Ad[(int64_t)r * lda + c] = (c <= r) ? Dp[pidx(r, c)] : 0.0;
   }
-  for (int e = tid; e < nb * nb; e += blockDim.x) {
-    const int r = e / nb, c = e - r * nb;
-    Dinv[e] = (r < w && c <= r) ? Xp[pidx(r, c)] : 0.0;
-  }
+  store_lower_square(Dinv, nb, Xp, w);
 }
 
 // Zero the strict upper triangle of an n x n matrix.

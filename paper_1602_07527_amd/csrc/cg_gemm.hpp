@@ -163,6 +163,136 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
       }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Fast path for tile-aligned products (M, N multiples of 128; every K-chunk a multiple of 32;
+// leading dimensions even and A, B 16-byte aligned): eight wave64s (2 x 4, each 64 x 32 of the
+// 128 x 128 tile, two waves per SIMD) and gfx950's direct global->LDS loads
+// (global_load_lds_dwordx4) into a two-stage ring of 32-deep K-tiles, so no registers stage the
+// operands.  Operands that are contiguous along K are stored with their 16-byte chunks XOR-swizzled
+// by row, which keeps the MFMA fragment reads free of LDS bank conflicts.
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr int DMA_BK = 32;
+constexpr int DMA_THREADS = 512;
+
+__host__ __device__ constexpr int waitcnt_vm(int n) {  // s_waitcnt immediate: vmcnt(n) only
+  return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
+}
+
+template <bool AT, bool BT, int TAG>
+__global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
+  constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = DMA_BK, TILE = BM * BK;
+  constexpr int WM = 2, WN = 4, NW = WM * WN;
+  constexpr int NQ = TILE * 8 / 1024 / NW;     // 1 KB DMA instructions per wave per operand per tile
+  static_assert(NQ * NW * 1024 == TILE * 8, "tile must split evenly over the waves");
+  constexpr int CH = BK / 2;                   // 16-byte chunks in a K-contiguous row
+  constexpr int RPI = 64 / CH;                 // K-contiguous rows per DMA instruction
+  constexpr int TMW = BM / WM / 16, TNW = BN / WN / 16;
+  __shared__ __attribute__((aligned(16))) double smem[2 * 2 * TILE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  if (p.lower_only && m0 + BM - 1 < n0) return;
+  const int z = blockIdx.z;
+  const int kbeg = z * p.kchunk;
+  const int kend = min(p.K, kbeg + p.kchunk);
+  const int nkt = (kend > kbeg) ? (kend - kbeg) / BK : 0;
+  double *Cout = p.C + (int64_t)z * p.split_stride;
+
+  // Loop-invariant per-lane byte offsets inside a tile; the tile bases advance uniformly.
+  uint32_t offA[NQ], offB[NQ];
+  int ldsA[NQ], ldsB[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = wave * NQ + q;
+    if (!AT) {
+      const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
+      offA[q] = (uint32_t)(r * p.lda * 8 + c * 16);
+      ldsA[q] = i * RPI * BK;
+    } else {
+      offA[q] = (uint32_t)(i * p.lda * 8 + lane * 16);
+      ldsA[q] = i * BM;
+    }
+    if (!BT) {
+      offB[q] = (uint32_t)(i * p.ldb * 8 + lane * 16);
+      ldsB[q] = i * BN;
+    } else {
+      const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
+      offB[q] = (uint32_t)(r * p.ldb * 8 + c * 16);
+      ldsB[q] = i * RPI * BK;
+    }
+  }
+  const char *baseA = (const char *)(AT ? p.A + (int64_t)kbeg * p.lda + m0 : p.A + (int64_t)m0 * p.lda + kbeg);
+  const char *baseB = (const char *)(BT ? p.B + (int64_t)n0 * p.ldb + kbeg : p.B + (int64_t)kbeg * p.ldb + n0);
+  const int64_t stepA = AT ? (int64_t)BK * p.lda * 8 : BK * 8;
+  const int64_t stepB = BT ? BK * 8 : (int64_t)BK * p.ldb * 8;
+
+  auto issue = [&](int kt, int st) {
+    const char *ga = baseA + kt * stepA;
+    const char *gb = baseB + kt * stepB;
+    double *as = smem + (2 * st) * TILE;
+    double *bs = smem + (2 * st + 1) * TILE;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      __builtin_amdgcn_global_load_lds((const void *)(ga + offA[q]), (lds_void *)(as + ldsA[q]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(gb + offB[q]), (lds_void *)(bs + ldsB[q]), 16, 0, 0);
+    }
+  };
+
+  dbl4 acc[TMW][TNW];
+#pragma unroll
+  for (int a = 0; a < TMW; ++a)
+#pragma unroll
+    for (int b = 0; b < TNW; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  if (nkt > 0) issue(0, 0);
+  const int fk = lane >> 4, fi = lane & 15;
+  constexpr int W0 = waitcnt_vm(0);
+  for (int kt = 0; kt < nkt; ++kt) {
+    // This wave's loads of tile kt are done; the barrier makes every wave's part visible and
+    // guarantees the other stage is no longer being read before it is refilled.
+    __builtin_amdgcn_s_waitcnt(W0);
+    __builtin_amdgcn_s_barrier();
+    if (kt + 1 < nkt) issue(kt + 1, (kt + 1) & 1);
+    const double *as = smem + (2 * (kt & 1)) * TILE;
+    const double *bs = smem + (2 * (kt & 1) + 1) * TILE;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + fk;
+      double af[TMW], bf[TNW];
+#pragma unroll
+      for (int t = 0; t < TMW; ++t) {
+        const int m = wm * (BM / WM) + t * 16 + fi;
+        af[t] = AT ? as[k * BM + m] : as[m * BK + (((k >> 1) ^ (m % CH)) << 1) + (k & 1)];
+      }
+#pragma unroll
+      for (int t = 0; t < TNW; ++t) {
+        const int n = wn * (BN / WN) + t * 16 + fi;
+        bf[t] = BT ? bs[n * BK + (((k >> 1) ^ (n % CH)) << 1) + (k & 1)] : bs[k * BN + n];
+      }
+#pragma unroll
+      for (int a = 0; a < TMW; ++a)
+#pragma unroll
+        for (int b = 0; b < TNW; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  }
+
+  const double alpha = p.alpha, beta = p.beta;
+#pragma unroll
+  for (int a = 0; a < TMW; ++a)
+#pragma unroll
+    for (int b = 0; b < TNW; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + wm * (BM / WM) + a * 16 + 4 * i + (lane >> 4);
+        const int gn = n0 + wn * (BN / WN) + b * 16 + (lane & 15);
+        double v = alpha * acc[a][b][i];
+        if (beta != 0.0) v += beta * p.Cin[(int64_t)gm * p.ldcin + gn];
+        Cout[(int64_t)gm * p.ldc + gn] = v;
+        if (p.Cm) p.Cm[(int64_t)gn * p.ldcm + gm] = v;
+      }
+}
+
 // C[m, n] = alpha * sum_{s < S} P[s*sstride + m*ldp + n] + beta * Cin[m, n], summed in split order;
 // lower_only restricts the writes to n <= m.  Optional transposed copy Cm as in the GEMM.
 __global__ __launch_bounds__(256) void reduce_splits_kernel(int M, int N, const double *P, int64_t ldp,

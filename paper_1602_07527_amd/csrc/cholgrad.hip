@@ -10,6 +10,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "cholgrad.h"
@@ -54,7 +55,8 @@ struct SweepWs {
   double *dinv = nullptr;   // inverses of the diagonal blocks of L: nblk x nb x nb
   double *panel = nullptr;  // one block column: n x nb
   double *dblk = nullptr;   // one diagonal block: nb x nb
-  double *part = nullptr;   // split-K partial tiles: PART_ELEMS
+  double *part = nullptr;   // split-K partial tiles of the main stream: PART_ELEMS
+  double *part2 = nullptr;  // split-K partial tiles of the side stream: PART_ELEMS
 };
 
 size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
@@ -64,14 +66,52 @@ size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
   w->panel = c.take((size_t)n * nb);
   w->dblk = c.take((size_t)nb * nb);
   w->part = c.take((size_t)PART_ELEMS);
+  w->part2 = c.take((size_t)PART_ELEMS);
   return c.off;
+}
+
+// Side stream for look-ahead: the diagonal-block chain of one step runs there while the next
+// step's bulk contraction runs on the caller's stream.  Created once per device on first use
+// (default priority, non-blocking) and kept for the life of the process; the mutex serialises
+// the enqueue sequences of concurrent callers so the shared events are never re-recorded
+// mid-sequence.
+struct Side {
+  hipStream_t s = nullptr;
+  hipEvent_t start = nullptr, panel = nullptr, diag = nullptr;
+};
+constexpr int MAX_DEVICES = 64;
+std::mutex g_side_mu;
+Side g_side[MAX_DEVICES];
+
+hipError_t side_for_current_device(Side **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  Side &sd = g_side[dev];
+  if (!sd.s) {
+    if ((e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.start, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.panel, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.diag, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  *out = &sd;
+  return hipSuccess;
 }
 
 bool nb_ok(int nb) { return nb == 0 || (nb >= 32 && nb <= cg::DIAG_MAX && nb % 32 == 0); }
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 template <int TAG>
-void launch_gemm_tag(bool at, bool bt, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+void launch_gemm_tag(bool at, bool bt, bool fast, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+  if (fast) {
+    const dim3 block(cg::DMA_THREADS);
+    if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, false, TAG>), grid, block, 0, s, p);
+    else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, true, TAG>), grid, block, 0, s, p);
+    else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, false, TAG>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, true, TAG>), grid, block, 0, s, p);
+    return;
+  }
   const dim3 block(cg::GEMM_THREADS);
   if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<true, false, TAG>), grid, block, 0, s, p);
   else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, true, TAG>), grid, block, 0, s, p);
@@ -79,14 +119,16 @@ void launch_gemm_tag(bool at, bool bt, dim3 grid, const cg::GemmArgs &p, hipStre
   else hipLaunchKernelGGL((cg::gemm_f64_kernel<true, true, TAG>), grid, block, 0, s, p);
 }
 
-void launch_gemm(bool at, bool bt, int tag, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+void launch_gemm(bool at, bool bt, bool fast, int tag, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
   switch (tag) {
-    case 1: launch_gemm_tag<1>(at, bt, grid, p, s); break;
-    case 2: launch_gemm_tag<2>(at, bt, grid, p, s); break;
-    case 3: launch_gemm_tag<3>(at, bt, grid, p, s); break;
-    default: launch_gemm_tag<0>(at, bt, grid, p, s); break;
+    case 1: launch_gemm_tag<1>(at, bt, fast, grid, p, s); break;
+    case 2: launch_gemm_tag<2>(at, bt, fast, grid, p, s); break;
+    case 3: launch_gemm_tag<3>(at, bt, fast, grid, p, s); break;
+    default: launch_gemm_tag<0>(at, bt, fast, grid, p, s); break;
   }
 }
+
+bool aligned16(const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
 
 // C = alpha * op(A) op(B) + beta * Cin on the MFMA kernel; splits K when the output has too few
 // tiles to fill the GPU, then sums the partial tiles in split order.  part == nullptr forbids
@@ -99,14 +141,20 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, cg::GEMM_BN);
   int tiles = tm * tn;
   if (lower_only && tm == tn) tiles = (tm * (tm + 1)) / 2;
+  // The direct-to-LDS kernel needs whole 128 x 128 output tiles, whole 32-deep K-tiles in every
+  // split, even leading dimensions and 16-byte aligned operands (its 16-byte loads never cross
+  // the matrix); everything else takes the general kernel, which guards every access.
+  const bool fast = (M % cg::GEMM_BM == 0) && (N % cg::GEMM_BN == 0) && (K > 0) && (K % cg::DMA_BK == 0) &&
+                    (lda % 2 == 0) && (ldb % 2 == 0) && aligned16(A) && aligned16(B);
+  const int kstep = fast ? cg::DMA_BK : cg::GEMM_BK;
   int S = 1;
-  int kchunk = (int)(cdiv(K > 0 ? K : 1, cg::GEMM_BK) * cg::GEMM_BK);
+  int kchunk = (int)(cdiv(K > 0 ? K : 1, kstep) * kstep);
   if (part && K > 0) {
     int64_t s_want = TARGET_WGS / tiles;
     s_want = std::min<int64_t>(s_want, cdiv(K, min_kchunk));
     s_want = std::min<int64_t>(s_want, PART_ELEMS / ((int64_t)M * N));
     if (s_want > 1) {
-      kchunk = (int)(cdiv(cdiv(K, s_want), cg::GEMM_BK) * cg::GEMM_BK);
+      kchunk = (int)(cdiv(cdiv(K, s_want), kstep) * kstep);
       S = (int)cdiv(K, kchunk);
     }
   }
@@ -130,7 +178,7 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
     g_prof.klass[u] = tag;
     g_prof.flops[u] = 2.0 * (double)M * (double)N * (double)K;
   }
-  launch_gemm(at, bt, tag, grid, p, s);
+  launch_gemm(at, bt, fast, tag, grid, p, s);
   if (timed) {
     if (hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s) != hipSuccess) return hipErrorUnknown;
     ++g_prof.used;
@@ -247,37 +295,59 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   double *A = static_cast<double *>(Av);
   const int64_t nblk = cdiv(n, nb);
 
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side *side = nullptr;
+  CG_TRY(side_for_current_device(&side));
+  hipStream_t s2 = side->s;
+
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
                      ldl, ws.dinv);
   CG_TRY(hipGetLastError());
+  CG_TRY(hipEventRecord(side->start, s));
+  CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
 
   // Reverse sweep over block columns, right to left, in left-looking ("lazy") order: when block
   // [j, k) is reached, everything right of it is final and is stored as the symmetric gradient
   // S_sym in both triangles of A[k:, k:].  The accumulated knock-on terms of Sec. 4.2's
   // B-bar / R-bar updates then collapse to one product:
   //   C-bar = L-bar_C - (T + T^T)[k:, k:] L[k:, j:k] = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k].
+  // Look-ahead: the rows of that product below block b+1 need only block b+1's panel, so they run
+  // on the caller's stream while block b+1's SYRK and diagonal adjoint run on the side stream;
+  // only block b+1's own rows wait for its diagonal block.
   for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
     const int m = (int)(n - k);
     if (m > 0) {
-      // X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k]                   -> panel (m x w)
-      CG_TRY(gemm(false, false, m, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
+      const int m1 = std::min(m, nb);  // rows of block b+1
+      const int m2 = m - m1;           // rows below block b+1
+      // X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k]   -> panel (m x w), rows below block b+1 first
+      if (m2 > 0)
+        CG_TRY(gemm(false, false, m2, w, m, A + (k + m1) * lda + k, lda, L + k * ldl + j, ldl, -2.0,
+                    A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0,
+                    ws.part, 128, s, 1));
+      CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
+      CG_TRY(gemm(false, false, m1, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                   A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 128, s, 1));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
       // triangles.
       CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0,
                   0.0, A + k * lda + j, lda, A + j * lda + k, lda, 0, nullptr, 128, s));
+      CG_TRY(hipEventRecord(side->panel, s));
+      CG_TRY(hipStreamWaitEvent(s2, side->panel, 0));
       // D-bar = tril(L-bar_D) - tril(C-bar^T C), C-bar = 2 * A[k:, j:k]   -> dblk (w x w)
       CG_TRY(gemm(true, false, w, w, m, A + k * lda + j, lda, L + k * ldl + j, ldl, -2.0,
-                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part, 64, s));
+                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part2, 64, s2));
     } else {
-      CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s));
+      CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s2));
     }
-    hipLaunchKernelGGL(cg::diag_rev_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w,
-                       L + j * ldl + j, ldl, (const double *)ws.dblk, (int64_t)nb, A + j * lda + j, lda);
+    hipLaunchKernelGGL(cg::diag_rev_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w,
+                       L + j * ldl + j, ldl, (const double *)ws.dblk, (int64_t)nb,
+                       (const double *)(ws.dinv + b * nb * nb), nb, A + j * lda + j, lda);
     CG_TRY(hipGetLastError());
+    CG_TRY(hipEventRecord(side->diag, s2));
   }
+  CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
   if (sbar_form == CHOL_SBAR_TRIL) {
     const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
     hipLaunchKernelGGL(cg::sym_to_tril_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
@@ -367,7 +437,7 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     }
     // D-dot <- chol_unblocked_fwd(D, D-dot)   (strict upper triangle of the block set to 0)
     hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w, L + j * ldl + j,
-                       ldl, A + j * lda + j, lda);
+                       ldl, (const double *)(ws.dinv + b * nb * nb), nb, A + j * lda + j, lda);
     CG_TRY(hipGetLastError());
     if (m > 0) {
       // C-dot <- (C-dot - C D-dot^T) D^-T
