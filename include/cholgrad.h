@@ -111,6 +111,55 @@ int chol_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int6
              void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Batched forms: many independent problems in ONE persistent launch (Sec. 4.2 algorithms applied
+ * per problem, nb = 128; a problem with n <= 128 is one diagonal block and stays in LDS).  All
+ * per-problem arguments are DEVICE arrays with `batch` entries: n[b] is the size of problem b,
+ * A[b] (and L[b], y[b], G[b]) are device pointers to its row-major data with leading dimensions
+ * lda[b] (ldl[b], ldg[b]) >= n[b].  n_max (host value, <= 512) bounds every n[b]; sizes above 512
+ * return CHOL_ERR_UNSUPPORTED.  A problem whose size is outside [0, 512] or whose leading
+ * dimension is smaller than its size is skipped (its info entry, where there is one, becomes -1).
+ * Problems are processed largest first; each problem's result does not depend on the batch it is
+ * in.  Workspace: chol_batched_workspace_bytes(precision, batch, n_max) bytes, 256-byte aligned.
+ * Semantics per problem are those of the single-matrix calls above.
+ */
+size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max);
+
+/* Arguments: 1 precision, 2 batch, 3 n, 4 A, 5 lda, 6 n_max, 7 info (device, batch ints),
+ *            8 workspace, 9 workspace_bytes, 10 stream. */
+int chol_factor_batched(int precision, int batch, const int64_t *n, void *const *A, const int64_t *lda,
+                        int64_t n_max, int *info, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Arguments: 1 precision, 2 batch, 3 n, 4 L, 5 ldl, 6 A, 7 lda, 8 n_max, 9 sbar_form, 10 workspace,
+ *            11 workspace_bytes, 12 stream. */
+int chol_rev_batched(int precision, int batch, const int64_t *n, const void *const *L, const int64_t *ldl,
+                     void *const *A, const int64_t *lda, int64_t n_max, int sbar_form, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* Arguments: 1 precision, 2 batch, 3 n, 4 L, 5 ldl, 6 A, 7 lda, 8 n_max, 9 workspace,
+ *            10 workspace_bytes, 11 stream. */
+int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *const *L, const int64_t *ldl,
+                     void *const *A, const int64_t *lda, int64_t n_max, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/*
+ * chol_gp_nll_batched -- the whole x -> Sigma -> L -> f -> Sigma-bar chain of Sec. 2 per problem, in
+ * one launch, for the Gaussian-process style loss
+ *     f_b = sum_i log L_ii + (1/2) |L^-1 y_b|^2      (= (1/2) log det Sigma + (1/2) y^T Sigma^-1 y)
+ * whose reverse-mode input is L-bar = diag(1/L_ii) - tril(w z^T), z = L^-1 y, w = L^-T z:
+ *   A[b]   in: tril = Sigma_b.  out: L_b (strict upper set to 0).
+ *   y[b]   in: n[b] doubles.
+ *   G[b]   out: Sigma-bar_b = df_b/dSigma_b, the symmetric gradient in both triangles
+ *          (= (Sigma^-1 - a a^T)/2 with a = Sigma^-1 y).
+ *   f      out: device array of batch doubles.
+ *   info   out: device array of batch ints (LAPACK convention; f = NaN and G untouched when > 0).
+ *   Arguments: 1 precision, 2 batch, 3 n, 4 A, 5 lda, 6 y, 7 G, 8 ldg, 9 f, 10 n_max, 11 info,
+ *              12 workspace, 13 workspace_bytes, 14 stream.
+ */
+int chol_gp_nll_batched(int precision, int batch, const int64_t *n, void *const *A, const int64_t *lda,
+                        const void *const *y, void *const *G, const int64_t *ldg, void *f, int64_t n_max,
+                        int *info, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Benchmark instrumentation (creates HIP events, so not for allocation-free paths).
  * chol_profile_begin: until chol_profile_end, each launch of a sweep's panel contraction -- the
  *   kernel that carries nearly all of a sweep's flops -- is bracketed by a pair of hipEvents on the

@@ -311,16 +311,22 @@ __device__ __forceinline__ void store_lower_square(double *dst, int nb, const do
 // Inverse of each lower-triangular diagonal block: block b covers rows/cols [b*nb, min(n,(b+1)nb)).
 // Output Dinv + b*nb*nb, row-major with leading dimension nb, zero above the diagonal and outside
 // the w x w block.
+__device__ __forceinline__ void trinv_block(int w, const double *Ld, int64_t ldl, double *Dinv, int nb, double *Dp,
+                            double *Xp) {
+  load_packed(Dp, Ld, ldl, w);
+  __syncthreads();
+  block_inverse(Dp, Xp, w);
+  store_lower_square(Dinv, nb, Xp, w);
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(DIAG_THREADS) void trinv_kernel(int64_t n, int nb, const double *L,
                                                              int64_t ldl, double *Dinv) {
   __shared__ double Dp[DIAG_PACKED];
   __shared__ double Xp[DIAG_PACKED];
   const int64_t j = (int64_t)blockIdx.x * nb;
   const int w = (int)min<int64_t>(nb, n - j);
-  load_packed(Dp, L + j * ldl + j, ldl, w);
-  __syncthreads();
-  block_inverse(Dp, Xp, w);
-  store_lower_square(Dinv + (int64_t)blockIdx.x * nb * nb, nb, Xp, w);
+  trinv_block(w, L + j * ldl + j, ldl, Dinv + (int64_t)blockIdx.x * nb * nb, nb, Dp, Xp);
 }
 
 // Stage the 32 x 32 diagonal sub-block [a, a+32)^2 of a block inverse (row-major, ld nb) in LDS.
@@ -340,13 +346,9 @@ __device__ __forceinline__ void stage_inverse32(double *Xi, const double *Dinv, 
 // Dinv: this block's inverse (ld nb).
 // Out: the block of the symmetric gradient, written to both triangles of A + (j, j):
 //   A[r][c] = A[c][r] = T[r][c] / 2 (r > c),  A[r][r] = T[r][r],   T = final D-bar.
-__global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const double *Ld, int64_t ldl,
-                                                                const double *Dbar, int64_t ldd,
-                                                                const double *Dinv, int nb,
-                                                                double *Aout, int64_t lda) {
-  __shared__ double Dp[DIAG_PACKED];
-  __shared__ double Bp[DIAG_PACKED];
-  __shared__ double Xi[INNER * XLD];
+__device__ __forceinline__ void diag_rev_block(int w, const double *Ld, int64_t ldl, const double *Dbar, int64_t ldd,
+                               const double *Dinv, int nb, double *Aout, int64_t lda, double *Dp,
+                               double *Bp, double *Xi) {
   const int tid = threadIdx.x, wave = tid >> 6;
   load_packed(Dp, Ld, ldl, w);
   load_packed(Bp, Dbar, ldd, w);
@@ -453,6 +455,17 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const dou
       Aout[(int64_t)r * lda + cc] = v;
     }
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const double *Ld, int64_t ldl,
+                                                                const double *Dbar, int64_t ldd,
+                                                                const double *Dinv, int nb,
+                                                                double *Aout, int64_t lda) {
+  __shared__ double Dp[DIAG_PACKED];
+  __shared__ double Bp[DIAG_PACKED];
+  __shared__ double Xi[INNER * XLD];
+  diag_rev_block(w, Ld, ldl, Dbar, ldd, Dinv, nb, Aout, lda, Dp, Bp, Xi);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -463,12 +476,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const dou
 // In: L + (j, j) (ldl), A + (j, j) holding tril of the updated Sigma-dot block, Dinv: this
 // block's inverse (ld nb).  Out: the block's L-dot in the lower triangle of A + (j, j); its strict
 // upper triangle is set to 0.
-__global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const double *Ld, int64_t ldl,
-                                                                const double *Dinv, int nb,
-                                                                double *Ad, int64_t lda) {
-  __shared__ double Dp[DIAG_PACKED];
-  __shared__ double Ap[DIAG_PACKED];
-  __shared__ double Xi[INNER * XLD];
+__device__ __forceinline__ void diag_fwd_block(int w, const double *Ld, int64_t ldl, const double *Dinv, int nb,
+                               double *Ad, int64_t lda, double *Dp, double *Ap, double *Xi) {
   const int tid = threadIdx.x, wave = tid >> 6;
   load_packed(Dp, Ld, ldl, w);
   load_packed(Ap, Ad, lda, w);
@@ -555,6 +564,16 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const dou
     const int r = e / w, c = e - r * w;
     Ad[(int64_t)r * lda + c] = (c <= r) ? Ap[pidx(r, c)] : 0.0;
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const double *Ld, int64_t ldl,
+                                                                const double *Dinv, int nb,
+                                                                double *Ad, int64_t lda) {
+  __shared__ double Dp[DIAG_PACKED];
+  __shared__ double Ap[DIAG_PACKED];
+  __shared__ double Xi[INNER * XLD];
+  diag_fwd_block(w, Ld, ldl, Dinv, nb, Ad, lda, Dp, Ap, Xi);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -565,12 +584,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const dou
 // with NaN so that every kernel still exits normally.
 // In/out: A + (j, j) (lower triangle in, factor out, strict upper set to 0).  Out: Dinv (w x w
 // inverse, ld nb, zero above the diagonal).
-__global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, int64_t lda,
-                                                             double *Dinv, int nb, int *info,
-                                                             int64_t col0) {
-  __shared__ double Dp[DIAG_PACKED];
-  __shared__ double Xp[DIAG_PACKED];
-  __shared__ int bad;
+__device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int nb, int *info,
+                            int64_t col0, double *Dp, double *Xp, int &bad) {
   const int tid = threadIdx.x, wave = tid >> 6;
   load_packed(Dp, Ad, lda, w);
   if (tid == 0) bad = -1;
@@ -638,6 +653,16 @@ __global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, 
     Ad[(int64_t)r * lda + c] = (c <= r) ? Dp[pidx(r, c)] : 0.0;
   }
   store_lower_square(Dinv, nb, Xp, w);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, int64_t lda,
+                                                             double *Dinv, int nb, int *info,
+                                                             int64_t col0) {
+  __shared__ double Dp[DIAG_PACKED];
+  __shared__ double Xp[DIAG_PACKED];
+  __shared__ int bad;
+  potf2_block(w, Ad, lda, Dinv, nb, info, col0, Dp, Xp, bad);
 }
 
 // Zero the strict upper triangle of an n x n matrix.

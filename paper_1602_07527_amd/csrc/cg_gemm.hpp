@@ -44,27 +44,26 @@ struct GemmArgs {
   int lower_only;       // skip output tiles lying strictly above the diagonal (m < n throughout)
 };
 
-// TAG only separates kernel names for profiling (1: reverse-sweep panel contraction,
-// 2: factor-sweep panel contraction, 3: forward-sweep panel contraction, 0: other products).
-template <bool AT, bool BT, int TAG>
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
+constexpr int GEMM_LDS_A = GEMM_BK * (GEMM_BM + GEMM_PAD);   // doubles per A stage
+constexpr int GEMM_LDS_B = GEMM_BK * (GEMM_BN + GEMM_PAD);   // doubles per B stage
+constexpr int GEMM_LDS = 2 * (GEMM_LDS_A + GEMM_LDS_B);      // doubles of LDS for one tile product
+
+// One 128 x 128 output tile (rows m0.., columns n0..) over K range [kbeg, kend), written to Cout
+// with the epilogue of p (alpha, beta * Cin, optional transposed copy).  Called by a whole
+// 256-thread workgroup; `lds` holds GEMM_LDS doubles.  Ends with a barrier, so the workgroup may
+// reuse `lds` right after.
+template <bool AT, bool BT>
+__device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend, double *Cout,
+                          double *lds) {
   constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK, LDA_S = BM + GEMM_PAD,
                 LDB_S = BN + GEMM_PAD;
-  __shared__ double As[2][BK * LDA_S];
-  __shared__ double Bs[2][BK * LDB_S];
+  double *As[2] = {lds, lds + GEMM_LDS_A};
+  double *Bs[2] = {lds + 2 * GEMM_LDS_A, lds + 2 * GEMM_LDS_A + GEMM_LDS_B};
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
-  if (p.lower_only && m0 + BM - 1 < n0) return;  // whole tile strictly above the diagonal
-
-  const int z = blockIdx.z;
-  const int kbeg = z * p.kchunk;
-  const int kend = min(p.K, kbeg + p.kchunk);
-  double *Cout = p.C + (int64_t)z * p.split_stride;
 
   dbl4 acc[4][4];
 #pragma unroll
@@ -161,6 +160,21 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
           if (p.Cm) p.Cm[(int64_t)gn * p.ldcm + gm] = v;
         }
       }
+  __syncthreads();
+}
+
+// TAG only separates kernel names for profiling (1: reverse-sweep panel contraction,
+// 2: factor-sweep panel contraction, 3: forward-sweep panel contraction, 0: other products).
+template <bool AT, bool BT, int TAG>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
+  __shared__ double lds[GEMM_LDS];
+  const int m0 = blockIdx.x * GEMM_BM;
+  const int n0 = blockIdx.y * GEMM_BN;
+  if (p.lower_only && m0 + GEMM_BM - 1 < n0) return;  // whole tile strictly above the diagonal
+  const int z = blockIdx.z;
+  const int kbeg = z * p.kchunk;
+  const int kend = min(p.K, kbeg + p.kchunk);
+  gemm_tile<AT, BT>(p, m0, n0, kbeg, kend, p.C + (int64_t)z * p.split_stride, lds);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -294,7 +308,9 @@ __global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
 }
 
 // C[m, n] = alpha * sum_{s < S} P[s*sstride + m*ldp + n] + beta * Cin[m, n], summed in split order;
-// lower_only restricts the writes to n <= m.  Optional transposed copy Cm as in the GEMM.
+// lower_only restricts the writes to n <= m.  Optional transposed copy Cm as in the GEMM.  Eight
+// partial loads are kept in flight per thread; the additions stay in split order, so the result
+// is bitwise reproducible.
 __global__ __launch_bounds__(256) void reduce_splits_kernel(int M, int N, const double *P, int64_t ldp,
                                                             int64_t sstride, int S, double alpha,
                                                             const double *Cin, int64_t ldcin,
@@ -305,8 +321,17 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(int M, int N, const 
        e += (int64_t)gridDim.x * blockDim.x) {
     const int m = (int)(e / N), n = (int)(e % N);
     if (lower_only && n > m) continue;
+    const double *src = P + (int64_t)m * ldp + n;
     double s = 0.0;
-    for (int z = 0; z < S; ++z) s += P[(int64_t)z * sstride + (int64_t)m * ldp + n];
+    int z = 0;
+    for (; z + 8 <= S; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(z + u) * sstride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; z < S; ++z) s += src[(int64_t)z * sstride];
     double v = alpha * s;
     if (beta != 0.0) v += beta * Cin[(int64_t)m * ldcin + n];
     C[(int64_t)m * ldc + n] = v;

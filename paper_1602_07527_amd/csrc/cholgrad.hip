@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "cholgrad.h"
+#include "cg_batched.hpp"
 #include "cg_diag.hpp"
 #include "cg_gemm.hpp"
 
@@ -186,7 +187,7 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || S == 1) return e;
   const int64_t total = (int64_t)M * N;
-  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 2048);
+  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 4096);
   hipLaunchKernelGGL(cg::reduce_splits_kernel, dim3(blocks), dim3(256), 0, s, M, N, part, (int64_t)N,
                      (int64_t)M * N, S, alpha, Cin, ldcin, beta, C, ldc, Cm, ldcm, lower_only);
   return hipGetLastError();
@@ -203,11 +204,54 @@ hipError_t copy_scaled(int M, int N, const double *src, int64_t lds, double beta
   return hipGetLastError();
 }
 
+
 #define CG_TRY(expr)                          \
   do {                                        \
     hipError_t _e = (expr);                   \
     if (_e != hipSuccess) return CHOL_ERR_HIP; \
   } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Batched forms: one persistent launch of cg::batch_kernel with BATCH_WGS workgroups.
+constexpr int BATCH_WGS = 256;  // one 140 KB-LDS workgroup per compute unit of an MI355X
+
+struct BatchWs {
+  int *order = nullptr;
+  int *counter = nullptr;
+  double *slots = nullptr;
+};
+
+size_t carve_batch(int batch, void *base, BatchWs *w) {
+  Carver c(base);
+  w->order = reinterpret_cast<int *>(c.take((size_t)cdiv(batch, 2)));
+  w->counter = reinterpret_cast<int *>(c.take(1));
+  w->slots = c.take((size_t)BATCH_WGS * cg::SLOT_DOUBLES);
+  return c.off;
+}
+
+int run_batched(cg::BatchArgs a, int64_t n_max, void *workspace, size_t workspace_bytes, hipStream_t s) {
+  BatchWs ws;
+  const size_t need = carve_batch(a.batch, nullptr, &ws);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
+    return CHOL_ERR_WORKSPACE;
+  carve_batch(a.batch, workspace, &ws);
+  a.order = ws.order;
+  a.counter = ws.counter;
+  a.slots = ws.slots;
+  hipLaunchKernelGGL(cg::batch_order_kernel, dim3(1), dim3(256), 0, s, a.batch, a.n, (int)n_max, ws.order,
+                     ws.counter);
+  CG_TRY(hipGetLastError());
+  const dim3 grid(std::min(a.batch, BATCH_WGS)), block(cg::DIAG_THREADS);
+  switch (a.op) {
+    case cg::BATCH_FACTOR: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FACTOR>, grid, block, 0, s, a); break;
+    case cg::BATCH_REV: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_REV>, grid, block, 0, s, a); break;
+    case cg::BATCH_FWD: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FWD>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_GP>, grid, block, 0, s, a); break;
+  }
+  CG_TRY(hipGetLastError());
+  return CHOL_SUCCESS;
+}
+
 
 }  // namespace
 
@@ -325,10 +369,10 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       if (m2 > 0)
         CG_TRY(gemm(false, false, m2, w, m, A + (k + m1) * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                     A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0,
-                    ws.part, 128, s, 1));
+                    ws.part, 256, s, 1));
       CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
       CG_TRY(gemm(false, false, m1, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
-                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 128, s, 1));
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 256, s, 1));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
       // triangles.
       CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0,
@@ -337,7 +381,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       CG_TRY(hipStreamWaitEvent(s2, side->panel, 0));
       // D-bar = tril(L-bar_D) - tril(C-bar^T C), C-bar = 2 * A[k:, j:k]   -> dblk (w x w)
       CG_TRY(gemm(true, false, w, w, m, A + k * lda + j, lda, L + k * ldl + j, ldl, -2.0,
-                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part2, 64, s2));
+                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part2, 256, s2));
     } else {
       CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s2));
     }
@@ -374,26 +418,44 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   hipStream_t s = static_cast<hipStream_t>(stream);
   double *A = static_cast<double *>(Av);
   const int64_t nblk = cdiv(n, nb);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side *side = nullptr;
+  CG_TRY(side_for_current_device(&side));
+  hipStream_t s2 = side->s;
   hipLaunchKernelGGL(cg::set_int_kernel, dim3(1), dim3(1), 0, s, info, 0);
   CG_TRY(hipGetLastError());
-  // Sec. 4.2 chol_blocked, left to right.
+  CG_TRY(hipEventRecord(side->start, s));
+  CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
+  // Sec. 4.2 chol_blocked, left to right, with look-ahead: the update of block column b over the
+  // columns left of block b-1 runs on the caller's stream while block b-1's diagonal factor and
+  // panel solve run on the side stream; only the K = nb slice over block b-1 waits for them.
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
     const int m = (int)(n - k);
-    // [D; C] <- [D; C] - [R; B] R^T   (D - tril(R R^T) and C - B R^T in one product, K = j)
-    if (j > 0)
-      CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, A + j * lda, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s, 2));
+    if (b > 0) {
+      const int64_t jp = j - nb;  // block b-1 is [jp, j)
+      // [D; C] <- [D; C] - [R; B] R^T   (D - tril(R R^T) and C - B R^T in one product)
+      if (jp > 0)
+        CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, A + j * lda, lda, -1.0,
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2));
+      CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+      CG_TRY(gemm(false, true, (int)(n - j), w, nb, A + j * lda + jp, lda, A + j * lda + jp, lda, -1.0,
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2));
+      CG_TRY(hipEventRecord(side->diag, s));
+      CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
+    }
     // D <- chol_unblocked(D); D^-1 for the panel solve
-    hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w, A + j * lda + j, lda,
+    hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, A + j * lda + j, lda,
                        ws.dblk, nb, info, j);
     CG_TRY(hipGetLastError());
     // C <- C tril(D)^-T   (every output tile spans all w <= 128 columns, so in place is safe)
     if (m > 0)
       CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
-                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s));
+                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+    CG_TRY(hipEventRecord(side->panel, s2));
   }
+  CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
   const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
   hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
   CG_TRY(hipGetLastError());
@@ -420,37 +482,140 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   const double *L = static_cast<const double *>(Lv);
   double *A = static_cast<double *>(Av);
   const int64_t nblk = cdiv(n, nb);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side *side = nullptr;
+  CG_TRY(side_for_current_device(&side));
+  hipStream_t s2 = side->s;
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
                      ldl, ws.dinv);
   CG_TRY(hipGetLastError());
-  // Sec. 4.2 chol_blocked_fwd, left to right.
+  CG_TRY(hipEventRecord(side->start, s));
+  CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
+  // Sec. 4.2 chol_blocked_fwd, left to right, with the same look-ahead as chol_factor.
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
     const int m = (int)(n - k);
-    if (j > 0) {
-      // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T   (K = j each)
-      CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s, 3));
-      CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, L + j * ldl, ldl, A + j * lda, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 128, s, 3));
+    if (b > 0) {
+      const int64_t jp = j - nb;
+      // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T   over columns [0, jp), then [jp, j)
+      if (jp > 0) {
+        CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, L + j * ldl, ldl, -1.0,
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+        CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, L + j * ldl, ldl, A + j * lda, lda, -1.0,
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+      }
+      CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+      CG_TRY(gemm(false, true, (int)(n - j), w, nb, A + j * lda + jp, lda, L + j * ldl + jp, ldl, -1.0,
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+      CG_TRY(gemm(false, true, (int)(n - j), w, nb, L + j * ldl + jp, ldl, A + j * lda + jp, lda, -1.0,
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+      CG_TRY(hipEventRecord(side->diag, s));
+      CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
     }
     // D-dot <- chol_unblocked_fwd(D, D-dot)   (strict upper triangle of the block set to 0)
-    hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, w, L + j * ldl + j,
+    hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, L + j * ldl + j,
                        ldl, (const double *)(ws.dinv + b * nb * nb), nb, A + j * lda + j, lda);
     CG_TRY(hipGetLastError());
     if (m > 0) {
       // C-dot <- (C-dot - C D-dot^T) D^-T
       CG_TRY(gemm(false, true, m, w, w, L + k * ldl + j, ldl, A + j * lda + j, lda, -1.0,
-                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, nullptr, 128, s));
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, nullptr, 128, s2));
       CG_TRY(gemm(false, true, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 1.0, nullptr, 0, 0.0,
-                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s));
+                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
     }
+    CG_TRY(hipEventRecord(side->panel, s2));
   }
+  CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
   const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
   hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
   CG_TRY(hipGetLastError());
   return CHOL_SUCCESS;
+}
+
+
+size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max) {
+  if (precision != CHOL_PREC_F64 || batch <= 0 || n_max < 0 || n_max > cg::BATCH_NMAX) return 0;
+  BatchWs w;
+  return carve_batch(batch, nullptr, &w);
+}
+
+static int batched_common_checks(int precision, int batch, int64_t n_max) {
+  if (precision != CHOL_PREC_F64) return -1;
+  if (batch < 0) return -2;
+  if (n_max < 0 || n_max > cg::BATCH_NMAX) return CHOL_ERR_UNSUPPORTED;
+  return CHOL_SUCCESS;
+}
+
+int chol_factor_batched(int precision, int batch, const int64_t *n, void *const *A, const int64_t *lda,
+                        int64_t n_max, int *info, void *workspace, size_t workspace_bytes, void *stream) {
+  int rc = batched_common_checks(precision, batch, n_max);
+  if (rc != CHOL_SUCCESS) return rc;
+  if (batch == 0) return CHOL_SUCCESS;
+  if (!n) return -3;
+  if (!A) return -4;
+  if (!lda) return -5;
+  if (!info) return -7;
+  cg::BatchArgs a{};
+  a.op = cg::BATCH_FACTOR; a.batch = batch; a.n = n; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
+  a.info = info;
+  return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int chol_rev_batched(int precision, int batch, const int64_t *n, const void *const *L, const int64_t *ldl,
+                     void *const *A, const int64_t *lda, int64_t n_max, int sbar_form, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+  int rc = batched_common_checks(precision, batch, n_max);
+  if (rc != CHOL_SUCCESS) return rc;
+  if (batch == 0) return CHOL_SUCCESS;
+  if (!n) return -3;
+  if (!L) return -4;
+  if (!ldl) return -5;
+  if (!A) return -6;
+  if (!lda) return -7;
+  if (sbar_form != CHOL_SBAR_SYM && sbar_form != CHOL_SBAR_TRIL) return -9;
+  cg::BatchArgs a{};
+  a.op = cg::BATCH_REV; a.batch = batch; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
+  a.ldl = ldl; a.A = reinterpret_cast<double *const *>(A); a.lda = lda; a.sbar_form = sbar_form;
+  return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *const *L, const int64_t *ldl,
+                     void *const *A, const int64_t *lda, int64_t n_max, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+  int rc = batched_common_checks(precision, batch, n_max);
+  if (rc != CHOL_SUCCESS) return rc;
+  if (batch == 0) return CHOL_SUCCESS;
+  if (!n) return -3;
+  if (!L) return -4;
+  if (!ldl) return -5;
+  if (!A) return -6;
+  if (!lda) return -7;
+  cg::BatchArgs a{};
+  a.op = cg::BATCH_FWD; a.batch = batch; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
+  a.ldl = ldl; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
+  return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int chol_gp_nll_batched(int precision, int batch, const int64_t *n, void *const *A, const int64_t *lda,
+                        const void *const *y, void *const *G, const int64_t *ldg, void *f, int64_t n_max,
+                        int *info, void *workspace, size_t workspace_bytes, void *stream) {
+  int rc = batched_common_checks(precision, batch, n_max);
+  if (rc != CHOL_SUCCESS) return rc;
+  if (batch == 0) return CHOL_SUCCESS;
+  if (!n) return -3;
+  if (!A) return -4;
+  if (!lda) return -5;
+  if (!y) return -6;
+  if (!G) return -7;
+  if (!ldg) return -8;
+  if (!f) return -9;
+  if (!info) return -11;
+  cg::BatchArgs a{};
+  a.op = cg::BATCH_GP; a.batch = batch; a.n = n; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
+  a.y = reinterpret_cast<const double *const *>(y); a.G = reinterpret_cast<double *const *>(G); a.ldg = ldg;
+  a.f = static_cast<double *>(f); a.info = info;
+  return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
