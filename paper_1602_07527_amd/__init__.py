@@ -4,9 +4,13 @@ Public calls (torch tensors as device memory, work on the current stream):
   chol_factor(A)     Sigma -> L               (Sec. 4.2 chol_blocked)
   chol_rev(L, A)     L-bar -> Sigma-bar       (Sec. 4.2 chol_blocked_rev)
   chol_fwd(L, A)     Sigma-dot -> L-dot       (Sec. 4.2 chol_blocked_fwd)
+and their batched forms (many matrices, n <= 512, one persistent launch), including a fused
+Gaussian-process loss chol_gp_nll_batched (Sigma -> L -> f -> Sigma-bar per matrix).
 """
-from ._binding import (CholError, LIB_PATH, chol_factor, chol_fwd, chol_rev, load_library,
-                       profile_begin, profile_end, workspace_bytes)
+from ._binding import (Batch, CholError, LIB_PATH, batched_workspace_bytes, chol_factor,
+                       chol_factor_batched, chol_fwd, chol_fwd_batched, chol_gp_nll_batched, chol_rev,
+                       chol_rev_batched, load_library, profile_begin, profile_end, workspace_bytes)
 
-__all__ = ["CholError", "LIB_PATH", "chol_factor", "chol_fwd", "chol_rev", "load_library",
-           "profile_begin", "profile_end", "workspace_bytes"]
+__all__ = ["Batch", "CholError", "LIB_PATH", "batched_workspace_bytes", "chol_factor",
+           "chol_factor_batched", "chol_fwd", "chol_fwd_batched", "chol_gp_nll_batched", "chol_rev",
+           "chol_rev_batched", "load_library", "profile_begin", "profile_end", "workspace_bytes"]

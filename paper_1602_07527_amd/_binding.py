@@ -49,6 +49,16 @@ def load_library():
     lib.chol_status_string.restype = ctypes.c_char_p
     lib.chol_version.argtypes = []
     lib.chol_version.restype = i32
+    lib.chol_batched_workspace_bytes.argtypes = [i32, i32, i64]
+    lib.chol_batched_workspace_bytes.restype = sz
+    lib.chol_factor_batched.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp, sz, vp]
+    lib.chol_factor_batched.restype = i32
+    lib.chol_rev_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, i32, vp, sz, vp]
+    lib.chol_rev_batched.restype = i32
+    lib.chol_fwd_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, vp, sz, vp]
+    lib.chol_fwd_batched.restype = i32
+    lib.chol_gp_nll_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, sz, vp]
+    lib.chol_gp_nll_batched.restype = i32
     lib.chol_profile_begin.argtypes = [i32]
     lib.chol_profile_begin.restype = i32
     lib.chol_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -150,3 +160,128 @@ def profile_end():
     nl = (ctypes.c_int64 * 3)()
     _check("chol_profile_end", load_library().chol_profile_end(ms, fl, nl))
     return {k: (ms[i], fl[i], int(nl[i])) for i, k in enumerate(("rev", "factor", "fwd"))}
+
+
+# ------------------------------------------------------------------------------------------------
+# Batched forms (one persistent launch per call)
+
+BATCH_NMAX = 512
+
+
+class Batch:
+    """Device-side description of a list of square float64 matrices (sizes, pointers, leading
+    dimensions), built once and reusable across calls on the same tensors."""
+
+    def __init__(self, mats):
+        if len(mats) == 0:
+            raise ValueError("empty batch")
+        dev = mats[0].device
+        sizes, ptrs, lds = [], [], []
+        for t in mats:
+            if t.device != dev:
+                raise ValueError("all matrices of a batch must be on one device")
+            n = _square("batch matrix", t)
+            sizes.append(n)
+            ptrs.append(t.data_ptr())
+            lds.append(t.stride(0) if n else 1)
+        self.device = dev
+        self.mats = list(mats)
+        self.sizes = sizes
+        self.n_max = max(sizes)
+        if self.n_max > BATCH_NMAX:
+            raise ValueError(f"batched calls support n <= {BATCH_NMAX}")
+        self.n = torch.tensor(sizes, dtype=torch.int64).to(dev)
+        self.ptr = torch.tensor(ptrs, dtype=torch.int64).to(dev)
+        self.ld = torch.tensor(lds, dtype=torch.int64).to(dev)
+
+    def __len__(self):
+        return len(self.sizes)
+
+
+def _vec_ptrs(vecs, sizes, dev):
+    for v, n in zip(vecs, sizes):
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+                and v.numel() == n and v.device == dev):
+            raise ValueError("vectors must be contiguous float64 device tensors matching the sizes")
+    return torch.tensor([v.data_ptr() for v in vecs], dtype=torch.int64).to(dev)
+
+
+def batched_workspace_bytes(batch, n_max):
+    return int(load_library().chol_batched_workspace_bytes(PREC_F64, int(batch), int(n_max)))
+
+
+def _batch_ws(batch, n_max, device, workspace):
+    need = batched_workspace_bytes(batch, n_max)
+    if workspace is None:
+        return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace must hold {need} bytes")
+    return workspace
+
+
+def _as_batch(x):
+    return x if isinstance(x, Batch) else Batch(x)
+
+
+def chol_factor_batched(A, info=None, workspace=None):
+    """In place on every matrix: tril = Sigma -> L (strict upper 0).  Returns the device int32
+    info array (0, LAPACK-style pivot index, or -1 for an invalid entry)."""
+    lib = load_library()
+    A = _as_batch(A)
+    if info is None:
+        info = torch.empty(len(A), dtype=torch.int32, device=A.device)
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    with torch.cuda.device(A.device):
+        _check("chol_factor_batched", lib.chol_factor_batched(
+            PREC_F64, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), A.n_max, info.data_ptr(),
+            ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return info
+
+
+def chol_rev_batched(L, A, form="sym", workspace=None):
+    """In place on every A[b]: tril = L-bar -> Sigma-bar (form 'sym' or 'tril')."""
+    lib = load_library()
+    L, A = _as_batch(L), _as_batch(A)
+    if L.sizes != A.sizes:
+        raise ValueError("L and A batches must have the same sizes")
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    with torch.cuda.device(A.device):
+        _check("chol_rev_batched", lib.chol_rev_batched(
+            PREC_F64, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
+            A.ld.data_ptr(), A.n_max, _FORMS[form], ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return A.mats
+
+
+def chol_fwd_batched(L, A, workspace=None):
+    """In place on every A[b]: tril = tril(Sigma-dot) -> L-dot (strict upper 0)."""
+    lib = load_library()
+    L, A = _as_batch(L), _as_batch(A)
+    if L.sizes != A.sizes:
+        raise ValueError("L and A batches must have the same sizes")
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    with torch.cuda.device(A.device):
+        _check("chol_fwd_batched", lib.chol_fwd_batched(
+            PREC_F64, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
+            A.ld.data_ptr(), A.n_max, ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return A.mats
+
+
+def chol_gp_nll_batched(A, y, G, f=None, info=None, workspace=None):
+    """Per problem b, in one launch: A[b] (Sigma -> L), f[b] = sum log L_ii + |L^-1 y_b|^2 / 2 and
+    G[b] = df_b/dSigma_b (symmetric).  Returns (f, info) device tensors."""
+    lib = load_library()
+    A, G = _as_batch(A), _as_batch(G)
+    if A.sizes != G.sizes:
+        raise ValueError("A and G batches must have the same sizes")
+    yp = _vec_ptrs(y, A.sizes, A.device)
+    if f is None:
+        f = torch.empty(len(A), dtype=torch.float64, device=A.device)
+    if info is None:
+        info = torch.empty(len(A), dtype=torch.int32, device=A.device)
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    with torch.cuda.device(A.device):
+        _check("chol_gp_nll_batched", lib.chol_gp_nll_batched(
+            PREC_F64, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), yp.data_ptr(),
+            G.ptr.data_ptr(), G.ld.data_ptr(), f.data_ptr(), A.n_max, info.data_ptr(), ws.data_ptr(),
+            ws.numel(), _stream(A.device)))
+    return f, info

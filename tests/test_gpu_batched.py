@@ -1,0 +1,158 @@
+"""GPU parity of the one-launch batched forms against the FP64 oracle.
+
+Tolerance 1e-10 relative Frobenius per problem, as for the single-matrix calls (same algorithms,
+same L as the oracle for rev/fwd).  The Gaussian-process mode is checked against the oracle's loss
+and reverse sweep, and against the closed form Sigma-bar = (Sigma^-1 - a a^T)/2, a = Sigma^-1 y.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+SIZES = [1, 2, 16, 31, 64, 100, 128, 129, 200, 256, 257, 300, 384, 511, 512, 7, 130, 255]
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    import paper_1602_07527_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def dev(cg):
+    import torch
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def to_dev(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def problems(sizes, seed):
+    out = []
+    for i, n in enumerate(sizes):
+        S, rng = W.dense_spd(n, seed + 17 * i)
+        L = sla.cholesky(S, lower=True)
+        out.append({"S": S, "L": L, "Lb": W.lower_normal(n, rng), "Sd": W.sym_normal(n, rng),
+                    "y": rng.standard_normal(n),
+                    "junk": np.triu(rng.standard_normal((n, n)) * 1e3, 1)})
+    return out
+
+
+def test_factor_batched(cg, dev):
+    P = problems(SIZES, 100)
+    mats = [to_dev(p["S"] + p["junk"], dev) for p in P]
+    info = cg.chol_factor_batched(mats)
+    assert info.cpu().tolist() == [0] * len(P)
+    for p, m in zip(P, mats):
+        Lg = m.cpu().numpy()
+        Lo, _ = O.chol(p["S"])
+        assert rel(Lg, Lo) <= TOL
+        assert np.all(np.triu(Lg, 1) == 0)
+
+
+@pytest.mark.parametrize("form", ["sym", "tril"])
+def test_rev_batched(cg, dev, form):
+    P = problems(SIZES, 200)
+    Ls = [to_dev(p["L"], dev) for p in P]
+    As = [to_dev(p["Lb"] + p["junk"], dev) for p in P]
+    cg.chol_rev_batched(Ls, As, form=form)
+    for p, a in zip(P, As):
+        assert rel(a.cpu().numpy(), O.chol_rev(p["L"], p["Lb"], form)) <= TOL
+
+
+def test_fwd_batched(cg, dev):
+    P = problems(SIZES, 300)
+    Ls = [to_dev(p["L"], dev) for p in P]
+    As = [to_dev(np.tril(p["Sd"]) + p["junk"], dev) for p in P]
+    cg.chol_fwd_batched(Ls, As)
+    for p, a in zip(P, As):
+        got = a.cpu().numpy()
+        assert rel(got, O.chol_fwd(p["L"], p["Sd"])) <= TOL
+        assert np.all(np.triu(got, 1) == 0)
+
+
+def test_gp_batched(cg, dev):
+    import torch
+    P = problems(SIZES, 400)
+    As = [to_dev(p["S"], dev) for p in P]
+    Gs = [torch.empty_like(a) for a in As]
+    ys = [to_dev(p["y"], dev) for p in P]
+    f, info = cg.chol_gp_nll_batched(As, ys, Gs)
+    assert info.cpu().tolist() == [0] * len(P)
+    f = f.cpu().numpy()
+    for i, (p, g) in enumerate(zip(P, Gs)):
+        Lo, _ = O.chol(p["S"])
+        fo, Lbar = O.gp_loss_and_lbar(Lo, p["y"])
+        assert f[i] == pytest.approx(fo, rel=1e-11, abs=1e-12)
+        Gg = g.cpu().numpy()
+        assert rel(Gg, O.chol_rev(Lo, Lbar)) <= TOL
+        a = np.linalg.solve(p["S"], p["y"])
+        assert rel(Gg, 0.5 * (np.linalg.inv(p["S"]) - np.outer(a, a))) <= 1e-9
+
+
+def test_batched_info_and_isolation(cg, dev):
+    """A non-SPD problem gets its LAPACK-style info without disturbing its neighbours."""
+    sizes = [150, 40, 300]
+    P = problems(sizes, 500)
+    bad = P[1]["S"].copy()
+    bad[9, 9] = -1.0
+    mats = [to_dev(P[0]["S"], dev), to_dev(bad, dev), to_dev(P[2]["S"], dev)]
+    info = cg.chol_factor_batched(mats).cpu().tolist()
+    assert info == [0, O.chol(bad)[1], 0] and info[1] == 10
+    for k in (0, 2):
+        assert rel(mats[k].cpu().numpy(), O.chol(P[k]["S"])[0]) <= TOL
+
+
+def test_alone_equals_in_batch_bitwise(cg, dev):
+    P = problems(SIZES, 600)
+    k = SIZES.index(384)
+    alone = [to_dev(P[k]["Lb"], dev)]
+    cg.chol_rev_batched([to_dev(P[k]["L"], dev)], alone)
+    Ls = [to_dev(p["L"], dev) for p in P]
+    As = [to_dev(p["Lb"], dev) for p in P]
+    cg.chol_rev_batched(Ls, As)
+    assert np.array_equal(alone[0].cpu().numpy(), As[k].cpu().numpy())
+
+
+def test_batched_matches_single_path(cg, dev):
+    P = problems([384], 700)[0]
+    one = cg.chol_rev(to_dev(P["L"], dev), to_dev(P["Lb"], dev), nb=128).cpu().numpy()
+    As = [to_dev(P["Lb"], dev)]
+    cg.chol_rev_batched([to_dev(P["L"], dev)], As)
+    assert rel(As[0].cpu().numpy(), one) <= 1e-13
+
+
+def test_gp_batch_of_2048(cg, dev):
+    """The batched workload: 2048 matrices, n log-uniform in [16, 512], Sigma = A A^T/n + 0.1 I,
+    y ~ N(0,1); 16 sampled problems checked against the oracle and the closed form."""
+    import torch
+    case = W.batch_case()
+    As = [to_dev(S, dev) for S in case["Sigma"]]
+    Gs = [torch.empty_like(a) for a in As]
+    ys = [to_dev(y, dev) for y in case["y"]]
+    f, info = cg.chol_gp_nll_batched(As, ys, Gs)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    f = f.cpu().numpy()
+    rng = np.random.default_rng(9)
+    for i in rng.choice(len(As), size=16, replace=False):
+        S, y = case["Sigma"][i], case["y"][i]
+        Lo, _ = O.chol(S)
+        fo, Lbar = O.gp_loss_and_lbar(Lo, y)
+        assert f[i] == pytest.approx(fo, rel=1e-11)
+        assert rel(Gs[i].cpu().numpy(), O.chol_rev(Lo, Lbar)) <= TOL
+        assert rel(As[i].cpu().numpy(), Lo) <= TOL
