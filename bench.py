@@ -7,6 +7,9 @@ nugget 1e-2), built on the device from a fixed seed.  One step is the whole path
 (each preceded by a device copy of its input, since the calls work in place).  The reported value
 is chol_rev's throughput, (2/3) N^3 flops per call over the event-timed duration of the chol_rev
 calls inside the timed steps; per-call figures for all three sweeps are reported beside it.
+Each step also runs the batched form once: 2048 SPD matrices (n log-uniform in [16, 512]) through
+factor + Gaussian-process loss + reverse sweep in one launch; its solves/s and launch-time
+percentiles are reported under "batched".
 
 Output: one JSON line on stdout.  `--gpus` above 1 is refused (single-GPU build).
 """
@@ -69,6 +72,40 @@ def cpu_baseline(Sigma_dev, Lbar_dev, n_sample):
                       f"{dt:.2f} s"}
 
 
+def batched_setup(dev):
+    """The batched workload on the device: 2048 matrices, n log-uniform in [16, 512],
+    Sigma = A A^T/n + 0.1 I, y ~ N(0,1), packed back to back in one buffer (so the per-step input
+    copy is one device copy) with per-matrix row-major views."""
+    import numpy as np
+    import torch
+    import paper_1602_07527_amd as cg
+    import workloads
+    case = workloads.batch_case()
+    sizes = [int(n) for n in case["sizes"]]
+    offs = np.concatenate([[0], np.cumsum([n * n for n in sizes])])
+    host = np.empty(int(offs[-1]))
+    for i, S in enumerate(case["Sigma"]):
+        host[offs[i]:offs[i + 1]] = S.ravel()
+    master = torch.from_numpy(host).to(dev)
+    work = torch.empty_like(master)
+    grad = torch.empty_like(master)
+    views = lambda buf: [buf[offs[i]:offs[i + 1]].view(n, n) for i, n in enumerate(sizes)]
+    ys = [torch.from_numpy(y).to(dev) for y in case["y"]]
+    A, G = cg.Batch(views(work)), cg.Batch(views(grad))
+    ws = torch.empty(cg.batched_workspace_bytes(len(sizes), max(sizes)), dtype=torch.uint8, device=dev)
+    f = torch.empty(len(sizes), dtype=torch.float64, device=dev)
+    info = torch.empty(len(sizes), dtype=torch.int32, device=dev)
+    n3 = float(sum(n ** 3 for n in sizes))
+    n2 = float(sum(n * n for n in sizes))
+    return {"master": master, "work": work, "A": A, "G": G, "ys": ys, "ws": ws, "f": f, "info": info,
+            "batch": len(sizes), "flops": n3 / 3.0 + 2.0 / 3.0 * n3, "bytes": 2.0 * 8.0 * n2}
+
+
+def batched_run(cg, b):
+    b["work"].copy_(b["master"])
+    cg.chol_gp_nll_batched(b["A"], b["ys"], b["G"], f=b["f"], info=b["info"], workspace=b["ws"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +113,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--batch-launches", type=int, default=50,
+                    help="timed launches of the batched path for its latency percentiles")
     ap.add_argument("--cpu-sample", type=int, default=10240,
                     help="leading-block size for the CPU oracle baseline (0 skips it)")
     args = ap.parse_args()
@@ -100,8 +139,10 @@ def main():
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     ws_bytes = max(cg.workspace_bytes(op, n, nb) for op in ("factor", "rev", "fwd"))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d")}
-    times = {"f": 0.0, "r": 0.0, "d": 0.0}
+    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d", "b")}
+    times = {"f": 0.0, "r": 0.0, "d": 0.0, "b": 0.0}
+    log("[bench] building the batched workload (2048 matrices)")
+    bat = batched_setup(dev)
 
     def step(record):
         A.copy_(Sigma)
@@ -116,6 +157,10 @@ def main():
         if record: ev["d"][0].record()
         cg.chol_fwd(A, Ad, nb=nb, workspace=ws)
         if record: ev["d"][1].record()
+        bat["work"].copy_(bat["master"])
+        if record: ev["b"][0].record()
+        cg.chol_gp_nll_batched(bat["A"], bat["ys"], bat["G"], f=bat["f"], info=bat["info"], workspace=bat["ws"])
+        if record: ev["b"][1].record()
 
     for i in range(args.warmup):
         step(False)
@@ -140,6 +185,29 @@ def main():
         raise RuntimeError(f"chol_factor reported info={int(info.item())}")
     if not bool(torch.isfinite(Ab).all()) or not bool(torch.isfinite(Ad).all()):
         raise RuntimeError("non-finite result")
+    if int((bat["info"] != 0).sum()) != 0 or not bool(torch.isfinite(bat["f"]).all()):
+        raise RuntimeError("batched factorisation failed")
+
+    # Launch-time distribution of the one-launch batched path (factor + loss + reverse sweep).
+    import numpy as np
+    lat = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.batch_launches):
+        bat["work"].copy_(bat["master"])
+        e0.record()
+        cg.chol_gp_nll_batched(bat["A"], bat["ys"], bat["G"], f=bat["f"], info=bat["info"], workspace=bat["ws"])
+        e1.record()
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
+    batched = {"workload": "2048 SPD matrices, n log-uniform in [16, 512], A A^T/n + 0.1 I; one launch = "
+                           "factor + GP loss + chol_rev per matrix (chol_gp_nll_batched)",
+               "launches": int(len(lat)), "ms_p50": round(float(np.percentile(lat, 50)), 3),
+               "ms_p99": round(float(np.percentile(lat, 99)), 3),
+               "solves_per_s": round(bat["batch"] / (float(np.percentile(lat, 50)) * 1e-3), 1),
+               "tflops": round(bat["flops"] / (float(np.percentile(lat, 50)) * 1e-3) / 1e12, 3),
+               "gbps_algorithmic": round(bat["bytes"] / (float(np.percentile(lat, 50)) * 1e-3) / 1e9, 1),
+               "in_step_ms": None}
 
     K = args.steps
     ms_step = (t1 - t0) * 1e3 / K
@@ -148,6 +216,7 @@ def main():
     rev_ms = times["r"] / K
     fac_ms = times["f"] / K
     fwd_ms = times["d"] / K
+    batched["in_step_ms"] = round(times["b"] / K, 3)
     rev_tflops = f_rev / (rev_ms * 1e-3) / 1e12
 
     k_ms, k_flops, k_launch = prof["rev"]
@@ -175,6 +244,7 @@ def main():
         "chol_factor_tflops": round(f_fac / (fac_ms * 1e-3) / 1e12, 3),
         "chol_fwd_tflops": round(f_rev / (fwd_ms * 1e-3) / 1e12, 3),
         "roofline": roofline,
+        "batched": batched,
     }
     if args.cpu_sample > 0:
         log(f"[bench] timing the CPU oracle on a {args.cpu_sample} sample")
