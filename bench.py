@@ -12,7 +12,15 @@ factor + Gaussian-process loss + reverse sweep in one launch; its solves/s and l
 percentiles are reported under "batched".
 
 Output: one JSON line on stdout.  `--gpus` above 1 is refused (single-GPU build).
+
+HBM traffic of the dominant kernel: run this script twice under `rocprofv3 --pmc FETCH_SIZE` and
+`--pmc WRITE_SIZE` with `--steps 1 --warmup 0 --cpu-sample 0 --batch-launches 0
+--calibration-mib 1024` (the calibration is one plain elementwise copy, torch.neg, of a known
+size, whose counters give the scale factor), then `--ingest-pmc FETCH.csv WRITE.csv
+--calibration-mib 1024` writes the per-launch record that later runs report as roofline.traffic
+while the kernel source is unchanged.
 """
+import csv
 import argparse
 import hashlib
 import json
@@ -45,6 +53,49 @@ def traffic_for(kernel_hash):
     if rec.get("kernel_source_sha256") != kernel_hash:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+TARGET_KERNEL = "gemm_f64_dma_kernel<false, false, 1>"
+CALIBRATION_KERNEL = "neg_kernel"
+
+
+def _pmc_rows(path, counter):
+    """(kernel name, grid size, value) per dispatch of a rocprofv3 counter_collection.csv."""
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            rows.append((r["Kernel_Name"], int(float(r.get("Grid_Size", 0) or 0)), float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"{path}: no {counter} rows")
+    return rows
+
+
+def ingest_pmc(fetch_csv, write_csv, calibration_mib):
+    """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for the calibration copy
+    of known size and record the per-launch HBM bytes of the reverse-sweep contraction."""
+    known = calibration_mib * 2 ** 20
+    rec = {"kernel": TARGET_KERNEL, "kernel_source_sha256": hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest(),
+           "calibration": f"torch.neg of {calibration_mib} MiB float64 (reads and writes {known} bytes)"}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _pmc_rows(path, counter)
+        cal = [v for k, g, v in rows if CALIBRATION_KERNEL in k]
+        tgt = [v for k, g, v in rows if TARGET_KERNEL in k]
+        if not cal or not tgt:
+            raise SystemExit(f"{path}: calibration ({len(cal)}) or target ({len(tgt)}) dispatches missing")
+        factor = known / (max(cal) * 1024.0)
+        per[counter] = {"launches": len(tgt), "raw_kib_per_launch": sum(tgt) / len(tgt),
+                        "calibration_raw_kib": max(cal), "scale": factor,
+                        "bytes_per_launch": factor * 1024.0 * sum(tgt) / len(tgt)}
+    rec["counters"] = per
+    rec["hbm_bytes_per_launch"] = per["FETCH_SIZE"]["bytes_per_launch"] + per["WRITE_SIZE"]["bytes_per_launch"]
+    os.makedirs(os.path.dirname(TRAFFIC_RECORD), exist_ok=True)
+    with open(TRAFFIC_RECORD, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(Sigma_dev, Lbar_dev, n_sample):
@@ -117,7 +168,16 @@ def main():
                     help="timed launches of the batched path for its latency percentiles")
     ap.add_argument("--cpu-sample", type=int, default=10240,
                     help="leading-block size for the CPU oracle baseline (0 skips it)")
+    ap.add_argument("--calibration-mib", type=int, default=0,
+                    help="run one plain elementwise copy of this size first (PMC calibration)")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc runs into the traffic record and exit")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        if args.calibration_mib <= 0:
+            raise SystemExit("--ingest-pmc needs the --calibration-mib of the profiled runs")
+        ingest_pmc(*args.ingest_pmc, args.calibration_mib)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
               file=sys.stderr)
@@ -141,6 +201,12 @@ def main():
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d", "b")}
     times = {"f": 0.0, "r": 0.0, "d": 0.0, "b": 0.0}
+    if args.calibration_mib > 0:
+        src = torch.ones(args.calibration_mib * 2 ** 17, dtype=torch.float64, device=dev)
+        torch.neg(src, out=torch.empty_like(src))
+        torch.cuda.synchronize()
+        del src
+        log(f"[bench] calibration copy of {args.calibration_mib} MiB done")
     log("[bench] building the batched workload (2048 matrices)")
     bat = batched_setup(dev)
 
@@ -199,6 +265,8 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         lat.append(e0.elapsed_time(e1))
+    if not lat:   # no separate launches asked for: fall back to the in-step batched time
+        lat = [times["b"] / args.steps]
     lat = np.array(lat)
     batched = {"workload": "2048 SPD matrices, n log-uniform in [16, 512], A A^T/n + 0.1 I; one launch = "
                            "factor + GP loss + chol_rev per matrix (chol_gp_nll_batched)",
@@ -219,7 +287,7 @@ def main():
     batched["in_step_ms"] = round(times["b"] / K, 3)
     rev_tflops = f_rev / (rev_ms * 1e-3) / 1e12
 
-    k_ms, k_flops, k_launch = prof["rev"]
+    k_ms, k_flops, k_bytes, k_launch = prof["rev"]
     achieved = k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
     kernel_hash = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
     traffic = traffic_for(kernel_hash)
@@ -228,6 +296,8 @@ def main():
                 "traffic": traffic,
                 "kernel": "gemm_f64_dma_kernel<false,false,1> (reverse-sweep panel contraction)",
                 "kernel_avg_us": round(k_ms * 1e3 / max(k_launch, 1), 2),
+                "algorithmic_bytes_per_launch": round(k_bytes / max(k_launch, 1)),
+                "algorithmic_flops_per_launch": round(k_flops / max(k_launch, 1)),
                 "launches_per_step": k_launch // K}
 
     out = {

@@ -167,12 +167,15 @@ int chol_gp_nll_batched(int precision, int batch, const int64_t *n, void *const 
  *   active or max_launches is not in [1, 2^20].
  * chol_profile_end: waits for the recorded events and returns, per sweep (index 0 chol_rev,
  *   1 chol_factor, 2 chol_fwd), the summed kernel time in ms, the summed flops of the
- *   contractions (2*M*N*K per launch) and the number of launches; then releases the events.
- *   ms, flops and launches must each point to 3 elements.  Returns 0, -1 (not active / NULL
+ *   contractions (2*M*N*K per launch), their summed algorithmic HBM bytes (8 bytes for each
+ *   element of op(A) and op(B) read once, of the accumulated-into C read once when it is read,
+ *   and of C, and of its mirrored copy when one is written, written once; split-K partial sums
+ *   are not counted) and the number of launches; then releases the events.  ms, flops, bytes
+ *   and launches must each point to 3 elements.  Returns 0, -1 (not active / NULL
  *   argument) or CHOL_ERR_HIP.  Process-global; not thread-safe.
  */
 int chol_profile_begin(int max_launches);
-int chol_profile_end(double *ms, double *flops, int64_t *launches);
+int chol_profile_end(double *ms, double *flops, double *bytes, int64_t *launches);
 
 /* Human-readable text for a status code (static storage; never NULL). */
 const char *chol_status_string(int status);

@@ -62,7 +62,7 @@ def load_library():
     lib.chol_profile_begin.argtypes = [i32]
     lib.chol_profile_begin.restype = i32
     lib.chol_profile_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_int64)]
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.chol_profile_end.restype = i32
     _lib = lib
     return lib
@@ -154,12 +154,13 @@ def profile_begin(max_launches=1 << 16):
 
 
 def profile_end():
-    """Stop and return {'rev'|'factor'|'fwd': (kernel_ms, flops, launches)}."""
+    """Stop and return {'rev'|'factor'|'fwd': (kernel_ms, flops, algorithmic_bytes, launches)}."""
     ms = (ctypes.c_double * 3)()
     fl = (ctypes.c_double * 3)()
+    by = (ctypes.c_double * 3)()
     nl = (ctypes.c_int64 * 3)()
-    _check("chol_profile_end", load_library().chol_profile_end(ms, fl, nl))
-    return {k: (ms[i], fl[i], int(nl[i])) for i, k in enumerate(("rev", "factor", "fwd"))}
+    _check("chol_profile_end", load_library().chol_profile_end(ms, fl, by, nl))
+    return {k: (ms[i], fl[i], by[i], int(nl[i])) for i, k in enumerate(("rev", "factor", "fwd"))}
 
 
 # ------------------------------------------------------------------------------------------------

@@ -33,6 +33,7 @@ struct Profile {
   std::vector<hipEvent_t> ev;   // 2 per launch
   std::vector<int> klass;
   std::vector<double> flops;
+  std::vector<double> bytes;
   int used = 0;
 };
 Profile g_prof;
@@ -178,6 +179,10 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
     if (hipEventRecord(g_prof.ev[2 * u], s) != hipSuccess) return hipErrorUnknown;
     g_prof.klass[u] = tag;
     g_prof.flops[u] = 2.0 * (double)M * (double)N * (double)K;
+    // Algorithmic HBM bytes of the contraction: read op(A), op(B) and Cin once, write C (and
+    // its mirror) once; split-K partials are not counted.
+    const double mn = (double)M * (double)N * (lower_only ? 0.5 : 1.0);
+    g_prof.bytes[u] = 8.0 * ((double)M * K + (double)K * N + mn * ((beta != 0.0 ? 2.0 : 1.0) + (Cm ? 1.0 : 0.0)));
   }
   launch_gemm(at, bt, fast, tag, grid, p, s);
   if (timed) {
@@ -267,17 +272,18 @@ int chol_profile_begin(int max_launches) {
     if (hipEventCreate(&e) != hipSuccess) return CHOL_ERR_HIP;
   g_prof.klass.assign(max_launches, 0);
   g_prof.flops.assign(max_launches, 0.0);
+  g_prof.bytes.assign(max_launches, 0.0);
   g_prof.cap = max_launches;
   g_prof.used = 0;
   g_prof.on = true;
   return CHOL_SUCCESS;
 }
 
-int chol_profile_end(double *ms, double *flops, int64_t *launches) {
+int chol_profile_end(double *ms, double *flops, double *bytes, int64_t *launches) {
   if (!g_prof.on) return -1;
-  if (!ms || !flops || !launches) return -1;
+  if (!ms || !flops || !bytes || !launches) return -1;
   int rc = CHOL_SUCCESS;
-  for (int c = 0; c < 3; ++c) { ms[c] = 0.0; flops[c] = 0.0; launches[c] = 0; }
+  for (int c = 0; c < 3; ++c) { ms[c] = 0.0; flops[c] = 0.0; bytes[c] = 0.0; launches[c] = 0; }
   for (int u = 0; u < g_prof.used; ++u) {
     float t = 0.0f;
     if (hipEventSynchronize(g_prof.ev[2 * u + 1]) != hipSuccess ||
@@ -289,6 +295,7 @@ int chol_profile_end(double *ms, double *flops, int64_t *launches) {
     if (c < 0 || c > 2) continue;
     ms[c] += t;
     flops[c] += g_prof.flops[u];
+    bytes[c] += g_prof.bytes[u];
     launches[c] += 1;
   }
   for (auto &e : g_prof.ev)

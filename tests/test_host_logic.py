@@ -1,0 +1,52 @@
+"""Host-side logic that needs no GPU: the autograd module's surface, the benchmark's refusal of more
+than one GPU, and the PMC-record ingestion on synthetic counter files."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_autograd_module_surface():
+    from paper_1602_07527_amd import autograd
+    for name in ("cholesky", "cholesky_ex", "cholesky_batched", "gp_neg_log_lik"):
+        assert callable(getattr(autograd, name))
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _write_counters(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name",
+                                          "Counter_Value"])
+        w.writeheader()
+        for i, (k, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Grid_Size": 1024, "Kernel_Name": k, "Counter_Name": counter,
+                        "Counter_Value": v})
+
+
+def test_ingest_pmc_scales_by_the_calibration_copy(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(tmp_path / "rec.json"))
+    tgt = "void cg::gemm_f64_dma_kernel<false, false, 1>(cg::GemmArgs)"
+    cal = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(...)>"
+    # The calibration copy of 64 MiB reads as 32768 KiB: every raw value is half the truth.
+    _write_counters(tmp_path / "f.csv", "FETCH_SIZE",
+                    [(cal, 32768.0), (tgt, 100.0), (tgt, 300.0), ("other", 1e9)])
+    _write_counters(tmp_path / "w.csv", "WRITE_SIZE", [(cal, 16384.0), (tgt, 50.0)])
+    bench.ingest_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 64)
+    rec = json.load(open(tmp_path / "rec.json"))
+    assert rec["counters"]["FETCH_SIZE"]["scale"] == pytest.approx(2.0)
+    assert rec["counters"]["WRITE_SIZE"]["scale"] == pytest.approx(4.0)
+    assert rec["hbm_bytes_per_launch"] == pytest.approx(2.0 * 200 * 1024 + 4.0 * 50 * 1024)
+    assert bench.traffic_for(rec["kernel_source_sha256"]) == pytest.approx(rec["hbm_bytes_per_launch"])
+    assert bench.traffic_for("0" * 64) is None
