@@ -9,7 +9,8 @@ is chol_rev's throughput, (2/3) N^3 flops per call over the event-timed duration
 calls inside the timed steps; per-call figures for all three sweeps are reported beside it.
 Each step also runs the batched form once: 2048 SPD matrices (n log-uniform in [16, 512]) through
 factor + Gaussian-process loss + reverse sweep in one launch; its solves/s and launch-time
-percentiles are reported under "batched".
+percentiles are reported under "batched", and those of the same matrices in FP32 storage under
+"batched_f32".
 
 Output: one JSON line on stdout.  `--gpus` above 1 is refused (single-GPU build).
 
@@ -123,10 +124,10 @@ def cpu_baseline(Sigma_dev, Lbar_dev, n_sample):
                       f"{dt:.2f} s"}
 
 
-def batched_setup(dev):
+def batched_setup(dev, dtype=None):
     """The batched workload on the device: 2048 matrices, n log-uniform in [16, 512],
     Sigma = A A^T/n + 0.1 I, y ~ N(0,1), packed back to back in one buffer (so the per-step input
-    copy is one device copy) with per-matrix row-major views."""
+    copy is one device copy) with per-matrix row-major views; float64, or float32 storage."""
     import numpy as np
     import torch
     import paper_1602_07527_amd as cg
@@ -137,19 +138,20 @@ def batched_setup(dev):
     host = np.empty(int(offs[-1]))
     for i, S in enumerate(case["Sigma"]):
         host[offs[i]:offs[i + 1]] = S.ravel()
-    master = torch.from_numpy(host).to(dev)
+    dtype = dtype or torch.float64
+    master = torch.from_numpy(host).to(dev).to(dtype)
     work = torch.empty_like(master)
     grad = torch.empty_like(master)
     views = lambda buf: [buf[offs[i]:offs[i + 1]].view(n, n) for i, n in enumerate(sizes)]
-    ys = [torch.from_numpy(y).to(dev) for y in case["y"]]
+    ys = [torch.from_numpy(y).to(dev).to(dtype) for y in case["y"]]
     A, G = cg.Batch(views(work)), cg.Batch(views(grad))
-    ws = torch.empty(cg.batched_workspace_bytes(len(sizes), max(sizes)), dtype=torch.uint8, device=dev)
-    f = torch.empty(len(sizes), dtype=torch.float64, device=dev)
+    ws = torch.empty(cg.batched_workspace_bytes(len(sizes), max(sizes), A.prec), dtype=torch.uint8, device=dev)
+    f = torch.empty(len(sizes), dtype=dtype, device=dev)
     info = torch.empty(len(sizes), dtype=torch.int32, device=dev)
     n3 = float(sum(n ** 3 for n in sizes))
     n2 = float(sum(n * n for n in sizes))
     return {"master": master, "work": work, "A": A, "G": G, "ys": ys, "ws": ws, "f": f, "info": info,
-            "batch": len(sizes), "flops": n3 / 3.0 + 2.0 / 3.0 * n3, "bytes": 2.0 * 8.0 * n2}
+            "batch": len(sizes), "flops": n3 / 3.0 + 2.0 / 3.0 * n3, "bytes": 2.0 * master.element_size() * n2}
 
 
 def batched_run(cg, b):
@@ -254,28 +256,44 @@ def main():
     if int((bat["info"] != 0).sum()) != 0 or not bool(torch.isfinite(bat["f"]).all()):
         raise RuntimeError("batched factorisation failed")
 
-    # Launch-time distribution of the one-launch batched path (factor + loss + reverse sweep).
+    # Launch-time distribution of the one-launch batched path (factor + loss + reverse sweep), for
+    # FP64 storage (the bench workload) and FP32 storage of the same matrices.
     import numpy as np
-    lat = []
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(args.batch_launches):
-        bat["work"].copy_(bat["master"])
-        e0.record()
-        cg.chol_gp_nll_batched(bat["A"], bat["ys"], bat["G"], f=bat["f"], info=bat["info"], workspace=bat["ws"])
-        e1.record()
-        torch.cuda.synchronize()
-        lat.append(e0.elapsed_time(e1))
-    if not lat:   # no separate launches asked for: fall back to the in-step batched time
-        lat = [times["b"] / args.steps]
-    lat = np.array(lat)
-    batched = {"workload": "2048 SPD matrices, n log-uniform in [16, 512], A A^T/n + 0.1 I; one launch = "
-                           "factor + GP loss + chol_rev per matrix (chol_gp_nll_batched)",
-               "launches": int(len(lat)), "ms_p50": round(float(np.percentile(lat, 50)), 3),
-               "ms_p99": round(float(np.percentile(lat, 99)), 3),
-               "solves_per_s": round(bat["batch"] / (float(np.percentile(lat, 50)) * 1e-3), 1),
-               "tflops": round(bat["flops"] / (float(np.percentile(lat, 50)) * 1e-3) / 1e12, 3),
-               "gbps_algorithmic": round(bat["bytes"] / (float(np.percentile(lat, 50)) * 1e-3) / 1e9, 1),
-               "in_step_ms": None}
+
+    def launch_times(b, launches):
+        lat = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(launches):
+            b["work"].copy_(b["master"])
+            e0.record()
+            cg.chol_gp_nll_batched(b["A"], b["ys"], b["G"], f=b["f"], info=b["info"], workspace=b["ws"])
+            e1.record()
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        if int((b["info"] != 0).sum()) != 0 or not bool(torch.isfinite(b["f"]).all()):
+            raise RuntimeError("batched factorisation failed")
+        return np.array(lat)
+
+    def batched_summary(b, lat, storage):
+        p50 = float(np.percentile(lat, 50))
+        return {"workload": f"2048 SPD matrices, n log-uniform in [16, 512], A A^T/n + 0.1 I, {storage} "
+                            "storage; one launch = factor + GP loss + chol_rev per matrix (chol_gp_nll_batched)",
+                "launches": int(len(lat)), "ms_p50": round(p50, 3),
+                "ms_p99": round(float(np.percentile(lat, 99)), 3),
+                "solves_per_s": round(b["batch"] / (p50 * 1e-3), 1),
+                "tflops": round(b["flops"] / (p50 * 1e-3) / 1e12, 3),
+                "gbps_algorithmic": round(b["bytes"] / (p50 * 1e-3) / 1e9, 1)}
+
+    lat = launch_times(bat, args.batch_launches) if args.batch_launches > 0 else \
+        np.array([times["b"] / args.steps])   # no separate launches: the in-step time
+    batched = batched_summary(bat, lat, "FP64")
+    batched["in_step_ms"] = round(times["b"] / args.steps, 3)
+    batched_f32 = None
+    if args.batch_launches > 0:
+        log("[bench] FP32-storage batched launches")
+        bat32 = batched_setup(dev, torch.float32)
+        batched_f32 = batched_summary(bat32, launch_times(bat32, args.batch_launches), "FP32")
+        del bat32
 
     K = args.steps
     ms_step = (t1 - t0) * 1e3 / K
@@ -284,7 +302,6 @@ def main():
     rev_ms = times["r"] / K
     fac_ms = times["f"] / K
     fwd_ms = times["d"] / K
-    batched["in_step_ms"] = round(times["b"] / K, 3)
     rev_tflops = f_rev / (rev_ms * 1e-3) / 1e12
 
     k_ms, k_flops, k_bytes, k_launch = prof["rev"]
@@ -315,6 +332,7 @@ def main():
         "chol_fwd_tflops": round(f_rev / (fwd_ms * 1e-3) / 1e12, 3),
         "roofline": roofline,
         "batched": batched,
+        "batched_f32": batched_f32,
     }
     if args.cpu_sample > 0:
         log(f"[bench] timing the CPU oracle on a {args.cpu_sample} sample")

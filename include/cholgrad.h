@@ -11,7 +11,8 @@
  *
  * Conventions for every entry point
  *   - Matrices are DEVICE pointers, row-major: element (i, j) of an n x n matrix lives at
- *     A[i * ld + j], with ld >= max(1, n).  Storage type is double for the CHOL_PREC_F64* modes.
+ *     A[i * ld + j], with ld >= max(1, n).  Storage type is double for the CHOL_PREC_F64* modes
+ *     and float for CHOL_PREC_F32.
  *   - Only the lower triangle (i >= j) of each input matrix is read (Sec. 4.1: the algorithms only
  *     inspect the lower triangle).  Sigma-dot is symmetric; its lower triangle defines it (Sec. 3).
  *   - Outputs overwrite the array in place, as the paper's algorithms do.  The strict upper
@@ -49,8 +50,15 @@ extern "C" {
 #define CHOL_ERR_WORKSPACE (-102)    /* workspace NULL, too small, or not 256-byte aligned    */
 #define CHOL_ERR_UNSUPPORTED (-103)  /* precision / form / size combination not implemented */
 
-/* Arithmetic of the call.  Storage is double for all CHOL_PREC_F64* modes. */
-#define CHOL_PREC_F64 0              /* every step in FP64 (FP64 MFMA for the contractions)   */
+/* Precision of the call.
+ *   CHOL_PREC_F64 : double storage; every step in FP64 (FP64 MFMA for the contractions).
+ *   CHOL_PREC_F32 : float storage (matrices, vectors and losses), batched calls only; each
+ *                   problem's lower triangle is widened to FP64 in the workspace, computed exactly
+ *                   as in CHOL_PREC_F64 and rounded to float once on output, so the result is the
+ *                   FP64 result for the float input to within float rounding.  Single-matrix
+ *                   calls return CHOL_ERR_UNSUPPORTED for it. */
+#define CHOL_PREC_F64 0
+#define CHOL_PREC_F32 1
 
 /* Which reverse-mode output (Sec. 3, eqns (symrev) and (symrevtril); S = L^-T Phi(L^T Lbar) L^-1):
  *   CHOL_SBAR_SYM  : (S + S^T)/2 in both triangles -- the symmetric gradient, for which
@@ -115,11 +123,13 @@ int chol_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int6
  * per problem, nb = 128; a problem with n <= 128 is one diagonal block and stays in LDS).  All
  * per-problem arguments are DEVICE arrays with `batch` entries: n[b] is the size of problem b,
  * A[b] (and L[b], y[b], G[b]) are device pointers to its row-major data with leading dimensions
- * lda[b] (ldl[b], ldg[b]) >= n[b].  n_max (host value, <= 512) bounds every n[b]; sizes above 512
- * return CHOL_ERR_UNSUPPORTED.  A problem whose size is outside [0, 512] or whose leading
+ * lda[b] (ldl[b], ldg[b]) >= n[b].  n_max (host value, <= 512) bounds every n[b]; n_max above 512
+ * returns CHOL_ERR_UNSUPPORTED.  A problem whose size is outside [0, n_max] or whose leading
  * dimension is smaller than its size is skipped (its info entry, where there is one, becomes -1).
  * Problems are processed largest first; each problem's result does not depend on the batch it is
- * in.  Workspace: chol_batched_workspace_bytes(precision, batch, n_max) bytes, 256-byte aligned.
+ * in.  Workspace: chol_batched_workspace_bytes(precision, batch, n_max) bytes, 256-byte aligned
+ * (about 300 MB; CHOL_PREC_F32 adds 16 * n_max^2 bytes of FP64 staging per workgroup, for at
+ * most 256 workgroups: 1.07 GB at n_max = 512).
  * Semantics per problem are those of the single-matrix calls above.
  */
 size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max);
@@ -147,10 +157,10 @@ int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *con
  *     f_b = sum_i log L_ii + (1/2) |L^-1 y_b|^2      (= (1/2) log det Sigma + (1/2) y^T Sigma^-1 y)
  * whose reverse-mode input is L-bar = diag(1/L_ii) - tril(w z^T), z = L^-1 y, w = L^-T z:
  *   A[b]   in: tril = Sigma_b.  out: L_b (strict upper set to 0).
- *   y[b]   in: n[b] doubles.
+ *   y[b]   in: n[b] values (double, or float for CHOL_PREC_F32).
  *   G[b]   out: Sigma-bar_b = df_b/dSigma_b, the symmetric gradient in both triangles
  *          (= (Sigma^-1 - a a^T)/2 with a = Sigma^-1 y).
- *   f      out: device array of batch doubles.
+ *   f      out: device array of batch values (double, or float for CHOL_PREC_F32).
  *   info   out: device array of batch ints (LAPACK convention; f = NaN and G untouched when > 0).
  *   Arguments: 1 precision, 2 batch, 3 n, 4 A, 5 lda, 6 y, 7 G, 8 ldg, 9 f, 10 n_max, 11 info,
  *              12 workspace, 13 workspace_bytes, 14 stream.

@@ -13,6 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libcholgrad.so")
 
 PREC_F64 = 0
+PREC_F32 = 1
 SBAR_SYM, SBAR_TRIL = 0, 1
 OP_FACTOR, OP_REV, OP_FWD = 0, 1, 2
 _FORMS = {"sym": SBAR_SYM, "tril": SBAR_TRIL}
@@ -74,11 +75,11 @@ def _check(fn, status):
         raise CholError(fn, status, lib.chol_status_string(status).decode())
 
 
-def _square(name, t):
+def _square(name, t, dtypes=(torch.float64,)):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
-    if t.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must be {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
     if t.dim() != 2 or t.shape[0] != t.shape[1]:
         raise ValueError(f"{name} must be square 2-D, got {tuple(t.shape)}")
     n = t.shape[0]
@@ -169,19 +170,27 @@ def profile_end():
 BATCH_NMAX = 512
 
 
+_BATCH_PREC = {torch.float64: PREC_F64, torch.float32: PREC_F32}
+
+
 class Batch:
-    """Device-side description of a list of square float64 matrices (sizes, pointers, leading
-    dimensions), built once and reusable across calls on the same tensors."""
+    """Device-side description of a list of square matrices (sizes, pointers, leading dimensions),
+    built once and reusable across calls on the same tensors.  All matrices share one dtype:
+    float64 (FP64) or float32 (FP32 storage, computed in FP64 inside the library)."""
 
     def __init__(self, mats):
         if len(mats) == 0:
             raise ValueError("empty batch")
         dev = mats[0].device
+        self.dtype = mats[0].dtype
+        if self.dtype not in _BATCH_PREC:
+            raise TypeError(f"batched calls take float64 or float32 matrices, got {self.dtype}")
+        self.prec = _BATCH_PREC[self.dtype]
         sizes, ptrs, lds = [], [], []
         for t in mats:
             if t.device != dev:
                 raise ValueError("all matrices of a batch must be on one device")
-            n = _square("batch matrix", t)
+            n = _square("batch matrix", t, (self.dtype,))
             sizes.append(n)
             ptrs.append(t.data_ptr())
             lds.append(t.stride(0) if n else 1)
@@ -199,20 +208,22 @@ class Batch:
         return len(self.sizes)
 
 
-def _vec_ptrs(vecs, sizes, dev):
+def _vec_ptrs(vecs, sizes, dev, dtype):
+    if len(vecs) != len(sizes):
+        raise ValueError("one vector per matrix")
     for v, n in zip(vecs, sizes):
-        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == dtype and v.is_contiguous()
                 and v.numel() == n and v.device == dev):
-            raise ValueError("vectors must be contiguous float64 device tensors matching the sizes")
+            raise ValueError(f"vectors must be contiguous {dtype} device tensors matching the sizes")
     return torch.tensor([v.data_ptr() for v in vecs], dtype=torch.int64).to(dev)
 
 
-def batched_workspace_bytes(batch, n_max):
-    return int(load_library().chol_batched_workspace_bytes(PREC_F64, int(batch), int(n_max)))
+def batched_workspace_bytes(batch, n_max, prec=PREC_F64):
+    return int(load_library().chol_batched_workspace_bytes(int(prec), int(batch), int(n_max)))
 
 
-def _batch_ws(batch, n_max, device, workspace):
-    need = batched_workspace_bytes(batch, n_max)
+def _batch_ws(batch, n_max, device, workspace, prec=PREC_F64):
+    need = batched_workspace_bytes(batch, n_max, prec)
     if workspace is None:
         return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
     if workspace.numel() * workspace.element_size() < need:
@@ -231,10 +242,10 @@ def chol_factor_batched(A, info=None, workspace=None):
     A = _as_batch(A)
     if info is None:
         info = torch.empty(len(A), dtype=torch.int32, device=A.device)
-    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace, A.prec)
     with torch.cuda.device(A.device):
         _check("chol_factor_batched", lib.chol_factor_batched(
-            PREC_F64, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), A.n_max, info.data_ptr(),
+            A.prec, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), A.n_max, info.data_ptr(),
             ws.data_ptr(), ws.numel(), _stream(A.device)))
     return info
 
@@ -243,12 +254,12 @@ def chol_rev_batched(L, A, form="sym", workspace=None):
     """In place on every A[b]: tril = L-bar -> Sigma-bar (form 'sym' or 'tril')."""
     lib = load_library()
     L, A = _as_batch(L), _as_batch(A)
-    if L.sizes != A.sizes:
-        raise ValueError("L and A batches must have the same sizes")
-    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    if L.sizes != A.sizes or L.dtype != A.dtype or L.device != A.device:
+        raise ValueError("L and A batches must have the same sizes, dtype and device")
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace, A.prec)
     with torch.cuda.device(A.device):
         _check("chol_rev_batched", lib.chol_rev_batched(
-            PREC_F64, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
+            A.prec, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
             A.ld.data_ptr(), A.n_max, _FORMS[form], ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A.mats
 
@@ -257,12 +268,12 @@ def chol_fwd_batched(L, A, workspace=None):
     """In place on every A[b]: tril = tril(Sigma-dot) -> L-dot (strict upper 0)."""
     lib = load_library()
     L, A = _as_batch(L), _as_batch(A)
-    if L.sizes != A.sizes:
-        raise ValueError("L and A batches must have the same sizes")
-    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    if L.sizes != A.sizes or L.dtype != A.dtype or L.device != A.device:
+        raise ValueError("L and A batches must have the same sizes, dtype and device")
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace, A.prec)
     with torch.cuda.device(A.device):
         _check("chol_fwd_batched", lib.chol_fwd_batched(
-            PREC_F64, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
+            A.prec, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
             A.ld.data_ptr(), A.n_max, ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A.mats
 
@@ -272,17 +283,19 @@ def chol_gp_nll_batched(A, y, G, f=None, info=None, workspace=None):
     G[b] = df_b/dSigma_b (symmetric).  Returns (f, info) device tensors."""
     lib = load_library()
     A, G = _as_batch(A), _as_batch(G)
-    if A.sizes != G.sizes:
-        raise ValueError("A and G batches must have the same sizes")
-    yp = _vec_ptrs(y, A.sizes, A.device)
+    if A.sizes != G.sizes or A.dtype != G.dtype or A.device != G.device:
+        raise ValueError("A and G batches must have the same sizes, dtype and device")
+    yp = _vec_ptrs(y, A.sizes, A.device, A.dtype)
     if f is None:
-        f = torch.empty(len(A), dtype=torch.float64, device=A.device)
+        f = torch.empty(len(A), dtype=A.dtype, device=A.device)
+    elif f.dtype != A.dtype or f.numel() < len(A) or not f.is_contiguous() or f.device != A.device:
+        raise ValueError(f"f must be a contiguous {A.dtype} device tensor with one entry per problem")
     if info is None:
         info = torch.empty(len(A), dtype=torch.int32, device=A.device)
-    ws = _batch_ws(len(A), A.n_max, A.device, workspace)
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace, A.prec)
     with torch.cuda.device(A.device):
         _check("chol_gp_nll_batched", lib.chol_gp_nll_batched(
-            PREC_F64, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), yp.data_ptr(),
+            A.prec, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), yp.data_ptr(),
             G.ptr.data_ptr(), G.ld.data_ptr(), f.data_ptr(), A.n_max, info.data_ptr(), ws.data_ptr(),
             ws.numel(), _stream(A.device)))
     return f, info

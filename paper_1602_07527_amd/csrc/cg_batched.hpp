@@ -49,7 +49,17 @@ struct BatchArgs {
   const int *order;         // processing order (largest first)
   int *counter;             // work counter, zero at launch
   double *slots;            // gridDim.x * SLOT_DOUBLES
+  int n_max;                // bound on every size (host value); larger problems are skipped
+  int f32;                  // FP32 storage: matrices, vectors and losses are float
+  double *stage;            // FP32 storage: gridDim.x * stage_stride doubles of FP64 staging
+  int64_t stage_stride;
 };
+
+// Doubles of FP64 staging one workgroup needs for FP32 storage at sizes up to n_max: two n x n
+// matrices, one vector and the loss, rounded up to whole 256-byte lines.
+__host__ __device__ constexpr int64_t stage_doubles(int64_t n_max) {
+  return (2 * n_max * n_max + n_max + 1 + 31) / 32 * 32;
+}
 
 // Out-of-line entry points to the diagonal-block routines for the batched kernels (the single-
 // matrix kernels inline them).
@@ -83,6 +93,25 @@ __device__ __noinline__ void wg_gemm(int M, int N, int K, const double *A, int64
   p.Cm = Cm; p.ldcm = ldcm; p.kchunk = K; p.split_stride = 0; p.lower_only = 0;
   for (int m0 = 0; m0 < M; m0 += GEMM_BM)
     for (int n0 = 0; n0 < N; n0 += GEMM_BN) gemm_tile<AT, BT>(p, m0, n0, 0, K, C, lds);
+}
+
+// FP32 storage: the lower triangle of a float input is widened into a compact FP64 copy (leading
+// dimension n, strict upper 0), the problem is computed exactly as in FP64, and each output is
+// rounded to float once at the end.
+__device__ void stage_in_lower(int n, const float *src, int64_t ld, double *dst) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e - r * n;
+    dst[e] = (c <= r) ? (double)src[(int64_t)r * ld + c] : 0.0;
+  }
+  __syncthreads();
+}
+
+__device__ void stage_out(int n, const double *src, float *dst, int64_t ld) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e - r * n;
+    dst[(int64_t)r * ld + c] = (float)src[e];
+  }
+  __syncthreads();
 }
 
 __device__ void wg_zero_upper(int n, double *A, int64_t lda) {
@@ -279,14 +308,16 @@ __global__ __launch_bounds__(256) void batch_order_kernel(int batch, const int64
 }
 
 // The persistent kernel.  Every workgroup loops until the counter passes the batch, so all waves
-// reach the same exit.  A problem with an invalid size or leading dimension is skipped (its info,
-// when there is one, is set to -1).
+// reach the same exit.  A problem with a size outside [0, n_max] or a leading dimension below its
+// size is skipped (its info, when there is one, is set to -1); n_max <= BATCH_NMAX keeps every
+// slot and staging access inside the workgroup's own region.
 template <int OP>
 __global__ __launch_bounds__(DIAG_THREADS) void batch_kernel(BatchArgs a) {
   __shared__ double lds[BATCH_LDS];
   __shared__ int item;
   __shared__ int bad;
   double *slot = a.slots + (int64_t)blockIdx.x * SLOT_DOUBLES;
+  double *stage = a.f32 ? a.stage + (int64_t)blockIdx.x * a.stage_stride : nullptr;
   for (;;) {
     if (threadIdx.x == 0) item = atomicAdd(a.counter, 1);
     __syncthreads();
@@ -296,7 +327,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void batch_kernel(BatchArgs a) {
     const int b = a.order[it];
     const int64_t n64 = a.n[b];
     const bool has_info = (OP == BATCH_FACTOR || OP == BATCH_GP);
-    if (n64 < 0 || n64 > BATCH_NMAX || a.lda[b] < n64 ||
+    if (n64 < 0 || n64 > a.n_max || a.lda[b] < n64 ||
         ((OP == BATCH_REV || OP == BATCH_FWD) && a.ldl[b] < n64) || (OP == BATCH_GP && a.ldg[b] < n64)) {
       if (has_info && threadIdx.x == 0) a.info[b] = -1;
       continue;
@@ -304,11 +335,23 @@ __global__ __launch_bounds__(DIAG_THREADS) void batch_kernel(BatchArgs a) {
     const int n = (int)n64;
     if (n == 0) {
       if (has_info && threadIdx.x == 0) a.info[b] = 0;
-      if (OP == BATCH_GP && threadIdx.x == 0) a.f[b] = 0.0;
+      if (OP == BATCH_GP && threadIdx.x == 0) {
+        if (a.f32) reinterpret_cast<float *>(a.f)[b] = 0.0f;
+        else a.f[b] = 0.0;
+      }
       continue;
     }
+    // Working copies: the caller's arrays for FP64 storage, the staging area for FP32 storage.
+    double *const st2 = a.f32 ? stage + (int64_t)n * n : nullptr;      // second matrix (L or G)
+    double *const sty = a.f32 ? stage + 2 * (int64_t)n * n : nullptr;  // y
+    double *const stf = a.f32 ? sty + n : nullptr;                      // loss
     double *A = a.A[b];
-    const int64_t lda = a.lda[b];
+    int64_t lda = a.lda[b];
+    if (a.f32) {
+      stage_in_lower(n, reinterpret_cast<const float *>(a.A[b]), a.lda[b], stage);
+      A = stage;
+      lda = n;
+    }
     if (OP == BATCH_FACTOR || OP == BATCH_GP) {
       if (threadIdx.x == 0) a.info[b] = 0;
       __syncthreads();
@@ -317,19 +360,42 @@ __global__ __launch_bounds__(DIAG_THREADS) void batch_kernel(BatchArgs a) {
         const int inf = a.info[b];
         __syncthreads();
         if (inf != 0) {  // not positive definite: no loss or gradient
-          if (threadIdx.x == 0) a.f[b] = __builtin_nan("");
-          continue;
+          if (threadIdx.x == 0) {
+            if (a.f32) reinterpret_cast<float *>(a.f)[b] = __builtin_nanf("");
+            else a.f[b] = __builtin_nan("");
+          }
+        } else {
+          const double *y = a.y[b];
+          double *G = a.G[b];
+          int64_t ldg = a.ldg[b];
+          double *fo = &a.f[b];
+          if (a.f32) {
+            const float *yf = reinterpret_cast<const float *>(a.y[b]);
+            for (int i = threadIdx.x; i < n; i += blockDim.x) sty[i] = (double)yf[i];
+            __syncthreads();
+            y = sty; G = st2; ldg = n; fo = stf;
+          }
+          batch_gp_loss_one(n, A, lda, y, G, ldg, fo, slot, lds);
+          batch_rev_one(n, A, lda, G, ldg, 0, slot, lds);
+          if (a.f32) {
+            stage_out(n, st2, reinterpret_cast<float *>(a.G[b]), a.ldg[b]);
+            if (threadIdx.x == 0) reinterpret_cast<float *>(a.f)[b] = (float)*stf;
+          }
         }
-        batch_gp_loss_one(n, A, lda, a.y[b], a.G[b], a.ldg[b], &a.f[b], slot, lds);
-        batch_rev_one(n, A, lda, a.G[b], a.ldg[b], 0, slot, lds);
       }
     } else {
       const double *L = a.L[b];
-      const int64_t ldl = a.ldl[b];
+      int64_t ldl = a.ldl[b];
+      if (a.f32) {
+        stage_in_lower(n, reinterpret_cast<const float *>(a.L[b]), a.ldl[b], st2);
+        L = st2;
+        ldl = n;
+      }
       batch_block_inverses(n, L, ldl, slot, lds);
       if (OP == BATCH_REV) batch_rev_one(n, L, ldl, A, lda, a.sbar_form, slot, lds);
       else batch_fwd_one(n, L, ldl, A, lda, slot, lds);
     }
+    if (a.f32) stage_out(n, stage, reinterpret_cast<float *>(a.A[b]), a.lda[b]);
   }
 }
 

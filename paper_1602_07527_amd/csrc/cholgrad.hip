@@ -224,25 +224,32 @@ struct BatchWs {
   int *order = nullptr;
   int *counter = nullptr;
   double *slots = nullptr;
+  double *stage = nullptr;
 };
 
-size_t carve_batch(int batch, void *base, BatchWs *w) {
+// Workspace of a batched call: processing order, work counter, one slot per workgroup and, for
+// FP32 storage, one FP64 staging area per workgroup.
+size_t carve_batch(int batch, int64_t n_max, bool f32, void *base, BatchWs *w) {
   Carver c(base);
   w->order = reinterpret_cast<int *>(c.take((size_t)cdiv(batch, 2)));
   w->counter = reinterpret_cast<int *>(c.take(1));
   w->slots = c.take((size_t)BATCH_WGS * cg::SLOT_DOUBLES);
+  w->stage = f32 ? c.take((size_t)std::min(batch, BATCH_WGS) * cg::stage_doubles(n_max)) : nullptr;
   return c.off;
 }
 
 int run_batched(cg::BatchArgs a, int64_t n_max, void *workspace, size_t workspace_bytes, hipStream_t s) {
   BatchWs ws;
-  const size_t need = carve_batch(a.batch, nullptr, &ws);
+  const size_t need = carve_batch(a.batch, n_max, a.f32 != 0, nullptr, &ws);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
     return CHOL_ERR_WORKSPACE;
-  carve_batch(a.batch, workspace, &ws);
+  carve_batch(a.batch, n_max, a.f32 != 0, workspace, &ws);
   a.order = ws.order;
   a.counter = ws.counter;
   a.slots = ws.slots;
+  a.n_max = (int)n_max;
+  a.stage = ws.stage;
+  a.stage_stride = cg::stage_doubles(n_max);
   hipLaunchKernelGGL(cg::batch_order_kernel, dim3(1), dim3(256), 0, s, a.batch, a.n, (int)n_max, ws.order,
                      ws.counter);
   CG_TRY(hipGetLastError());
@@ -326,6 +333,7 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
 
 int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
+  if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   if (precision != CHOL_PREC_F64) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
   if (n == 0) return CHOL_SUCCESS;
@@ -409,6 +417,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
 
 int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *info,
                 void *workspace, size_t workspace_bytes, void *stream) {
+  if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   if (precision != CHOL_PREC_F64) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
   if (n == 0) return CHOL_SUCCESS;
@@ -471,6 +480,7 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
 
 int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream) {
+  if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   if (precision != CHOL_PREC_F64) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
   if (n == 0) return CHOL_SUCCESS;
@@ -541,14 +551,18 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
 }
 
 
+static bool batched_prec_ok(int precision) {
+  return precision == CHOL_PREC_F64 || precision == CHOL_PREC_F32;
+}
+
 size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max) {
-  if (precision != CHOL_PREC_F64 || batch <= 0 || n_max < 0 || n_max > cg::BATCH_NMAX) return 0;
+  if (!batched_prec_ok(precision) || batch <= 0 || n_max < 0 || n_max > cg::BATCH_NMAX) return 0;
   BatchWs w;
-  return carve_batch(batch, nullptr, &w);
+  return carve_batch(batch, n_max, precision == CHOL_PREC_F32, nullptr, &w);
 }
 
 static int batched_common_checks(int precision, int batch, int64_t n_max) {
-  if (precision != CHOL_PREC_F64) return -1;
+  if (!batched_prec_ok(precision)) return -1;
   if (batch < 0) return -2;
   if (n_max < 0 || n_max > cg::BATCH_NMAX) return CHOL_ERR_UNSUPPORTED;
   return CHOL_SUCCESS;
@@ -564,7 +578,7 @@ int chol_factor_batched(int precision, int batch, const int64_t *n, void *const 
   if (!lda) return -5;
   if (!info) return -7;
   cg::BatchArgs a{};
-  a.op = cg::BATCH_FACTOR; a.batch = batch; a.n = n; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
+  a.op = cg::BATCH_FACTOR; a.batch = batch; a.f32 = precision == CHOL_PREC_F32; a.n = n; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
   a.info = info;
   return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
@@ -582,7 +596,7 @@ int chol_rev_batched(int precision, int batch, const int64_t *n, const void *con
   if (!lda) return -7;
   if (sbar_form != CHOL_SBAR_SYM && sbar_form != CHOL_SBAR_TRIL) return -9;
   cg::BatchArgs a{};
-  a.op = cg::BATCH_REV; a.batch = batch; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
+  a.op = cg::BATCH_REV; a.batch = batch; a.f32 = precision == CHOL_PREC_F32; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
   a.ldl = ldl; a.A = reinterpret_cast<double *const *>(A); a.lda = lda; a.sbar_form = sbar_form;
   return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
@@ -599,7 +613,7 @@ int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *con
   if (!A) return -6;
   if (!lda) return -7;
   cg::BatchArgs a{};
-  a.op = cg::BATCH_FWD; a.batch = batch; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
+  a.op = cg::BATCH_FWD; a.batch = batch; a.f32 = precision == CHOL_PREC_F32; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
   a.ldl = ldl; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
   return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
@@ -619,7 +633,7 @@ int chol_gp_nll_batched(int precision, int batch, const int64_t *n, void *const 
   if (!f) return -9;
   if (!info) return -11;
   cg::BatchArgs a{};
-  a.op = cg::BATCH_GP; a.batch = batch; a.n = n; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
+  a.op = cg::BATCH_GP; a.batch = batch; a.f32 = precision == CHOL_PREC_F32; a.n = n; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
   a.y = reinterpret_cast<const double *const *>(y); a.G = reinterpret_cast<double *const *>(G); a.ldg = ldg;
   a.f = static_cast<double *>(f); a.info = info;
   return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));

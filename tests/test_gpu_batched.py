@@ -156,3 +156,109 @@ def test_gp_batch_of_2048(cg, dev):
         assert f[i] == pytest.approx(fo, rel=1e-11)
         assert rel(Gs[i].cpu().numpy(), O.chol_rev(Lo, Lbar)) <= TOL
         assert rel(As[i].cpu().numpy(), Lo) <= TOL
+
+
+# ------------------------------------------------------------------------------------------------
+# FP32 storage (computed in FP64 inside the library, rounded once on output).  Against the oracle
+# on the same float inputs the only difference is that final rounding: relative Frobenius error at
+# most 2^-24 plus the FP64 gate, so F32_SAME = 1e-7.  End to end against the FP64 oracle on the
+# FP64 inputs (input rounding amplified by conditioning, kappa <= 41 on the batched workload):
+# stated tolerances relL <= 3e-7, rel Sigma-bar <= 3e-6, rel f <= 1e-6 (CPU emulation of the same
+# rounding measured at most 5.0e-8, 3.4e-7 and 2.1e-7).
+F32_SAME = 1e-7
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32)
+
+
+def widened(x):
+    return f32(x).astype(np.float64)
+
+
+def test_factor_batched_f32(cg, dev):
+    P = problems(SIZES, 1100)
+    mats = [to_dev(f32(p["S"] + p["junk"]), dev) for p in P]
+    info = cg.chol_factor_batched(mats)
+    assert info.cpu().tolist() == [0] * len(P)
+    for p, m in zip(P, mats):
+        Lg = m.cpu().numpy().astype(np.float64)
+        assert rel(Lg, O.chol(widened(p["S"]))[0]) <= F32_SAME
+        assert rel(Lg, O.chol(p["S"])[0]) <= 3e-7
+        assert np.all(np.triu(Lg, 1) == 0)
+
+
+@pytest.mark.parametrize("form", ["sym", "tril"])
+def test_rev_batched_f32(cg, dev, form):
+    P = problems(SIZES, 1200)
+    Ls = [to_dev(f32(p["L"]), dev) for p in P]
+    As = [to_dev(f32(p["Lb"] + p["junk"]), dev) for p in P]
+    cg.chol_rev_batched(Ls, As, form=form)
+    for p, a in zip(P, As):
+        want = O.chol_rev(widened(p["L"]), widened(p["Lb"]), form)
+        assert rel(a.cpu().numpy().astype(np.float64), want) <= F32_SAME
+
+
+def test_fwd_batched_f32(cg, dev):
+    P = problems(SIZES, 1300)
+    Ls = [to_dev(f32(p["L"]), dev) for p in P]
+    As = [to_dev(f32(np.tril(p["Sd"]) + p["junk"]), dev) for p in P]
+    cg.chol_fwd_batched(Ls, As)
+    for p, a in zip(P, As):
+        got = a.cpu().numpy().astype(np.float64)
+        assert rel(got, O.chol_fwd(widened(p["L"]), widened(p["Sd"]))) <= F32_SAME
+        assert np.all(np.triu(got, 1) == 0)
+
+
+def test_gp_batched_f32(cg, dev):
+    import torch
+    P = problems(SIZES, 1400)
+    As = [to_dev(f32(p["S"]), dev) for p in P]
+    Gs = [torch.empty_like(a) for a in As]
+    ys = [to_dev(f32(p["y"]), dev) for p in P]
+    f, info = cg.chol_gp_nll_batched(As, ys, Gs)
+    assert f.dtype == torch.float32
+    assert info.cpu().tolist() == [0] * len(P)
+    f = f.cpu().numpy().astype(np.float64)
+    for i, (p, g) in enumerate(zip(P, Gs)):
+        Lo, _ = O.chol(widened(p["S"]))
+        fo, Lbar = O.gp_loss_and_lbar(Lo, widened(p["y"]))
+        assert f[i] == pytest.approx(fo, rel=6e-8, abs=1e-30)
+        assert rel(g.cpu().numpy().astype(np.float64), O.chol_rev(Lo, Lbar)) <= F32_SAME
+        assert rel(As[i].cpu().numpy().astype(np.float64), Lo) <= F32_SAME
+
+
+def test_f32_alone_equals_in_batch_bitwise(cg, dev):
+    P = problems(SIZES, 1500)
+    k = SIZES.index(257)
+    alone = [to_dev(f32(P[k]["S"]), dev)]
+    cg.chol_factor_batched(alone)
+    mats = [to_dev(f32(p["S"]), dev) for p in P]
+    cg.chol_factor_batched(mats)
+    assert np.array_equal(alone[0].cpu().numpy(), mats[k].cpu().numpy())
+
+
+def test_gp_batch_of_2048_f32(cg, dev):
+    """The batched workload stored in FP32: 16 sampled problems end to end against the FP64 oracle
+    on the FP64 inputs, at the stated tolerances."""
+    import torch
+    case = W.batch_case()
+    As = [to_dev(f32(S), dev) for S in case["Sigma"]]
+    Gs = [torch.empty_like(a) for a in As]
+    ys = [to_dev(f32(y), dev) for y in case["y"]]
+    f, info = cg.chol_gp_nll_batched(As, ys, Gs)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0
+    f = f.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(19)
+    worst = [0.0, 0.0, 0.0]
+    for i in rng.choice(len(As), size=16, replace=False):
+        S, y = case["Sigma"][i], case["y"][i]
+        Lo, _ = O.chol(S)
+        fo, Lbar = O.gp_loss_and_lbar(Lo, y)
+        e = (rel(As[i].cpu().numpy().astype(np.float64), Lo),
+             rel(Gs[i].cpu().numpy().astype(np.float64), O.chol_rev(Lo, Lbar)),
+             abs(f[i] - fo) / abs(fo))
+        worst = [max(a, b) for a, b in zip(worst, e)]
+    print(f"FP32 storage end to end: relL {worst[0]:.2e}, rel Sigma-bar {worst[1]:.2e}, rel f {worst[2]:.2e}")
+    assert worst[0] <= 3e-7 and worst[1] <= 3e-6 and worst[2] <= 1e-6
