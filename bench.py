@@ -10,7 +10,8 @@ calls inside the timed steps; per-call figures for all three sweeps are reported
 Each step also runs the batched form once: 2048 SPD matrices (n log-uniform in [16, 512]) through
 factor + Gaussian-process loss + reverse sweep in one launch; its solves/s and launch-time
 percentiles are reported under "batched", and those of the same matrices in FP32 storage under
-"batched_f32".
+"batched_f32".  The three sweeps in the reduced-precision mode (trailing contractions on FP32
+MFMA) are timed alone under "f64_trail_f32"; the headline value stays the FP64 path's.
 
 Output: one JSON line on stdout.  `--gpus` above 1 is refused (single-GPU build).
 
@@ -56,7 +57,7 @@ def traffic_for(kernel_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
-TARGET_KERNEL = "gemm_f64_dma_kernel<false, false, 1>"
+TARGET_KERNEL = "gemm_f64_dma_kernel<false, false, 1, 0>"
 CALIBRATION_KERNEL = "neg_kernel"
 
 
@@ -170,6 +171,8 @@ def main():
                     help="timed launches of the batched path for its latency percentiles")
     ap.add_argument("--cpu-sample", type=int, default=10240,
                     help="leading-block size for the CPU oracle baseline (0 skips it)")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="timed passes of the f64_trail_f32 mode (0 skips it)")
     ap.add_argument("--calibration-mib", type=int, default=0,
                     help="run one plain elementwise copy of this size first (PMC calibration)")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -256,6 +259,41 @@ def main():
     if int((bat["info"] != 0).sum()) != 0 or not bool(torch.isfinite(bat["f"]).all()):
         raise RuntimeError("batched factorisation failed")
 
+    # The reduced-precision mode (trailing contractions on FP32 MFMA) on the same workload: the
+    # three sweeps timed alone, after one untimed pass.
+    mixed = None
+    if args.mixed_steps > 0:
+        log("[bench] f64_trail_f32 sweeps")
+        mt = {"f": 0.0, "r": 0.0, "d": 0.0}
+        for i in range(args.mixed_steps + 1):
+            A.copy_(Sigma)
+            ev["f"][0].record()
+            cg.chol_factor(A, nb=nb, workspace=ws, info=info, precision="f64_trail_f32")
+            ev["f"][1].record()
+            Ab.copy_(Lbar)
+            ev["r"][0].record()
+            cg.chol_rev(A, Ab, nb=nb, workspace=ws, precision="f64_trail_f32")
+            ev["r"][1].record()
+            Ad.copy_(Sdot)
+            ev["d"][0].record()
+            cg.chol_fwd(A, Ad, nb=nb, workspace=ws, precision="f64_trail_f32")
+            ev["d"][1].record()
+            torch.cuda.synchronize()
+            if i > 0:
+                for k in mt:
+                    mt[k] += ev[k][0].elapsed_time(ev[k][1]) / args.mixed_steps
+        if int(info.item()) != 0:
+            raise RuntimeError("f64_trail_f32 chol_factor failed")
+        mixed = {"mode": "FP64 storage; trailing contractions on FP32 MFMA; diagonal blocks and panel "
+                         "solves FP64 (accuracy stated and tested separately)",
+                 "steps": args.mixed_steps,
+                 "chol_rev_ms": round(mt["r"], 3),
+                 "chol_rev_tflops": round(2.0 / 3.0 * n ** 3 / (mt["r"] * 1e-3) / 1e12, 3),
+                 "chol_factor_ms": round(mt["f"], 3),
+                 "chol_factor_tflops": round(n ** 3 / 3.0 / (mt["f"] * 1e-3) / 1e12, 3),
+                 "chol_fwd_ms": round(mt["d"], 3),
+                 "chol_fwd_tflops": round(2.0 / 3.0 * n ** 3 / (mt["d"] * 1e-3) / 1e12, 3)}
+
     # Launch-time distribution of the one-launch batched path (factor + loss + reverse sweep), for
     # FP64 storage (the bench workload) and FP32 storage of the same matrices.
     import numpy as np
@@ -311,7 +349,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": "gemm_f64_dma_kernel<false,false,1> (reverse-sweep panel contraction)",
+                "kernel": "gemm_f64_dma_kernel<false,false,1,0> (reverse-sweep panel contraction, FP64 MFMA)",
                 "kernel_avg_us": round(k_ms * 1e3 / max(k_launch, 1), 2),
                 "algorithmic_bytes_per_launch": round(k_bytes / max(k_launch, 1)),
                 "algorithmic_flops_per_launch": round(k_flops / max(k_launch, 1)),
@@ -333,6 +371,7 @@ def main():
         "roofline": roofline,
         "batched": batched,
         "batched_f32": batched_f32,
+        "f64_trail_f32": mixed,
     }
     if args.cpu_sample > 0:
         log(f"[bench] timing the CPU oracle on a {args.cpu_sample} sample")

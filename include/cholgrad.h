@@ -56,9 +56,19 @@ extern "C" {
  *                   problem's lower triangle is widened to FP64 in the workspace, computed exactly
  *                   as in CHOL_PREC_F64 and rounded to float once on output, so the result is the
  *                   FP64 result for the float input to within float rounding.  Single-matrix
- *                   calls return CHOL_ERR_UNSUPPORTED for it. */
+ *                   calls return CHOL_ERR_UNSUPPORTED for it.
+ *   CHOL_PREC_F64_TRAIL_F32 : double storage, single-matrix calls only (batched calls return
+ *                   CHOL_ERR_UNSUPPORTED).  The trailing contractions -- the block-column
+ *                   updates of chol_factor and chol_fwd and the panel contraction and SYRK of
+ *                   chol_rev -- round their operands to FP32 and run on FP32 MFMA with FP32
+ *                   accumulation within one launch's K range; diagonal blocks, block inverses,
+ *                   panel solves, split-K sums and every stored value stay FP64.  An
+ *                   approximation of the FP64 result: on the N = 16384 squared-exponential
+ *                   workload (condition number ~1e5) the stated relative Frobenius errors are
+ *                   <= 3e-4 for L and <= 3e-3 for Sigma-bar and L-dot. */
 #define CHOL_PREC_F64 0
 #define CHOL_PREC_F32 1
+#define CHOL_PREC_F64_TRAIL_F32 2
 
 /* Which reverse-mode output (Sec. 3, eqns (symrev) and (symrevtril); S = L^-T Phi(L^T Lbar) L^-1):
  *   CHOL_SBAR_SYM  : (S + S^T)/2 in both triangles -- the symmetric gradient, for which

@@ -30,7 +30,7 @@ import numpy as np
 from scipy.linalg import solve_triangular
 
 __all__ = [
-    "tril", "Phi", "sym_from_lower", "chol", "chol_fwd", "chol_rev", "chol_rev_S", "sbar_forms",
+    "tril", "Phi", "sym_from_lower", "chol", "chol_host", "chol_fwd", "chol_rev", "chol_rev_S", "sbar_forms",
     "level2partition", "chol_unblocked", "chol_unblocked_fwd", "chol_unblocked_rev",
     "level3partition", "chol_blocked", "chol_blocked_fwd", "chol_blocked_rev",
     "vech", "vec", "elimination_matrix", "duplication_matrix",
@@ -85,6 +85,16 @@ def chol(Sigma):
         L[j, j] = np.sqrt(piv)
         L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ L[j, :j]) / L[j, j]
     return L, 0
+
+
+def chol_host(Sigma):
+    """The same unique factor as ``chol`` (Sec. 1) computed by host LAPACK's dpotrf: the library
+    special case of the definition, for sizes where the column-by-column loop is too slow
+    (pinned against ``chol`` in the CPU tests).  Only tril(Sigma) is read; raises on a
+    non-positive pivot."""
+    from scipy.linalg import cholesky
+    L = cholesky(np.tril(np.asarray(Sigma, dtype=np.float64)), lower=True, check_finite=False)
+    return np.ascontiguousarray(L)
 
 
 def chol_fwd(L, Sigma_dot):

@@ -14,6 +14,9 @@ LIB_PATH = os.path.join(PKG, "libcholgrad.so")
 
 PREC_F64 = 0
 PREC_F32 = 1
+PREC_F64_TRAIL_F32 = 2
+# Precision modes of the single-matrix calls (FP64 storage).
+_PRECS = {"f64": PREC_F64, "f64_trail_f32": PREC_F64_TRAIL_F32}
 SBAR_SYM, SBAR_TRIL = 0, 1
 OP_FACTOR, OP_REV, OP_FWD = 0, 1, 2
 _FORMS = {"sym": SBAR_SYM, "tril": SBAR_TRIL}
@@ -92,13 +95,13 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def workspace_bytes(op, n, nb=0):
+def workspace_bytes(op, n, nb=0, precision="f64"):
     """Device workspace bytes for op in {'factor', 'rev', 'fwd'} at size n and block size nb."""
-    return int(load_library().chol_workspace_bytes(_OPS[op], PREC_F64, int(n), int(nb)))
+    return int(load_library().chol_workspace_bytes(_OPS[op], _PRECS[precision], int(n), int(nb)))
 
 
-def _workspace(op, n, nb, device, workspace):
-    need = workspace_bytes(op, n, nb)
+def _workspace(op, n, nb, device, workspace, precision="f64"):
+    need = workspace_bytes(op, n, nb, precision)
     if workspace is None:
         return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
     if workspace.device != device or workspace.numel() * workspace.element_size() < need:
@@ -106,44 +109,45 @@ def _workspace(op, n, nb, device, workspace):
     return workspace
 
 
-def chol_factor(A, nb=0, workspace=None, info=None):
+def chol_factor(A, nb=0, workspace=None, info=None, precision="f64"):
     """In place: tril(A) = Sigma -> tril(A) = L, strict upper set to 0.  Returns (A, info) where
-    info is a device int32 tensor (0, or the 1-based column of the first non-positive pivot)."""
+    info is a device int32 tensor (0, or the 1-based column of the first non-positive pivot).
+    precision: 'f64', or 'f64_trail_f32' (trailing updates on FP32 MFMA)."""
     lib = load_library()
     n = _square("A", A)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    ws = _workspace("factor", n, nb, A.device, workspace)
+    ws = _workspace("factor", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_factor", lib.chol_factor(PREC_F64, n, A.data_ptr(), A.stride(0) if n else 1, nb,
+        _check("chol_factor", lib.chol_factor(_PRECS[precision], n, A.data_ptr(), A.stride(0) if n else 1, nb,
                                               info.data_ptr(), ws.data_ptr(), ws.numel(),
                                               _stream(A.device)))
     return A, info
 
 
-def chol_rev(L, A, form="sym", nb=0, workspace=None):
+def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64"):
     """In place: tril(A) = L-bar -> A = Sigma-bar in the chosen form ('sym' or 'tril')."""
     lib = load_library()
     n = _square("L", L)
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
-    ws = _workspace("rev", n, nb, A.device, workspace)
+    ws = _workspace("rev", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_rev", lib.chol_rev(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1,
+        _check("chol_rev", lib.chol_rev(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
                                         A.data_ptr(), A.stride(0) if n else 1, _FORMS[form], nb,
                                         ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
 
-def chol_fwd(L, A, nb=0, workspace=None):
+def chol_fwd(L, A, nb=0, workspace=None, precision="f64"):
     """In place: tril(A) = tril(Sigma-dot) -> tril(A) = L-dot, strict upper set to 0."""
     lib = load_library()
     n = _square("L", L)
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
-    ws = _workspace("fwd", n, nb, A.device, workspace)
+    ws = _workspace("fwd", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_fwd", lib.chol_fwd(PREC_F64, n, L.data_ptr(), L.stride(0) if n else 1,
+        _check("chol_fwd", lib.chol_fwd(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
                                         A.data_ptr(), A.stride(0) if n else 1, nb, ws.data_ptr(),
                                         ws.numel(), _stream(A.device)))
     return A

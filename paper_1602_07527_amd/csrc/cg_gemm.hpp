@@ -1,5 +1,7 @@
-// FP64 MFMA contraction kernels for the Level-3 updates (Sec. 4.2 of Murray 2016: the GEMM-,
-// SYRK- and TRSM-shaped steps of the blocked factorisation and its derivatives).
+// MFMA contraction kernels for the Level-3 updates (Sec. 4.2 of Murray 2016: the GEMM-, SYRK- and
+// TRSM-shaped steps of the blocked factorisation and its derivatives).  Operands and results are
+// FP64 in memory; the products run on FP64 MFMA, or on FP32 MFMA for the reduced-precision
+// trailing updates (template parameter CP).
 //
 //   C[m, n] = alpha * sum_k A(m, k) B(k, n) + beta * Cin[m, n]        (m < M, n < N, k < K)
 //
@@ -19,6 +21,35 @@
 namespace cg {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Arithmetic of a contraction.  Operands and results are FP64 in memory either way.
+//   CP_F64: v_mfma_f64_16x16x4_f64, FP64 accumulation.
+//   CP_F32: operands rounded to FP32 as they leave LDS, v_mfma_f32_16x16x4_f32 with FP32
+//           accumulation over the K range of one launch (one split); the epilogue (alpha, beta,
+//           split sums) stays in FP64.
+constexpr int CP_F64 = 0;
+constexpr int CP_F32 = 1;
+
+template <int CP> struct Mfma;
+template <> struct Mfma<CP_F64> {
+  typedef dbl4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // Output layout of the 16 x 16 block: lane l, element i holds row 4*i + l/16, column l%16.
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+template <> struct Mfma<CP_F32> {
+  typedef flt4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+  }
+  // Output layout: lane l, element i holds row 4*(l/16) + i, column l%16.
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
 
 constexpr int GEMM_BM = 128;
 constexpr int GEMM_BN = 128;
@@ -52,9 +83,10 @@ constexpr int GEMM_LDS = 2 * (GEMM_LDS_A + GEMM_LDS_B);      // doubles of LDS f
 // with the epilogue of p (alpha, beta * Cin, optional transposed copy).  Called by a whole
 // 256-thread workgroup; `lds` holds GEMM_LDS doubles.  Ends with a barrier, so the workgroup may
 // reuse `lds` right after.
-template <bool AT, bool BT>
+template <bool AT, bool BT, int CP = CP_F64>
 __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend, double *Cout,
                           double *lds) {
+  typedef Mfma<CP> MM;
   constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK, LDA_S = BM + GEMM_PAD,
                 LDB_S = BN + GEMM_PAD;
   double *As[2] = {lds, lds + GEMM_LDS_A};
@@ -65,11 +97,11 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  dbl4 acc[4][4];
+  typename MM::acc_t acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = MM::zero();
 
   double ra[8], rb[8];
   // Global -> registers for the K-tile starting at k0.
@@ -137,13 +169,13 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = MM::step(af[a], bf[b], acc[a][b]);
     }
     if (kt + 1 < nkt) store_tile(buf ^ 1);
     __syncthreads();
   }
 
-  // Epilogue.  MFMA f64 16x16 output layout: lane l, element i holds row 4*i + l/16, column l%16.
+  // Epilogue in FP64.
   const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -151,10 +183,10 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gm = m0 + wm * 64 + a * 16 + 4 * i + (lane >> 4);
+        const int gm = m0 + wm * 64 + a * 16 + MM::row(lane, i);
         const int gn = n0 + wn * 64 + b * 16 + (lane & 15);
         if (gm < p.M && gn < p.N) {
-          double v = alpha * acc[a][b][i];
+          double v = alpha * (double)acc[a][b][i];
           if (beta != 0.0) v += beta * p.Cin[(int64_t)gm * p.ldcin + gn];
           Cout[(int64_t)gm * p.ldc + gn] = v;
           if (p.Cm) p.Cm[(int64_t)gn * p.ldcm + gm] = v;
@@ -165,7 +197,7 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
 
 // TAG only separates kernel names for profiling (1: reverse-sweep panel contraction,
 // 2: factor-sweep panel contraction, 3: forward-sweep panel contraction, 0: other products).
-template <bool AT, bool BT, int TAG>
+template <bool AT, bool BT, int TAG, int CP = CP_F64>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
   __shared__ double lds[GEMM_LDS];
   const int m0 = blockIdx.x * GEMM_BM;
@@ -174,7 +206,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
   const int z = blockIdx.z;
   const int kbeg = z * p.kchunk;
   const int kend = min(p.K, kbeg + p.kchunk);
-  gemm_tile<AT, BT>(p, m0, n0, kbeg, kend, p.C + (int64_t)z * p.split_stride, lds);
+  gemm_tile<AT, BT, CP>(p, m0, n0, kbeg, kend, p.C + (int64_t)z * p.split_stride, lds);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -192,8 +224,9 @@ __host__ __device__ constexpr int waitcnt_vm(int n) {  // s_waitcnt immediate: v
   return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
 }
 
-template <bool AT, bool BT, int TAG>
+template <bool AT, bool BT, int TAG, int CP = CP_F64>
 __global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
+  typedef Mfma<CP> MM;
   constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = DMA_BK, TILE = BM * BK;
   constexpr int WM = 2, WN = 4, NW = WM * WN;
   constexpr int NQ = TILE * 8 / 1024 / NW;     // 1 KB DMA instructions per wave per operand per tile
@@ -252,11 +285,11 @@ __global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
     }
   };
 
-  dbl4 acc[TMW][TNW];
+  typename MM::acc_t acc[TMW][TNW];
 #pragma unroll
   for (int a = 0; a < TMW; ++a)
 #pragma unroll
-    for (int b = 0; b < TNW; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < TNW; ++b) acc[a][b] = MM::zero();
 
   if (nkt > 0) issue(0, 0);
   const int fk = lane >> 4, fi = lane & 15;
@@ -287,7 +320,7 @@ __global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
       for (int a = 0; a < TMW; ++a)
 #pragma unroll
         for (int b = 0; b < TNW; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = MM::step(af[a], bf[b], acc[a][b]);
     }
   }
 
@@ -298,9 +331,9 @@ __global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
     for (int b = 0; b < TNW; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gm = m0 + wm * (BM / WM) + a * 16 + 4 * i + (lane >> 4);
+        const int gm = m0 + wm * (BM / WM) + a * 16 + MM::row(lane, i);
         const int gn = n0 + wn * (BN / WN) + b * 16 + (lane & 15);
-        double v = alpha * acc[a][b][i];
+        double v = alpha * (double)acc[a][b][i];
         if (beta != 0.0) v += beta * p.Cin[(int64_t)gm * p.ldcin + gn];
         Cout[(int64_t)gm * p.ldc + gn] = v;
         if (p.Cm) p.Cm[(int64_t)gn * p.ldcm + gm] = v;

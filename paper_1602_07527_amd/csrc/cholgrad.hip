@@ -101,33 +101,48 @@ hipError_t side_for_current_device(Side **out) {
   return hipSuccess;
 }
 
+// Precision modes of the single-matrix sweeps (FP64 storage): the trailing contractions run on
+// FP64 or FP32 MFMA; diagonal blocks and panel solves are FP64 in both.
+bool single_prec(int precision, int *cp) {
+  if (precision == CHOL_PREC_F64) { *cp = cg::CP_F64; return true; }
+  if (precision == CHOL_PREC_F64_TRAIL_F32) { *cp = cg::CP_F32; return true; }
+  return false;
+}
+
 bool nb_ok(int nb) { return nb == 0 || (nb >= 32 && nb <= cg::DIAG_MAX && nb % 32 == 0); }
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
-template <int TAG>
+template <int TAG, int CP>
 void launch_gemm_tag(bool at, bool bt, bool fast, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
   if (fast) {
     const dim3 block(cg::DMA_THREADS);
-    if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, false, TAG>), grid, block, 0, s, p);
-    else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, true, TAG>), grid, block, 0, s, p);
-    else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, false, TAG>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, true, TAG>), grid, block, 0, s, p);
+    if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, false, TAG, CP>), grid, block, 0, s, p);
+    else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, true, TAG, CP>), grid, block, 0, s, p);
+    else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, false, TAG, CP>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, true, TAG, CP>), grid, block, 0, s, p);
     return;
   }
   const dim3 block(cg::GEMM_THREADS);
-  if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<true, false, TAG>), grid, block, 0, s, p);
-  else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, true, TAG>), grid, block, 0, s, p);
-  else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, false, TAG>), grid, block, 0, s, p);
-  else hipLaunchKernelGGL((cg::gemm_f64_kernel<true, true, TAG>), grid, block, 0, s, p);
+  if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<true, false, TAG, CP>), grid, block, 0, s, p);
+  else if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, true, TAG, CP>), grid, block, 0, s, p);
+  else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_kernel<false, false, TAG, CP>), grid, block, 0, s, p);
+  else hipLaunchKernelGGL((cg::gemm_f64_kernel<true, true, TAG, CP>), grid, block, 0, s, p);
 }
 
-void launch_gemm(bool at, bool bt, bool fast, int tag, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+template <int CP>
+void launch_gemm_cp(bool at, bool bt, bool fast, int tag, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
   switch (tag) {
-    case 1: launch_gemm_tag<1>(at, bt, fast, grid, p, s); break;
-    case 2: launch_gemm_tag<2>(at, bt, fast, grid, p, s); break;
-    case 3: launch_gemm_tag<3>(at, bt, fast, grid, p, s); break;
-    default: launch_gemm_tag<0>(at, bt, fast, grid, p, s); break;
+    case 1: launch_gemm_tag<1, CP>(at, bt, fast, grid, p, s); break;
+    case 2: launch_gemm_tag<2, CP>(at, bt, fast, grid, p, s); break;
+    case 3: launch_gemm_tag<3, CP>(at, bt, fast, grid, p, s); break;
+    default: launch_gemm_tag<0, CP>(at, bt, fast, grid, p, s); break;
   }
+}
+
+void launch_gemm(bool at, bool bt, bool fast, int tag, int cp, dim3 grid, const cg::GemmArgs &p,
+                 hipStream_t s) {
+  if (cp == cg::CP_F32) launch_gemm_cp<cg::CP_F32>(at, bt, fast, tag, grid, p, s);
+  else launch_gemm_cp<cg::CP_F64>(at, bt, fast, tag, grid, p, s);
 }
 
 bool aligned16(const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
@@ -138,7 +153,7 @@ bool aligned16(const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u
 hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t lda,
                 const double *B, int64_t ldb, double alpha, const double *Cin, int64_t ldcin,
                 double beta, double *C, int64_t ldc, double *Cm, int64_t ldcm, int lower_only,
-                double *part, int min_kchunk, hipStream_t s, int tag = 0) {
+                double *part, int min_kchunk, hipStream_t s, int tag = 0, int cp = cg::CP_F64) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, cg::GEMM_BN);
   int tiles = tm * tn;
@@ -184,7 +199,7 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
     const double mn = (double)M * (double)N * (lower_only ? 0.5 : 1.0);
     g_prof.bytes[u] = 8.0 * ((double)M * K + (double)K * N + mn * ((beta != 0.0 ? 2.0 : 1.0) + (Cm ? 1.0 : 0.0)));
   }
-  launch_gemm(at, bt, fast, tag, grid, p, s);
+  launch_gemm(at, bt, fast, tag, cp, grid, p, s);
   if (timed) {
     if (hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s) != hipSuccess) return hipErrorUnknown;
     ++g_prof.used;
@@ -324,7 +339,8 @@ const char *chol_status_string(int status) {
 }
 
 size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
-  if (n <= 0 || precision != CHOL_PREC_F64 || !nb_ok(nb)) return 0;
+  int cp = cg::CP_F64;
+  if (n <= 0 || !single_prec(precision, &cp) || !nb_ok(nb)) return 0;
   if (op != CHOL_OP_FACTOR && op != CHOL_OP_REV && op != CHOL_OP_FWD) return 0;
   if (nb == 0) nb = DEFAULT_NB;
   SweepWs w;
@@ -334,7 +350,8 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
 int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
-  if (precision != CHOL_PREC_F64) return -1;
+  int cp = cg::CP_F64;
+  if (!single_prec(precision, &cp)) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
   if (n == 0) return CHOL_SUCCESS;
   if (!Lv || !aligned8(Lv)) return -3;
@@ -384,10 +401,10 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       if (m2 > 0)
         CG_TRY(gemm(false, false, m2, w, m, A + (k + m1) * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                     A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0,
-                    ws.part, 256, s, 1));
+                    ws.part, 256, s, 1, cp));
       CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
       CG_TRY(gemm(false, false, m1, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
-                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 256, s, 1));
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 256, s, 1, cp));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
       // triangles.
       CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0,
@@ -396,7 +413,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       CG_TRY(hipStreamWaitEvent(s2, side->panel, 0));
       // D-bar = tril(L-bar_D) - tril(C-bar^T C), C-bar = 2 * A[k:, j:k]   -> dblk (w x w)
       CG_TRY(gemm(true, false, w, w, m, A + k * lda + j, lda, L + k * ldl + j, ldl, -2.0,
-                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part2, 256, s2));
+                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part2, 256, s2, 0, cp));
     } else {
       CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s2));
     }
@@ -418,7 +435,8 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
 int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *info,
                 void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
-  if (precision != CHOL_PREC_F64) return -1;
+  int cp = cg::CP_F64;
+  if (!single_prec(precision, &cp)) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
   if (n == 0) return CHOL_SUCCESS;
   if (!Av || !aligned8(Av)) return -3;
@@ -454,10 +472,10 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
       // [D; C] <- [D; C] - [R; B] R^T   (D - tril(R R^T) and C - B R^T in one product)
       if (jp > 0)
         CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, A + j * lda, lda, -1.0,
-                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2));
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
       CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
       CG_TRY(gemm(false, true, (int)(n - j), w, nb, A + j * lda + jp, lda, A + j * lda + jp, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2));
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
       CG_TRY(hipEventRecord(side->diag, s));
       CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
     }
@@ -481,7 +499,8 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
 int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
-  if (precision != CHOL_PREC_F64) return -1;
+  int cp = cg::CP_F64;
+  if (!single_prec(precision, &cp)) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
   if (n == 0) return CHOL_SUCCESS;
   if (!Lv || !aligned8(Lv)) return -3;
@@ -518,15 +537,15 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T   over columns [0, jp), then [jp, j)
       if (jp > 0) {
         CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, L + j * ldl, ldl, -1.0,
-                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
         CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, L + j * ldl, ldl, A + j * lda, lda, -1.0,
-                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
       }
       CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
       CG_TRY(gemm(false, true, (int)(n - j), w, nb, A + j * lda + jp, lda, L + j * ldl + jp, ldl, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
       CG_TRY(gemm(false, true, (int)(n - j), w, nb, L + j * ldl + jp, ldl, A + j * lda + jp, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3));
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
       CG_TRY(hipEventRecord(side->diag, s));
       CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
     }
@@ -562,6 +581,7 @@ size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max) {
 }
 
 static int batched_common_checks(int precision, int batch, int64_t n_max) {
+  if (precision == CHOL_PREC_F64_TRAIL_F32) return CHOL_ERR_UNSUPPORTED;
   if (!batched_prec_ok(precision)) return -1;
   if (batch < 0) return -2;
   if (n_max < 0 || n_max > cg::BATCH_NMAX) return CHOL_ERR_UNSUPPORTED;

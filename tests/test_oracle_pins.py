@@ -48,8 +48,10 @@ def test_chol_reconstruction_and_lapack(N):
     assert info == 0
     assert np.all(np.diag(L) > 0) and np.all(np.triu(L, 1) == 0)
     assert rel(L @ L.T, S) <= 4 * N * U
-    # a library special case: host LAPACK dpotrf
+    # a library special case: host LAPACK dpotrf, also as the oracle's large-size route
     assert rel(L, sla.cholesky(S, lower=True)) <= 50 * N * U
+    Lh = O.chol_host(S + np.triu(np.full((N, N), 7.0), 1))     # reads the lower triangle only
+    assert rel(Lh, L) <= 50 * N * U and np.all(np.triu(Lh, 1) == 0)
 
 
 def test_chol_reads_lower_only():
