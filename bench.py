@@ -11,7 +11,10 @@ Each step also runs the batched form once: 2048 SPD matrices (n log-uniform in [
 factor + Gaussian-process loss + reverse sweep in one launch; its solves/s and launch-time
 percentiles are reported under "batched", and those of the same matrices in FP32 storage under
 "batched_f32".  The three sweeps in the reduced-precision mode (trailing contractions on FP32
-MFMA) are timed alone under "f64_trail_f32"; the headline value stays the FP64 path's.
+MFMA) are timed alone under "f64_trail_f32"; the headline value stays the FP64 path's.  Under
+"serving", a Poisson stream of factor + chol_rev requests of uneven size runs through the
+continuous-batching loop (paper_1602_07527_amd.serve) in both precision modes: p50/p99 latency and
+solves/s.
 
 Output: one JSON line on stdout.  `--gpus` above 1 is refused (single-GPU build).
 
@@ -171,6 +174,8 @@ def main():
                     help="timed launches of the batched path for its latency percentiles")
     ap.add_argument("--cpu-sample", type=int, default=10240,
                     help="leading-block size for the CPU oracle baseline (0 skips it)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the served request stream (0 skips it)")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed passes of the f64_trail_f32 mode (0 skips it)")
     ap.add_argument("--calibration-mib", type=int, default=0,
@@ -333,6 +338,29 @@ def main():
         batched_f32 = batched_summary(bat32, launch_times(bat32, args.batch_launches), "FP32")
         del bat32
 
+    # Serving: the Poisson request stream (200 requests/s, n log-uniform in [64, 4096], 2-D
+    # squared-exponential kernels), factor + chol_rev per request through the continuous-batching
+    # loop, in FP64 and with FP32-MFMA trailing contractions for the large requests.
+    serving = None
+    if args.serve_seconds > 0:
+        from paper_1602_07527_amd import serve
+        tr = workloads.serve_trace(rate=200.0, seconds=args.serve_seconds)
+        make = lambda i: workloads.se_request_device(tr["n"][i], tr["lengthscale"][i], tr["seed"][i], dev)
+        serving = {"workload": f"Poisson arrivals at 200/s for {args.serve_seconds:g} s ({len(tr['t'])} "
+                               "requests), n log-uniform in [64, 4096], SE kernel on U[0,1]^2 (lengthscale "
+                               "U[0.1, 0.5]) + 1e-3 I, L-bar = tril N(0,1); one request = chol_factor + "
+                               "chol_rev; HBM budget 64 GiB", "n_mean": round(float(tr["n"].mean()), 1)}
+        for mode in ("f64", "f64_trail_f32"):
+            log(f"[bench] serving {args.serve_seconds:g} s in {mode}")
+            srv = serve.Server(dev, hbm_budget=64 << 30, precision=mode)
+            done, wall = serve.replay(srv, tr["t"], make)
+            if any(int(r.info.item()) != 0 for r in done):
+                raise RuntimeError("a served factorisation failed")
+            serving[mode] = serve.latency_summary(done, wall)
+            serving[mode]["launches"] = dict(srv.launches)
+            serving[mode]["peak_admitted_gib"] = round(srv.peak_in_use / 2 ** 30, 3)
+            del done, srv
+
     K = args.steps
     ms_step = (t1 - t0) * 1e3 / K
     f_rev = 2.0 / 3.0 * n ** 3
@@ -372,6 +400,7 @@ def main():
         "batched": batched,
         "batched_f32": batched_f32,
         "f64_trail_f32": mixed,
+        "serving": serving,
     }
     if args.cpu_sample > 0:
         log(f"[bench] timing the CPU oracle on a {args.cpu_sample} sample")

@@ -21,9 +21,11 @@
  *     aligned to 256 bytes).  The library never allocates, frees or synchronises inside these calls;
  *     all work is enqueued on `stream` (a hipStream_t; NULL means the default stream) in order.
  *     Calls on distinct (stream, workspace) pairs may run concurrently.  The device of `stream`
- *     must be the current device.  chol_rev additionally runs part of its work on one auxiliary
- *     stream per device (default priority), ordered against `stream` with events; that stream and
- *     its three events are created by the first call on a device and kept for the process.
+ *     must be the current device.  The single-matrix calls additionally run their diagonal-block
+ *     chain on an auxiliary stream (default priority) ordered against `stream` with events: one
+ *     auxiliary stream and three events per (device, calling stream) pair for up to 8 calling
+ *     streams per device (further calling streams share them), created on first use and kept for
+ *     the process.  Host-side enqueueing of these calls is serialised by a library mutex.
  *   - Return value: CHOL_SUCCESS (0), or a negative status checked synchronously on the host
  *     before anything is enqueued:  -i  means argument i (1-based) is invalid;  CHOL_ERR_* below.
  *     Numerical breakdown of chol_factor is reported asynchronously through `info`.
@@ -160,6 +162,21 @@ int chol_rev_batched(int precision, int batch, const int64_t *n, const void *con
 int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *const *L, const int64_t *ldl,
                      void *const *A, const int64_t *lda, int64_t n_max, void *workspace,
                      size_t workspace_bytes, void *stream);
+
+/*
+ * chol_factor_rev_batched -- a factorisation followed by the reverse sweep on its own factor, per
+ * problem, in one launch (the Sigma -> L forward pass and the L-bar -> Sigma-bar backward pass of
+ * Sec. 2 with L kept on the device between them):
+ *   A[b]   in: tril = Sigma_b.  out: L_b (strict upper set to 0), left in place for later use.
+ *   G[b]   in: tril = L-bar_b.  out: Sigma-bar_b in the form selected by sbar_form (untouched when
+ *          info[b] != 0).
+ *   info   out: device array of batch ints (LAPACK convention; -1 for a skipped problem).
+ *   Arguments: 1 precision, 2 batch, 3 n, 4 A, 5 lda, 6 G, 7 ldg, 8 n_max, 9 sbar_form, 10 info,
+ *              11 workspace, 12 workspace_bytes, 13 stream.
+ */
+int chol_factor_rev_batched(int precision, int batch, const int64_t *n, void *const *A, const int64_t *lda,
+                            void *const *G, const int64_t *ldg, int64_t n_max, int sbar_form, int *info,
+                            void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * chol_gp_nll_batched -- the whole x -> Sigma -> L -> f -> Sigma-bar chain of Sec. 2 per problem, in

@@ -61,6 +61,8 @@ def load_library():
     lib.chol_rev_batched.restype = i32
     lib.chol_fwd_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, vp, sz, vp]
     lib.chol_fwd_batched.restype = i32
+    lib.chol_factor_rev_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, i32, vp, vp, sz, vp]
+    lib.chol_factor_rev_batched.restype = i32
     lib.chol_gp_nll_batched.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, sz, vp]
     lib.chol_gp_nll_batched.restype = i32
     lib.chol_profile_begin.argtypes = [i32]
@@ -280,6 +282,24 @@ def chol_fwd_batched(L, A, workspace=None):
             A.prec, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
             A.ld.data_ptr(), A.n_max, ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A.mats
+
+
+def chol_factor_rev_batched(A, G, form="sym", info=None, workspace=None):
+    """Per problem b, in one launch: A[b] (Sigma -> L, kept) then G[b] (L-bar -> Sigma-bar in the
+    chosen form, on that L).  Returns the device int32 info array."""
+    lib = load_library()
+    A, G = _as_batch(A), _as_batch(G)
+    if A.sizes != G.sizes or A.dtype != G.dtype or A.device != G.device:
+        raise ValueError("A and G batches must have the same sizes, dtype and device")
+    if info is None:
+        info = torch.empty(len(A), dtype=torch.int32, device=A.device)
+    ws = _batch_ws(len(A), A.n_max, A.device, workspace, A.prec)
+    with torch.cuda.device(A.device):
+        _check("chol_factor_rev_batched", lib.chol_factor_rev_batched(
+            A.prec, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), G.ptr.data_ptr(),
+            G.ld.data_ptr(), A.n_max, _FORMS[form], info.data_ptr(), ws.data_ptr(), ws.numel(),
+            _stream(A.device)))
+    return info
 
 
 def chol_gp_nll_batched(A, y, G, f=None, info=None, workspace=None):

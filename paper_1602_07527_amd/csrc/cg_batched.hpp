@@ -23,7 +23,7 @@ constexpr int BATCH_NBLK = BATCH_NMAX / BATCH_NB;
 constexpr int BATCH_LDS = 2 * DIAG_PACKED + INNER * XLD;
 static_assert(BATCH_LDS >= GEMM_LDS, "tile-product staging must fit in the shared LDS buffer");
 
-enum BatchOp { BATCH_FACTOR = 0, BATCH_REV = 1, BATCH_FWD = 2, BATCH_GP = 3 };
+enum BatchOp { BATCH_FACTOR = 0, BATCH_REV = 1, BATCH_FWD = 2, BATCH_GP = 3, BATCH_FACTOR_REV = 4 };
 
 // Per-workgroup scratch in global memory (doubles).
 constexpr int64_t SLOT_DINV = (int64_t)BATCH_NBLK * BATCH_NB * BATCH_NB;  // block inverses
@@ -37,12 +37,12 @@ struct BatchArgs {
   int batch;
   int sbar_form;
   const int64_t *n;
-  double *const *A;         // factor: Sigma -> L; rev: L-bar -> Sigma-bar; fwd: Sigma-dot -> L-dot
+  double *const *A;         // factor (+rev), GP: Sigma -> L; rev: L-bar -> Sigma-bar; fwd: Sigma-dot -> L-dot
   const int64_t *lda;
   const double *const *L;   // rev / fwd
   const int64_t *ldl;
   const double *const *y;   // GP mode: right-hand sides
-  double *const *G;         // GP mode: Sigma-bar output
+  double *const *G;         // GP mode: Sigma-bar output; factor+rev: L-bar -> Sigma-bar
   const int64_t *ldg;
   double *f;                // GP mode: losses
   int *info;                // factor / GP mode
@@ -326,9 +326,10 @@ __global__ __launch_bounds__(DIAG_THREADS) void batch_kernel(BatchArgs a) {
     if (it >= a.batch) break;
     const int b = a.order[it];
     const int64_t n64 = a.n[b];
-    const bool has_info = (OP == BATCH_FACTOR || OP == BATCH_GP);
+    const bool has_info = (OP == BATCH_FACTOR || OP == BATCH_GP || OP == BATCH_FACTOR_REV);
     if (n64 < 0 || n64 > a.n_max || a.lda[b] < n64 ||
-        ((OP == BATCH_REV || OP == BATCH_FWD) && a.ldl[b] < n64) || (OP == BATCH_GP && a.ldg[b] < n64)) {
+        ((OP == BATCH_REV || OP == BATCH_FWD) && a.ldl[b] < n64) ||
+        ((OP == BATCH_GP || OP == BATCH_FACTOR_REV) && a.ldg[b] < n64)) {
       if (has_info && threadIdx.x == 0) a.info[b] = -1;
       continue;
     }
@@ -352,10 +353,25 @@ __global__ __launch_bounds__(DIAG_THREADS) void batch_kernel(BatchArgs a) {
       A = stage;
       lda = n;
     }
-    if (OP == BATCH_FACTOR || OP == BATCH_GP) {
+    if (OP == BATCH_FACTOR || OP == BATCH_GP || OP == BATCH_FACTOR_REV) {
       if (threadIdx.x == 0) a.info[b] = 0;
       __syncthreads();
       batch_factor_one(n, A, lda, &a.info[b], slot, lds, bad);
+      if (OP == BATCH_FACTOR_REV) {  // the factor's block inverses are still in the slot
+        const int inf = a.info[b];
+        __syncthreads();
+        if (inf == 0) {
+          double *G = a.G[b];
+          int64_t ldg = a.ldg[b];
+          if (a.f32) {
+            stage_in_lower(n, reinterpret_cast<const float *>(a.G[b]), a.ldg[b], st2);
+            G = st2;
+            ldg = n;
+          }
+          batch_rev_one(n, A, lda, G, ldg, a.sbar_form, slot, lds);
+          if (a.f32) stage_out(n, st2, reinterpret_cast<float *>(a.G[b]), a.ldg[b]);
+        }
+      }
       if (OP == BATCH_GP) {
         const int inf = a.info[b];
         __syncthreads();

@@ -72,30 +72,52 @@ size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
   return c.off;
 }
 
-// Side stream for look-ahead: the diagonal-block chain of one step runs there while the next
-// step's bulk contraction runs on the caller's stream.  Created once per device on first use
-// (default priority, non-blocking) and kept for the life of the process; the mutex serialises
-// the enqueue sequences of concurrent callers so the shared events are never re-recorded
-// mid-sequence.
+// Side streams for look-ahead: the diagonal-block chain of one step runs there while the next
+// step's bulk contraction runs on the caller's stream.  One side stream (default priority,
+// non-blocking) and three events per (device, calling stream) pair, for up to SIDES_PER_DEVICE
+// calling streams per device; further calling streams share those slots round-robin, which only
+// costs overlap.  Created on first use and kept for the life of the process.  The mutex
+// serialises whole enqueue sequences, and every event wait of a call refers to a record made
+// earlier in the same call, so sharing a slot never mixes two calls' dependencies.
 struct Side {
   hipStream_t s = nullptr;
   hipEvent_t start = nullptr, panel = nullptr, diag = nullptr;
 };
 constexpr int MAX_DEVICES = 64;
+constexpr int SIDES_PER_DEVICE = 8;
+struct SideSlot {
+  bool used = false;
+  hipStream_t caller = nullptr;
+  Side side;
+};
 std::mutex g_side_mu;
-Side g_side[MAX_DEVICES];
+SideSlot g_sides[MAX_DEVICES][SIDES_PER_DEVICE];
+int g_side_next[MAX_DEVICES];
 
-hipError_t side_for_current_device(Side **out) {
+hipError_t side_for(hipStream_t caller, Side **out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
-  Side &sd = g_side[dev];
+  SideSlot *slot = nullptr;
+  for (int i = 0; i < SIDES_PER_DEVICE && !slot; ++i)
+    if (g_sides[dev][i].used && g_sides[dev][i].caller == caller) slot = &g_sides[dev][i];
+  for (int i = 0; i < SIDES_PER_DEVICE && !slot; ++i)
+    if (!g_sides[dev][i].used) slot = &g_sides[dev][i];
+  if (!slot) {  // every slot taken by other calling streams: share one
+    slot = &g_sides[dev][g_side_next[dev]];
+    g_side_next[dev] = (g_side_next[dev] + 1) % SIDES_PER_DEVICE;
+  }
+  Side &sd = slot->side;
   if (!sd.s) {
     if ((e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&sd.start, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&sd.panel, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&sd.diag, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  if (!slot->used) {
+    slot->used = true;
+    slot->caller = caller;
   }
   *out = &sd;
   return hipSuccess;
@@ -273,7 +295,8 @@ int run_batched(cg::BatchArgs a, int64_t n_max, void *workspace, size_t workspac
     case cg::BATCH_FACTOR: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FACTOR>, grid, block, 0, s, a); break;
     case cg::BATCH_REV: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_REV>, grid, block, 0, s, a); break;
     case cg::BATCH_FWD: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FWD>, grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_GP>, grid, block, 0, s, a); break;
+    case cg::BATCH_GP: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_GP>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FACTOR_REV>, grid, block, 0, s, a); break;
   }
   CG_TRY(hipGetLastError());
   return CHOL_SUCCESS;
@@ -373,7 +396,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
 
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
-  CG_TRY(side_for_current_device(&side));
+  CG_TRY(side_for(s, &side));
   hipStream_t s2 = side->s;
 
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
@@ -454,7 +477,7 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   const int64_t nblk = cdiv(n, nb);
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
-  CG_TRY(side_for_current_device(&side));
+  CG_TRY(side_for(s, &side));
   hipStream_t s2 = side->s;
   hipLaunchKernelGGL(cg::set_int_kernel, dim3(1), dim3(1), 0, s, info, 0);
   CG_TRY(hipGetLastError());
@@ -520,7 +543,7 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   const int64_t nblk = cdiv(n, nb);
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
-  CG_TRY(side_for_current_device(&side));
+  CG_TRY(side_for(s, &side));
   hipStream_t s2 = side->s;
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
                      ldl, ws.dinv);
@@ -635,6 +658,26 @@ int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *con
   cg::BatchArgs a{};
   a.op = cg::BATCH_FWD; a.batch = batch; a.f32 = precision == CHOL_PREC_F32; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
   a.ldl = ldl; a.A = reinterpret_cast<double *const *>(A); a.lda = lda;
+  return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int chol_factor_rev_batched(int precision, int batch, const int64_t *n, void *const *A, const int64_t *lda,
+                            void *const *G, const int64_t *ldg, int64_t n_max, int sbar_form, int *info,
+                            void *workspace, size_t workspace_bytes, void *stream) {
+  int rc = batched_common_checks(precision, batch, n_max);
+  if (rc != CHOL_SUCCESS) return rc;
+  if (batch == 0) return CHOL_SUCCESS;
+  if (!n) return -3;
+  if (!A) return -4;
+  if (!lda) return -5;
+  if (!G) return -6;
+  if (!ldg) return -7;
+  if (sbar_form != CHOL_SBAR_SYM && sbar_form != CHOL_SBAR_TRIL) return -9;
+  if (!info) return -10;
+  cg::BatchArgs a{};
+  a.op = cg::BATCH_FACTOR_REV; a.batch = batch; a.f32 = precision == CHOL_PREC_F32; a.n = n;
+  a.A = reinterpret_cast<double *const *>(A); a.lda = lda; a.G = reinterpret_cast<double *const *>(G);
+  a.ldg = ldg; a.sbar_form = sbar_form; a.info = info;
   return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 

@@ -23,6 +23,7 @@ SEED_SMALL = 1001      # dense N = 256 random-covariance case
 SEED_MEDIUM = 1002     # N = 4096 squared-exponential kernel, 3-D inputs, lengthscale 0.3
 SEED_LARGE = 1003      # N = 16384 squared-exponential kernel, 3-D inputs, lengthscale 0.2
 SEED_BATCH = 1004      # 2048 matrices, N log-uniform in [16, 512]
+SEED_SERVE = 1005      # serving stream: Poisson arrivals, N log-uniform in [64, 4096]
 
 
 def lower_normal(N, rng):
@@ -148,6 +149,27 @@ def se_case_device(N, seed, lengthscale, nugget, device, dim=3, with_sdot=True):
     if with_sdot:
         out["Sdot"] = torch.randn((N, N), dtype=torch.float64, device=device, generator=g).tril_()
     return out
+
+
+def serve_trace(rate=200.0, seconds=60.0, lo=64, hi=4096, seed=SEED_SERVE):
+    """Request stream of the serving workload: Poisson arrivals (exponential gaps at `rate` per
+    second) during `seconds`; per request n log-uniform in [lo, hi], a lengthscale U[0.1, 0.5]
+    and a seed for its inputs (see se_request_device)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.5) + 64)
+    t = np.cumsum(gaps)
+    t = t[t < seconds]
+    m = len(t)
+    n = np.clip(np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=m))).astype(np.int64), lo, hi)
+    return {"t": t, "n": n, "lengthscale": rng.uniform(0.1, 0.5, size=m),
+            "seed": rng.integers(1, 2 ** 31 - 1, size=m)}
+
+
+def se_request_device(n, lengthscale, seed, device):
+    """One serving request's inputs on the device: Sigma = SE kernel on n points uniform in [0,1]^2
+    (unit variance) + 1e-3 I, and L-bar = tril(N(0,1)) (float64, the se_case_device recipe)."""
+    c = se_case_device(int(n), int(seed), float(lengthscale), 1e-3, device, dim=2, with_sdot=False)
+    return c["Sigma"], c["Lbar"]
 
 
 def large_case_device(device, N=16384, seed=SEED_LARGE, with_sdot=True):
