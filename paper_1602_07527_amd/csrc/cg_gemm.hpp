@@ -210,14 +210,18 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Fast path for tile-aligned products (M, N multiples of 128; every K-chunk a multiple of 32;
+// Fast path for tile-aligned products (M, N multiples of 128; every K-chunk a multiple of 16;
 // leading dimensions even and A, B 16-byte aligned): eight wave64s (2 x 4, each 64 x 32 of the
-// 128 x 128 tile, two waves per SIMD) and gfx950's direct global->LDS loads
-// (global_load_lds_dwordx4) into a two-stage ring of 32-deep K-tiles, so no registers stage the
-// operands.  Operands that are contiguous along K are stored with their 16-byte chunks XOR-swizzled
-// by row, which keeps the MFMA fragment reads free of LDS bank conflicts.
+// 128 x 128 tile) and gfx950's direct global->LDS loads (global_load_lds_dwordx4) into a two-stage
+// ring of 16-deep K-tiles, so no registers stage the operands.  64 KB of LDS per workgroup lets two
+// workgroups share a compute unit (four waves per SIMD).  Operands that are contiguous along K are
+// stored with their 16-byte chunks XOR-swizzled by row, and each lane reads two consecutive k of
+// such an operand with one 16-byte LDS read that feeds two consecutive MFMAs: the k of MFMA
+// 2u + h for the lanes of slot s (= lane / 16) is 8u + 2s + h, which covers every k of the tile
+// once and lets 8 lanes of a read pass hit 8 distinct 16-byte bank groups.
 typedef __attribute__((address_space(3))) void lds_void;
-constexpr int DMA_BK = 32;
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+constexpr int DMA_BK = 16;
 constexpr int DMA_THREADS = 512;
 
 __host__ __device__ constexpr int waitcnt_vm(int n) {  // s_waitcnt immediate: vmcnt(n) only
@@ -225,12 +229,13 @@ __host__ __device__ constexpr int waitcnt_vm(int n) {  // s_waitcnt immediate: v
 }
 
 template <bool AT, bool BT, int TAG, int CP = CP_F64>
-__global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
+__global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p) {
   typedef Mfma<CP> MM;
   constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = DMA_BK, TILE = BM * BK;
   constexpr int WM = 2, WN = 4, NW = WM * WN;
   constexpr int NQ = TILE * 8 / 1024 / NW;     // 1 KB DMA instructions per wave per operand per tile
   static_assert(NQ * NW * 1024 == TILE * 8, "tile must split evenly over the waves");
+  static_assert(BK % 8 == 0, "paired fragment reads take k in groups of 8");
   constexpr int CH = BK / 2;                   // 16-byte chunks in a K-contiguous row
   constexpr int RPI = 64 / CH;                 // K-contiguous rows per DMA instruction
   constexpr int TMW = BM / WM / 16, TNW = BN / WN / 16;
@@ -303,24 +308,29 @@ __global__ __launch_bounds__(DMA_THREADS) void gemm_f64_dma_kernel(GemmArgs p) {
     const double *as = smem + (2 * (kt & 1)) * TILE;
     const double *bs = smem + (2 * (kt & 1) + 1) * TILE;
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int k = kk + fk;
-      double af[TMW], bf[TNW];
+    for (int u = 0; u < BK / 8; ++u) {
+      const int g = 4 * u + fk;      // this lane's 16-byte chunk along k: k = 2g and 2g + 1
+      const int k0 = 2 * g;
+      dbl2v af[TMW], bf[TNW];
 #pragma unroll
       for (int t = 0; t < TMW; ++t) {
         const int m = wm * (BM / WM) + t * 16 + fi;
-        af[t] = AT ? as[k * BM + m] : as[m * BK + (((k >> 1) ^ (m % CH)) << 1) + (k & 1)];
+        if (AT) af[t] = dbl2v{as[k0 * BM + m], as[(k0 + 1) * BM + m]};
+        else af[t] = *(const dbl2v *)&as[m * BK + ((g ^ (m % CH)) << 1)];
       }
 #pragma unroll
       for (int t = 0; t < TNW; ++t) {
         const int n = wn * (BN / WN) + t * 16 + fi;
-        bf[t] = BT ? bs[n * BK + (((k >> 1) ^ (n % CH)) << 1) + (k & 1)] : bs[k * BN + n];
+        if (BT) bf[t] = *(const dbl2v *)&bs[n * BK + ((g ^ (n % CH)) << 1)];
+        else bf[t] = dbl2v{bs[k0 * BN + n], bs[(k0 + 1) * BN + n]};
       }
 #pragma unroll
-      for (int a = 0; a < TMW; ++a)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int b = 0; b < TNW; ++b)
-          acc[a][b] = MM::step(af[a], bf[b], acc[a][b]);
+        for (int a = 0; a < TMW; ++a)
+#pragma unroll
+          for (int b = 0; b < TNW; ++b)
+            acc[a][b] = MM::step(af[a][h], bf[b][h], acc[a][b]);
     }
   }
 
