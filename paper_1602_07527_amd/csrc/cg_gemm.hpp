@@ -350,6 +350,54 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
       }
 }
 
+// The same sum for many splits of a small output: each element is shared by RG_GROUPS threads,
+// thread g summing splits g, g + RG_GROUPS, g + 2 RG_GROUPS, ... in that order, and the group sums
+// are then added in group order; the order is fixed, so the result is bitwise reproducible.
+// Blocks of 256 threads cover 256 / RG_GROUPS consecutive elements.
+constexpr int RG_GROUPS = 8;
+constexpr int RG_ELEMS = 256 / RG_GROUPS;
+__global__ __launch_bounds__(256) void reduce_splits_grouped_kernel(int M, int N, const double *P, int64_t ldp,
+                                                                    int64_t sstride, int S, double alpha,
+                                                                    const double *Cin, int64_t ldcin,
+                                                                    double beta, double *C, int64_t ldc,
+                                                                    double *Cm, int64_t ldcm, int lower_only) {
+  __shared__ double red[RG_GROUPS][RG_ELEMS];
+  const int el = threadIdx.x % RG_ELEMS, g = threadIdx.x / RG_ELEMS;
+  const int64_t total = (int64_t)M * N;
+  for (int64_t e0 = (int64_t)blockIdx.x * RG_ELEMS; e0 < total; e0 += (int64_t)gridDim.x * RG_ELEMS) {
+    const int64_t e = e0 + el;
+    double s = 0.0;
+    if (e < total) {
+      const int m = (int)(e / N), n = (int)(e % N);
+      const double *src = P + (int64_t)m * ldp + n;
+      int z = g;
+      for (; z + 3 * RG_GROUPS < S; z += 4 * RG_GROUPS) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = src[(int64_t)(z + u * RG_GROUPS) * sstride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += v[u];
+      }
+      for (; z < S; z += RG_GROUPS) s += src[(int64_t)z * sstride];
+    }
+    red[g][el] = s;
+    __syncthreads();
+    if (g == 0 && e < total) {
+      const int m = (int)(e / N), n = (int)(e % N);
+      double t = red[0][el];
+#pragma unroll
+      for (int q = 1; q < RG_GROUPS; ++q) t += red[q][el];
+      if (!(lower_only && n > m)) {
+        double v = alpha * t;
+        if (beta != 0.0) v += beta * Cin[(int64_t)m * ldcin + n];
+        C[(int64_t)m * ldc + n] = v;
+        if (Cm) Cm[(int64_t)n * ldcm + m] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // C[m, n] = alpha * sum_{s < S} P[s*sstride + m*ldp + n] + beta * Cin[m, n], summed in split order;
 // lower_only restricts the writes to n <= m.  Optional transposed copy Cm as in the GEMM.  Eight
 // partial loads are kept in flight per thread; the additions stay in split order, so the result

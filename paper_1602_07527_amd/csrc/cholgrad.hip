@@ -229,6 +229,13 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || S == 1) return e;
   const int64_t total = (int64_t)M * N;
+  if (S >= 4 * cg::RG_GROUPS && total <= (int64_t)64 * 1024) {  // many splits of a small output
+    const int blocks = (int)std::min<int64_t>(cdiv(total, cg::RG_ELEMS), 4096);
+    hipLaunchKernelGGL(cg::reduce_splits_grouped_kernel, dim3(blocks), dim3(256), 0, s, M, N, part,
+                       (int64_t)N, (int64_t)M * N, S, alpha, Cin, ldcin, beta, C, ldc, Cm, ldcm,
+                       lower_only);
+    return hipGetLastError();
+  }
   const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 4096);
   hipLaunchKernelGGL(cg::reduce_splits_kernel, dim3(blocks), dim3(256), 0, s, M, N, part, (int64_t)N,
                      (int64_t)M * N, S, alpha, Cin, ldcin, beta, C, ldc, Cm, ldcm, lower_only);
@@ -411,8 +418,8 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   // B-bar / R-bar updates then collapse to one product:
   //   C-bar = L-bar_C - (T + T^T)[k:, k:] L[k:, j:k] = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k].
   // Look-ahead: the rows of that product below block b+1 need only block b+1's panel, so they run
-  // on the caller's stream while block b+1's SYRK and diagonal adjoint run on the side stream;
-  // only block b+1's own rows wait for its diagonal block.
+  // on the caller's stream while block b+1's diagonal adjoint runs on the side stream; only block
+  // b+1's own rows wait for its diagonal block.
   for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
@@ -426,20 +433,25 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
                     A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0,
                     ws.part, 256, s, 1, cp));
       CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
+      // From here to the next diagonal adjoint every product is on the sweep's critical path and
+      // has a single 128-wide tile column: fine K-splits spread it over many compute units.
       CG_TRY(gemm(false, false, m1, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
-                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 256, s, 1, cp));
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 64, s, 1, cp));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
       // triangles.
       CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0,
-                  0.0, A + k * lda + j, lda, A + j * lda + k, lda, 0, nullptr, 128, s));
-      CG_TRY(hipEventRecord(side->panel, s));
-      CG_TRY(hipStreamWaitEvent(s2, side->panel, 0));
-      // D-bar = tril(L-bar_D) - tril(C-bar^T C), C-bar = 2 * A[k:, j:k]   -> dblk (w x w)
+                  0.0, A + k * lda + j, lda, A + j * lda + k, lda, 0, ws.part, 32, s));
+      // D-bar = tril(L-bar_D) - tril(C-bar^T C), C-bar = 2 * A[k:, j:k]   -> dblk (w x w).  On the
+      // caller's stream, before the next step's bulk product is queued: a small split-K product
+      // that runs fastest with the whole GPU to itself, and the diagonal adjoint released after
+      // it then finds a free compute unit while that bulk product runs.
       CG_TRY(gemm(true, false, w, w, m, A + k * lda + j, lda, L + k * ldl + j, ldl, -2.0,
-                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part2, 256, s2, 0, cp));
+                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part, 64, s, 0, cp));
     } else {
-      CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s2));
+      CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s));
     }
+    CG_TRY(hipEventRecord(side->panel, s));
+    CG_TRY(hipStreamWaitEvent(s2, side->panel, 0));
     hipLaunchKernelGGL(cg::diag_rev_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w,
                        L + j * ldl + j, ldl, (const double *)ws.dblk, (int64_t)nb,
                        (const double *)(ws.dinv + b * nb * nb), nb, A + j * lda + j, lda);
