@@ -5,6 +5,11 @@
 //
 //   C[m, n] = alpha * sum_k A(m, k) B(k, n) + beta * Cin[m, n]        (m < M, n < N, k < K)
 //
+// With a second operand pair (A2, B2 non-null) the sum runs over both pairs,
+//   C = alpha * (op(A) op(B) + op(A2) op(B2)) + beta * Cin,
+// as one K range of length 2K whose second half reads the second pair (the SYR2K-shaped updates
+// of the forward sweep: one launch and one pass over C instead of two).
+//
 // A(m, k) is read from A[m*lda + k] (AT = false) or A[k*lda + m] (AT = true); B(k, n) from
 // B[k*ldb + n] (BT = false) or B[n*ldb + k] (BT = true).  All matrices are row-major doubles.
 //
@@ -73,7 +78,14 @@ struct GemmArgs {
   int kchunk;           // K extent of one split (multiple of GEMM_BK)
   int64_t split_stride; // elements between the partial tiles of consecutive splits
   int lower_only;       // skip output tiles lying strictly above the diagonal (m < n throughout)
+  const double *A2;     // optional second pair, same shapes and transposition as (A, B)
+  int64_t lda2;
+  const double *B2;
+  int64_t ldb2;
 };
+
+// K extent of the combined range: K, or 2K with a second operand pair.
+__device__ __forceinline__ int gemm_k_total(const GemmArgs &p) { return p.A2 ? 2 * p.K : p.K; }
 
 constexpr int GEMM_LDS_A = GEMM_BK * (GEMM_BM + GEMM_PAD);   // doubles per A stage
 constexpr int GEMM_LDS_B = GEMM_BK * (GEMM_BN + GEMM_PAD);   // doubles per B stage
@@ -114,7 +126,10 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
       else     { k = e >> 7; m = e & 127; }     // contiguous along m
       const int gm = m0 + m, gk = k0 + k;
       double v = 0.0;
-      if (gm < p.M && gk < kend) v = AT ? p.A[(int64_t)gk * p.lda + gm] : p.A[(int64_t)gm * p.lda + gk];
+      if (gm < p.M && gk < kend) {
+        if (gk < p.K) v = AT ? p.A[(int64_t)gk * p.lda + gm] : p.A[(int64_t)gm * p.lda + gk];
+        else v = AT ? p.A2[(int64_t)(gk - p.K) * p.lda2 + gm] : p.A2[(int64_t)gm * p.lda2 + (gk - p.K)];
+      }
       ra[it] = v;
     }
 #pragma unroll
@@ -125,7 +140,10 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
       else     { n = e >> 4; k = e & 15; }      // contiguous along k
       const int gn = n0 + n, gk = k0 + k;
       double v = 0.0;
-      if (gn < p.N && gk < kend) v = BT ? p.B[(int64_t)gn * p.ldb + gk] : p.B[(int64_t)gk * p.ldb + gn];
+      if (gn < p.N && gk < kend) {
+        if (gk < p.K) v = BT ? p.B[(int64_t)gn * p.ldb + gk] : p.B[(int64_t)gk * p.ldb + gn];
+        else v = BT ? p.B2[(int64_t)gn * p.ldb2 + (gk - p.K)] : p.B2[(int64_t)(gk - p.K) * p.ldb2 + gn];
+      }
       rb[it] = v;
     }
   };
@@ -205,7 +223,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_f64_kernel(GemmArgs p) {
   if (p.lower_only && m0 + GEMM_BM - 1 < n0) return;  // whole tile strictly above the diagonal
   const int z = blockIdx.z;
   const int kbeg = z * p.kchunk;
-  const int kend = min(p.K, kbeg + p.kchunk);
+  const int kend = min(gemm_k_total(p), kbeg + p.kchunk);
   gemm_tile<AT, BT, CP>(p, m0, n0, kbeg, kend, p.C + (int64_t)z * p.split_stride, lds);
 }
 
@@ -228,7 +246,7 @@ __host__ __device__ constexpr int waitcnt_vm(int n) {  // s_waitcnt immediate: v
   return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
 }
 
-template <bool AT, bool BT, int TAG, int CP = CP_F64>
+template <bool AT, bool BT, int TAG, int CP = CP_F64, bool P2 = false>
 __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p) {
   typedef Mfma<CP> MM;
   constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = DMA_BK, TILE = BM * BK;
@@ -246,47 +264,55 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
   if (p.lower_only && m0 + BM - 1 < n0) return;
   const int z = blockIdx.z;
   const int kbeg = z * p.kchunk;
-  const int kend = min(p.K, kbeg + p.kchunk);
+  const int kend = min(P2 ? 2 * p.K : p.K, kbeg + p.kchunk);
   const int nkt = (kend > kbeg) ? (kend - kbeg) / BK : 0;
   double *Cout = p.C + (int64_t)z * p.split_stride;
 
-  // Loop-invariant per-lane byte offsets inside a tile; the tile bases advance uniformly.
-  uint32_t offA[NQ], offB[NQ];
+  // Loop-invariant per-lane byte offsets inside a tile (per operand pair); the tile bases are
+  // wave-uniform.  K is a multiple of BK, so no K-tile straddles the two pairs.  P2 (a second
+  // operand pair, in A2 and B2) is a template parameter so single products carry no pair logic.
+  constexpr int NP = P2 ? 2 : 1;
+  uint32_t offA[NP][NQ], offB[NP][NQ];
   int ldsA[NQ], ldsB[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int i = wave * NQ + q;
-    if (!AT) {
-      const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
-      offA[q] = (uint32_t)(r * p.lda * 8 + c * 16);
-      ldsA[q] = i * RPI * BK;
-    } else {
-      offA[q] = (uint32_t)(i * p.lda * 8 + lane * 16);
-      ldsA[q] = i * BM;
-    }
-    if (!BT) {
-      offB[q] = (uint32_t)(i * p.ldb * 8 + lane * 16);
-      ldsB[q] = i * BN;
-    } else {
-      const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
-      offB[q] = (uint32_t)(r * p.ldb * 8 + c * 16);
-      ldsB[q] = i * RPI * BK;
+  for (int h = 0; h < NP; ++h) {
+    const int64_t la = h ? p.lda2 : p.lda, lb = h ? p.ldb2 : p.ldb;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = wave * NQ + q;
+      if (!AT) {
+        const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
+        offA[h][q] = (uint32_t)(r * la * 8 + c * 16);
+        ldsA[q] = i * RPI * BK;
+      } else {
+        offA[h][q] = (uint32_t)(i * la * 8 + lane * 16);
+        ldsA[q] = i * BM;
+      }
+      if (!BT) {
+        offB[h][q] = (uint32_t)(i * lb * 8 + lane * 16);
+        ldsB[q] = i * BN;
+      } else {
+        const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
+        offB[h][q] = (uint32_t)(r * lb * 8 + c * 16);
+        ldsB[q] = i * RPI * BK;
+      }
     }
   }
-  const char *baseA = (const char *)(AT ? p.A + (int64_t)kbeg * p.lda + m0 : p.A + (int64_t)m0 * p.lda + kbeg);
-  const char *baseB = (const char *)(BT ? p.B + (int64_t)n0 * p.ldb + kbeg : p.B + (int64_t)kbeg * p.ldb + n0);
-  const int64_t stepA = AT ? (int64_t)BK * p.lda * 8 : BK * 8;
-  const int64_t stepB = BT ? BK * 8 : (int64_t)BK * p.ldb * 8;
 
   auto issue = [&](int kt, int st) {
-    const char *ga = baseA + kt * stepA;
-    const char *gb = baseB + kt * stepB;
+    const int kg = kbeg + kt * BK;                 // position in the combined K range
+    const int h = (P2 && kg >= p.K) ? 1 : 0;       // operand pair (wave-uniform)
+    const int kl = kg - h * p.K;
+    const double *Ab = h ? p.A2 : p.A, *Bb = h ? p.B2 : p.B;
+    const int64_t la = h ? p.lda2 : p.lda, lb = h ? p.ldb2 : p.ldb;
+    const char *ga = (const char *)(AT ? Ab + (int64_t)kl * la + m0 : Ab + (int64_t)m0 * la + kl);
+    const char *gb = (const char *)(BT ? Bb + (int64_t)n0 * lb + kl : Bb + (int64_t)kl * lb + n0);
     double *as = smem + (2 * st) * TILE;
     double *bs = smem + (2 * st + 1) * TILE;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      __builtin_amdgcn_global_load_lds((const void *)(ga + offA[q]), (lds_void *)(as + ldsA[q]), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds((const void *)(gb + offB[q]), (lds_void *)(bs + ldsB[q]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(ga + offA[P2 ? h : 0][q]), (lds_void *)(as + ldsA[q]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)(gb + offB[P2 ? h : 0][q]), (lds_void *)(bs + ldsB[q]), 16, 0, 0);
     }
   };
 

@@ -74,14 +74,14 @@ size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
 
 // Side streams for look-ahead: the diagonal-block chain of one step runs there while the next
 // step's bulk contraction runs on the caller's stream.  One side stream (default priority,
-// non-blocking) and three events per (device, calling stream) pair, for up to SIDES_PER_DEVICE
+// non-blocking) and five events per (device, calling stream) pair, for up to SIDES_PER_DEVICE
 // calling streams per device; further calling streams share those slots round-robin, which only
 // costs overlap.  Created on first use and kept for the life of the process.  The mutex
 // serialises whole enqueue sequences, and every event wait of a call refers to a record made
 // earlier in the same call, so sharing a slot never mixes two calls' dependencies.
 struct Side {
   hipStream_t s = nullptr;
-  hipEvent_t start = nullptr, panel = nullptr, diag = nullptr;
+  hipEvent_t start = nullptr, panel = nullptr, diag = nullptr, top = nullptr, low = nullptr;
 };
 constexpr int MAX_DEVICES = 64;
 constexpr int SIDES_PER_DEVICE = 8;
@@ -114,6 +114,8 @@ hipError_t side_for(hipStream_t caller, Side **out) {
     if ((e = hipEventCreateWithFlags(&sd.start, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&sd.panel, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&sd.diag, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.top, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.low, hipEventDisableTiming)) != hipSuccess) return e;
   }
   if (!slot->used) {
     slot->used = true;
@@ -136,6 +138,14 @@ bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0
 
 template <int TAG, int CP>
 void launch_gemm_tag(bool at, bool bt, bool fast, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+  if (fast && p.A2) {  // paired products (the forward sweep's symmetric updates: B transposed)
+    const dim3 block(cg::DMA_THREADS);
+    if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, true, TAG, CP, true>), grid, block, 0, s, p);
+    else if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, false, TAG, CP, true>), grid, block, 0, s, p);
+    else if (!at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, false, TAG, CP, true>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, true, TAG, CP, true>), grid, block, 0, s, p);
+    return;
+  }
   if (fast) {
     const dim3 block(cg::DMA_THREADS);
     if (at && !bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<true, false, TAG, CP>), grid, block, 0, s, p);
@@ -172,34 +182,49 @@ bool aligned16(const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u
 // C = alpha * op(A) op(B) + beta * Cin on the MFMA kernel; splits K when the output has too few
 // tiles to fill the GPU, then sums the partial tiles in split order.  part == nullptr forbids
 // splitting.
+// Optional second operand pair of a contraction (same shapes and transposition as the first).
+struct Pair2 {
+  const double *A2 = nullptr;
+  int64_t lda2 = 0;
+  const double *B2 = nullptr;
+  int64_t ldb2 = 0;
+};
+
+bool dma_ld_ok(int64_t ld) { return ld % 2 == 0 && ld < ((int64_t)1 << 21); }
+
 hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t lda,
                 const double *B, int64_t ldb, double alpha, const double *Cin, int64_t ldcin,
                 double beta, double *C, int64_t ldc, double *Cm, int64_t ldcm, int lower_only,
-                double *part, int min_kchunk, hipStream_t s, int tag = 0, int cp = cg::CP_F64) {
+                double *part, int min_kchunk, hipStream_t s, int tag = 0, int cp = cg::CP_F64,
+                Pair2 q = Pair2()) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, cg::GEMM_BN);
   int tiles = tm * tn;
   if (lower_only && tm == tn) tiles = (tm * (tm + 1)) / 2;
-  // The direct-to-LDS kernel needs whole 128 x 128 output tiles, whole 32-deep K-tiles in every
-  // split, even leading dimensions and 16-byte aligned operands (its 16-byte loads never cross
-  // the matrix); everything else takes the general kernel, which guards every access.
+  const int Kt = q.A2 ? 2 * K : K;  // combined K range
+  // The direct-to-LDS kernel needs whole 128 x 128 output tiles, whole 16-deep K-tiles in every
+  // split (and in each operand pair), even leading dimensions below 2^21 (32-bit lane offsets)
+  // and 16-byte aligned operands (its 16-byte loads never cross the matrix); everything else
+  // takes the general kernel, which guards every access.
   const bool fast = (M % cg::GEMM_BM == 0) && (N % cg::GEMM_BN == 0) && (K > 0) && (K % cg::DMA_BK == 0) &&
-                    (lda % 2 == 0) && (ldb % 2 == 0) && aligned16(A) && aligned16(B);
+                    dma_ld_ok(lda) && dma_ld_ok(ldb) && aligned16(A) && aligned16(B) &&
+                    (!q.A2 || (dma_ld_ok(q.lda2) && dma_ld_ok(q.ldb2) && aligned16(q.A2) && aligned16(q.B2)));
   const int kstep = fast ? cg::DMA_BK : cg::GEMM_BK;
   int S = 1;
-  int kchunk = (int)(cdiv(K > 0 ? K : 1, kstep) * kstep);
-  if (part && K > 0) {
+  int kchunk = (int)(cdiv(Kt > 0 ? Kt : 1, kstep) * kstep);
+  if (part && Kt > 0) {
     int64_t s_want = TARGET_WGS / tiles;
-    s_want = std::min<int64_t>(s_want, cdiv(K, min_kchunk));
+    s_want = std::min<int64_t>(s_want, cdiv(Kt, min_kchunk));
     s_want = std::min<int64_t>(s_want, PART_ELEMS / ((int64_t)M * N));
     if (s_want > 1) {
-      kchunk = (int)(cdiv(cdiv(K, s_want), kstep) * kstep);
-      S = (int)cdiv(K, kchunk);
+      kchunk = (int)(cdiv(cdiv(Kt, s_want), kstep) * kstep);
+      S = (int)cdiv(Kt, kchunk);
     }
   }
   cg::GemmArgs p;
   p.M = M; p.N = N; p.K = K;
   p.A = A; p.lda = lda; p.B = B; p.ldb = ldb;
+  p.A2 = q.A2; p.lda2 = q.A2 ? q.lda2 : 0; p.B2 = q.A2 ? q.B2 : nullptr; p.ldb2 = q.A2 ? q.ldb2 : 0;
   p.kchunk = kchunk;
   p.lower_only = lower_only;
   const dim3 grid(tm, tn, S);
@@ -215,11 +240,11 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
     const int u = g_prof.used;
     if (hipEventRecord(g_prof.ev[2 * u], s) != hipSuccess) return hipErrorUnknown;
     g_prof.klass[u] = tag;
-    g_prof.flops[u] = 2.0 * (double)M * (double)N * (double)K;
+    g_prof.flops[u] = 2.0 * (double)M * (double)N * (double)Kt;
     // Algorithmic HBM bytes of the contraction: read op(A), op(B) and Cin once, write C (and
     // its mirror) once; split-K partials are not counted.
     const double mn = (double)M * (double)N * (lower_only ? 0.5 : 1.0);
-    g_prof.bytes[u] = 8.0 * ((double)M * K + (double)K * N + mn * ((beta != 0.0 ? 2.0 : 1.0) + (Cm ? 1.0 : 0.0)));
+    g_prof.bytes[u] = 8.0 * ((double)M * Kt + (double)Kt * N + mn * ((beta != 0.0 ? 2.0 : 1.0) + (Cm ? 1.0 : 0.0)));
   }
   launch_gemm(at, bt, fast, tag, cp, grid, p, s);
   if (timed) {
@@ -495,33 +520,53 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   CG_TRY(hipGetLastError());
   CG_TRY(hipEventRecord(side->start, s));
   CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
-  // Sec. 4.2 chol_blocked, left to right, with look-ahead: the update of block column b over the
-  // columns left of block b-1 runs on the caller's stream while block b-1's diagonal factor and
-  // panel solve run on the side stream; only the K = nb slice over block b-1 waits for them.
+  // Sec. 4.2 chol_blocked, left to right, with look-ahead.  Block b's diagonal factor needs only
+  // block b's own rows updated, and those need only the rows of block b-1's panel solve that lie
+  // in block b; so the chain from one diagonal factor to the next is: panel solve of the next
+  // block's rows (side stream) -> update of those rows over block b-1's columns (caller's stream)
+  // -> POTF2.  Everything else -- the update over older columns, the rows below, their panel
+  // solve -- runs beside it.  Events: diag (own rows updated), low (rows below updated), top (own
+  // rows of the next block solved), panel (whole panel solved).
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
     const int m = (int)(n - k);
     if (b > 0) {
       const int64_t jp = j - nb;  // block b-1 is [jp, j)
-      // [D; C] <- [D; C] - [R; B] R^T   (D - tril(R R^T) and C - B R^T in one product)
+      // [D; C] <- [D; C] - [R; B] R^T over the columns left of block b-1 (all rows below j)
       if (jp > 0)
         CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, A + j * lda, lda, -1.0,
                     A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
-      CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
-      CG_TRY(gemm(false, true, (int)(n - j), w, nb, A + j * lda + jp, lda, A + j * lda + jp, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
+      // D <- D - D_{b,b-1} D_{b,b-1}^T   (chain: fine K-splits)
+      CG_TRY(hipStreamWaitEvent(s, side->top, 0));
+      CG_TRY(gemm(false, true, w, w, nb, A + j * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + j * lda + j,
+                  lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 2, cp));
       CG_TRY(hipEventRecord(side->diag, s));
       CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
+      // C <- C - B_{b-1} D_{b,b-1}^T   (rows below block b)
+      if (m > 0) {
+        CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+        CG_TRY(gemm(false, true, m, w, nb, A + k * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + k * lda + j,
+                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
+        CG_TRY(hipEventRecord(side->low, s));
+      }
     }
     // D <- chol_unblocked(D); D^-1 for the panel solve
     hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, A + j * lda + j, lda,
                        ws.dblk, nb, info, j);
     CG_TRY(hipGetLastError());
-    // C <- C tril(D)^-T   (every output tile spans all w <= 128 columns, so in place is safe)
-    if (m > 0)
-      CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
-                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+    // C <- C tril(D)^-T, the next block's rows first (every output tile spans all w <= 128
+    // columns, so in place is safe)
+    if (m > 0) {
+      const int m1 = std::min(m, nb);
+      if (b > 0) CG_TRY(hipStreamWaitEvent(s2, side->low, 0));
+      CG_TRY(gemm(false, true, m1, w, w, A + k * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
+                  A + k * lda + j, lda, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(hipEventRecord(side->top, s2));
+      if (m > m1)
+        CG_TRY(gemm(false, true, m - m1, w, w, A + (k + m1) * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
+                    A + (k + m1) * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+    }
     CG_TRY(hipEventRecord(side->panel, s2));
   }
   CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
@@ -562,38 +607,57 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   CG_TRY(hipGetLastError());
   CG_TRY(hipEventRecord(side->start, s));
   CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
-  // Sec. 4.2 chol_blocked_fwd, left to right, with the same look-ahead as chol_factor.
+  // Sec. 4.2 chol_blocked_fwd, left to right, with the same look-ahead as chol_factor: the chain
+  // is panel step of the next block's rows -> update of those rows over block b-1's columns ->
+  // diagonal block, everything else beside it.
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
     const int m = (int)(n - k);
     if (b > 0) {
       const int64_t jp = j - nb;
-      // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T   over columns [0, jp), then [jp, j)
-      if (jp > 0) {
+      // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T   over columns [0, jp)
+      // (one launch: the two products share the output as one combined K range)
+      if (jp > 0)
         CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, L + j * ldl, ldl, -1.0,
-                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
-        CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, L + j * ldl, ldl, A + j * lda, lda, -1.0,
-                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
-      }
-      CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
-      CG_TRY(gemm(false, true, (int)(n - j), w, nb, A + j * lda + jp, lda, L + j * ldl + jp, ldl, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
-      CG_TRY(gemm(false, true, (int)(n - j), w, nb, L + j * ldl + jp, ldl, A + j * lda + jp, lda, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp));
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp,
+                    Pair2{L + j * ldl, ldl, A + j * lda, lda}));
+      // block b's own rows over columns [jp, j)   (chain: fine K-splits)
+      CG_TRY(hipStreamWaitEvent(s, side->top, 0));
+      CG_TRY(gemm(false, true, w, w, nb, A + j * lda + jp, lda, L + j * ldl + jp, ldl, -1.0, A + j * lda + j,
+                  lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
+                  Pair2{L + j * ldl + jp, ldl, A + j * lda + jp, lda}));
       CG_TRY(hipEventRecord(side->diag, s));
       CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
+      // rows below block b over columns [jp, j)
+      if (m > 0) {
+        CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+        CG_TRY(gemm(false, true, m, w, nb, A + k * lda + jp, lda, L + j * ldl + jp, ldl, -1.0, A + k * lda + j,
+                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp,
+                    Pair2{L + k * ldl + jp, ldl, A + j * lda + jp, lda}));
+        CG_TRY(hipEventRecord(side->low, s));
+      }
     }
     // D-dot <- chol_unblocked_fwd(D, D-dot)   (strict upper triangle of the block set to 0)
     hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, L + j * ldl + j,
                        ldl, (const double *)(ws.dinv + b * nb * nb), nb, A + j * lda + j, lda);
     CG_TRY(hipGetLastError());
     if (m > 0) {
-      // C-dot <- (C-dot - C D-dot^T) D^-T
-      CG_TRY(gemm(false, true, m, w, w, L + k * ldl + j, ldl, A + j * lda + j, lda, -1.0,
-                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, nullptr, 128, s2));
-      CG_TRY(gemm(false, true, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 1.0, nullptr, 0, 0.0,
-                  A + k * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+      // C-dot <- (C-dot - C D-dot^T) D^-T, the next block's rows first
+      const int m1 = std::min(m, nb);
+      if (b > 0) CG_TRY(hipStreamWaitEvent(s2, side->low, 0));
+      CG_TRY(gemm(false, true, m1, w, w, L + k * ldl + j, ldl, A + j * lda + j, lda, -1.0,
+                  A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(gemm(false, true, m1, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 1.0, nullptr, 0, 0.0,
+                  A + k * lda + j, lda, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(hipEventRecord(side->top, s2));
+      if (m > m1) {
+        CG_TRY(gemm(false, true, m - m1, w, w, L + (k + m1) * ldl + j, ldl, A + j * lda + j, lda, -1.0,
+                    A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0, nullptr,
+                    128, s2));
+        CG_TRY(gemm(false, true, m - m1, w, w, ws.panel + (int64_t)m1 * nb, nb, ws.dinv + b * nb * nb, nb, 1.0,
+                    nullptr, 0, 0.0, A + (k + m1) * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+      }
     }
     CG_TRY(hipEventRecord(side->panel, s2));
   }
