@@ -264,6 +264,26 @@ def main():
     if int((bat["info"] != 0).sum()) != 0 or not bool(torch.isfinite(bat["f"]).all()):
         raise RuntimeError("batched factorisation failed")
 
+    # chol_factor_fwd: potrf and the forward sweep in one pass, timed alone after one untimed pass.
+    fused = None
+    if args.mixed_steps > 0:
+        log("[bench] chol_factor_fwd (one sweep)")
+        fused_ms = 0.0
+        for i in range(args.mixed_steps + 1):
+            A.copy_(Sigma)
+            Ad.copy_(Sdot)
+            ev["f"][0].record()
+            cg.chol_factor_fwd(A, Ad, nb=nb, workspace=ws, info=info)
+            ev["f"][1].record()
+            torch.cuda.synchronize()
+            if i > 0:
+                fused_ms += ev["f"][0].elapsed_time(ev["f"][1]) / args.mixed_steps
+        if int(info.item()) != 0:
+            raise RuntimeError("chol_factor_fwd failed")
+        fused = {"chol_factor_fwd_ms": round(fused_ms, 3),
+                 "tflops": round(n ** 3 / (fused_ms * 1e-3) / 1e12, 3),
+                 "separate_ms": None}
+
     # The reduced-precision mode (trailing contractions on FP32 MFMA) on the same workload: the
     # three sweeps timed alone, after one untimed pass.
     mixed = None
@@ -363,6 +383,8 @@ def main():
 
     K = args.steps
     ms_step = (t1 - t0) * 1e3 / K
+    if fused is not None:
+        fused["separate_ms"] = round((times["f"] + times["d"]) / K, 3)
     f_rev = 2.0 / 3.0 * n ** 3
     f_fac = n ** 3 / 3.0
     rev_ms = times["r"] / K
@@ -399,6 +421,7 @@ def main():
         "roofline": roofline,
         "batched": batched,
         "batched_f32": batched_f32,
+        "factor_fwd_one_sweep": fused,
         "f64_trail_f32": mixed,
         "serving": serving,
     }

@@ -131,6 +131,21 @@ int chol_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int6
              void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * chol_factor_fwd -- chol_factor and chol_fwd in ONE left-to-right sweep (Sec. 4.2: the forward
+ * updates of chol_blocked_fwd accumulated during the factorisation, as the paper remarks they can
+ * be): at block column b every column to its left already holds its final L and L-dot, which is
+ * all both updates need, so L is read once and POTF2's block inverse serves the forward step.
+ *   A     in : tril(A) = tril(Sigma).      out: tril(A) = L; strict upper triangle set to 0.
+ *   D     in : tril(D) = tril(Sigma-dot).  out: tril(D) = L-dot; strict upper triangle set to 0.
+ *   info  as chol_factor (L-dot is undefined when info != 0).  A and D must not overlap.
+ *   Workspace: chol_workspace_bytes(CHOL_OP_FWD, ...).
+ *   Arguments: 1 precision, 2 n, 3 A, 4 lda, 5 D, 6 ldd, 7 nb, 8 info, 9 workspace,
+ *              10 workspace_bytes, 11 stream.
+ */
+int chol_factor_fwd(int precision, int64_t n, void *A, int64_t lda, void *D, int64_t ldd, int nb, int *info,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Batched forms: many independent problems in ONE persistent launch (Sec. 4.2 algorithms applied
  * per problem, nb = 128; a problem with n <= 128 is one diagonal block and stays in LDS).  All
  * per-problem arguments are DEVICE arrays with `batch` entries: n[b] is the size of problem b,

@@ -4,17 +4,18 @@ Public calls (torch tensors as device memory, work on the current stream):
   chol_factor(A)     Sigma -> L               (Sec. 4.2 chol_blocked)
   chol_rev(L, A)     L-bar -> Sigma-bar       (Sec. 4.2 chol_blocked_rev)
   chol_fwd(L, A)     Sigma-dot -> L-dot       (Sec. 4.2 chol_blocked_fwd)
+  chol_factor_fwd(A, D)  both in one sweep (Sigma -> L and Sigma-dot -> L-dot)
 and their batched forms (many matrices, n <= 512, one persistent launch), including a fused
 factor + reverse sweep (chol_factor_rev_batched) and a fused Gaussian-process loss
 (chol_gp_nll_batched: Sigma -> L -> f -> Sigma-bar per matrix).  `autograd` wraps them as
 torch.autograd Functions; `serve` runs a continuous-batching request loop on top of them.
 """
 from ._binding import (Batch, CholError, LIB_PATH, batched_workspace_bytes, chol_factor,
-                       chol_factor_batched, chol_factor_rev_batched, chol_fwd, chol_fwd_batched,
-                       chol_gp_nll_batched, chol_rev, chol_rev_batched, load_library, profile_begin,
-                       profile_end, workspace_bytes)
+                       chol_factor_batched, chol_factor_fwd, chol_factor_rev_batched, chol_fwd,
+                       chol_fwd_batched, chol_gp_nll_batched, chol_rev, chol_rev_batched, load_library,
+                       profile_begin, profile_end, workspace_bytes)
 
 __all__ = ["Batch", "CholError", "LIB_PATH", "batched_workspace_bytes", "chol_factor",
-           "chol_factor_batched", "chol_factor_rev_batched", "chol_fwd", "chol_fwd_batched",
-           "chol_gp_nll_batched", "chol_rev", "chol_rev_batched", "load_library", "profile_begin",
-           "profile_end", "workspace_bytes"]
+           "chol_factor_batched", "chol_factor_fwd", "chol_factor_rev_batched", "chol_fwd",
+           "chol_fwd_batched", "chol_gp_nll_batched", "chol_rev", "chol_rev_batched", "load_library",
+           "profile_begin", "profile_end", "workspace_bytes"]

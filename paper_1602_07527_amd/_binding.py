@@ -49,6 +49,8 @@ def load_library():
     lib.chol_rev.restype = i32
     lib.chol_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, sz, vp]
     lib.chol_fwd.restype = i32
+    lib.chol_factor_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, vp, sz, vp]
+    lib.chol_factor_fwd.restype = i32
     lib.chol_status_string.argtypes = [i32]
     lib.chol_status_string.restype = ctypes.c_char_p
     lib.chol_version.argtypes = []
@@ -153,6 +155,23 @@ def chol_fwd(L, A, nb=0, workspace=None, precision="f64"):
                                         A.data_ptr(), A.stride(0) if n else 1, nb, ws.data_ptr(),
                                         ws.numel(), _stream(A.device)))
     return A
+
+
+def chol_factor_fwd(A, D, nb=0, workspace=None, info=None, precision="f64"):
+    """In place, one sweep: tril(A) = Sigma -> L and tril(D) = tril(Sigma-dot) -> L-dot (strict
+    upper triangles set to 0).  Returns (A, D, info)."""
+    lib = load_library()
+    n = _square("A", A)
+    if _square("D", D) != n or D.device != A.device:
+        raise ValueError("A and D must have the same size and device")
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    ws = _workspace("fwd", n, nb, A.device, workspace, precision)
+    with torch.cuda.device(A.device):
+        _check("chol_factor_fwd", lib.chol_factor_fwd(_PRECS[precision], n, A.data_ptr(), A.stride(0) if n else 1,
+                                                      D.data_ptr(), D.stride(0) if n else 1, nb, info.data_ptr(),
+                                                      ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return A, D, info
 
 
 def profile_begin(max_launches=1 << 16):

@@ -673,6 +673,114 @@ static bool batched_prec_ok(int precision) {
   return precision == CHOL_PREC_F64 || precision == CHOL_PREC_F32;
 }
 
+int chol_factor_fwd(int precision, int64_t n, void *Av, int64_t lda, void *Dv, int64_t ldd, int nb, int *info,
+                    void *workspace, size_t workspace_bytes, void *stream) {
+  if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
+  int cp = cg::CP_F64;
+  if (!single_prec(precision, &cp)) return -1;
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!Av || !aligned8(Av)) return -3;
+  if (lda < n) return -4;
+  if (!Dv || !aligned8(Dv)) return -5;
+  if (ldd < n) return -6;
+  if (!nb_ok(nb)) return -7;
+  if (!info) return -8;
+  if (nb == 0) nb = DEFAULT_NB;
+  SweepWs ws;
+  const size_t need = carve(n, nb, nullptr, &ws);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
+    return CHOL_ERR_WORKSPACE;
+  carve(n, nb, workspace, &ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *A = static_cast<double *>(Av);   // Sigma -> L
+  double *D = static_cast<double *>(Dv);   // Sigma-dot -> L-dot
+  const int64_t nblk = cdiv(n, nb);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  Side *side = nullptr;
+  CG_TRY(side_for(s, &side));
+  hipStream_t s2 = side->s;
+  hipLaunchKernelGGL(cg::set_int_kernel, dim3(1), dim3(1), 0, s, info, 0);
+  CG_TRY(hipGetLastError());
+  CG_TRY(hipEventRecord(side->start, s));
+  CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
+  // One left-to-right sweep carrying both Sec. 4.2 chol_blocked and chol_blocked_fwd: when block
+  // column b is reached, every column left of it holds its final L and L-dot, which is all both
+  // updates need.  The chain and the look-ahead are those of chol_factor, with the forward
+  // diagonal block (which reuses POTF2's block inverse) and the forward panel step following
+  // the factor's on the side stream.
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
+    const int w = (int)(k - j);
+    const int m = (int)(n - k);
+    if (b > 0) {
+      const int64_t jp = j - nb;
+      if (jp > 0) {
+        CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, A + j * lda, lda, -1.0,
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
+        CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, D + j * ldd, ldd, A + j * lda, lda, -1.0,
+                    D + j * ldd + j, ldd, 1.0, D + j * ldd + j, ldd, nullptr, 0, 0, ws.part, 256, s, 3, cp,
+                    Pair2{A + j * lda, lda, D + j * ldd, ldd}));
+      }
+      // block b's own rows over columns [jp, j)   (chain)
+      CG_TRY(hipStreamWaitEvent(s, side->top, 0));
+      CG_TRY(gemm(false, true, w, w, nb, A + j * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + j * lda + j,
+                  lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 2, cp));
+      CG_TRY(gemm(false, true, w, w, nb, D + j * ldd + jp, ldd, A + j * lda + jp, lda, -1.0, D + j * ldd + j,
+                  ldd, 1.0, D + j * ldd + j, ldd, nullptr, 0, 0, ws.part, 32, s, 3, cp,
+                  Pair2{A + j * lda + jp, lda, D + j * ldd + jp, ldd}));
+      CG_TRY(hipEventRecord(side->diag, s));
+      CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
+      // rows below block b over columns [jp, j)
+      if (m > 0) {
+        CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+        CG_TRY(gemm(false, true, m, w, nb, A + k * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + k * lda + j,
+                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
+        CG_TRY(gemm(false, true, m, w, nb, D + k * ldd + jp, ldd, A + j * lda + jp, lda, -1.0, D + k * ldd + j,
+                    ldd, 1.0, D + k * ldd + j, ldd, nullptr, 0, 0, ws.part, 256, s, 3, cp,
+                    Pair2{A + k * lda + jp, lda, D + j * ldd + jp, ldd}));
+        CG_TRY(hipEventRecord(side->low, s));
+      }
+    }
+    // L_bb = chol_unblocked(D_bb) and its inverse; then L-dot_bb = chol_unblocked_fwd(L_bb, D-dot_bb)
+    hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, A + j * lda + j, lda,
+                       ws.dblk, nb, info, j);
+    CG_TRY(hipGetLastError());
+    hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, (const double *)(A + j * lda + j),
+                       lda, (const double *)ws.dblk, nb, D + j * ldd + j, ldd);
+    CG_TRY(hipGetLastError());
+    if (m > 0) {
+      // C <- C tril(L_bb)^-T;  C-dot <- (C-dot - C L-dot_bb^T) L_bb^-T   -- the next block's rows first
+      const int m1 = std::min(m, nb);
+      if (b > 0) CG_TRY(hipStreamWaitEvent(s2, side->low, 0));
+      CG_TRY(gemm(false, true, m1, w, w, A + k * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
+                  A + k * lda + j, lda, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(gemm(false, true, m1, w, w, A + k * lda + j, lda, D + j * ldd + j, ldd, -1.0,
+                  D + k * ldd + j, ldd, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(gemm(false, true, m1, w, w, ws.panel, nb, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
+                  D + k * ldd + j, ldd, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(hipEventRecord(side->top, s2));
+      if (m > m1) {
+        const int64_t kl = k + m1;
+        CG_TRY(gemm(false, true, m - m1, w, w, A + kl * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
+                    A + kl * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+        CG_TRY(gemm(false, true, m - m1, w, w, A + kl * lda + j, lda, D + j * ldd + j, ldd, -1.0,
+                    D + kl * ldd + j, ldd, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0, nullptr, 128, s2));
+        CG_TRY(gemm(false, true, m - m1, w, w, ws.panel + (int64_t)m1 * nb, nb, ws.dblk, nb, 1.0, nullptr, 0,
+                    0.0, D + kl * ldd + j, ldd, nullptr, 0, 0, nullptr, 128, s2));
+      }
+    }
+    CG_TRY(hipEventRecord(side->panel, s2));
+  }
+  CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+  const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
+  hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
+  CG_TRY(hipGetLastError());
+  hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, D, ldd);
+  CG_TRY(hipGetLastError());
+  return CHOL_SUCCESS;
+}
+
 size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max) {
   if (!batched_prec_ok(precision) || batch <= 0 || n_max < 0 || n_max > cg::BATCH_NMAX) return 0;
   BatchWs w;

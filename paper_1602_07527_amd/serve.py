@@ -13,18 +13,20 @@ Scheduling, one `step()` at a time on the host:
     footprint: its two n x n FP64 buffers plus its share of workspace);
   * launch: the admitted requests with n <= small_max (512) form ONE batched launch per step
     (chol_factor_rev_batched: one persistent kernel for the whole group) on the small-request
-    stream; larger ones are launched one by one (chol_factor + chol_rev) on the large-request
-    stream.  Requests that arrive while earlier launches are still running are admitted and
-    launched as soon as memory allows, so their work overlaps on the device with what is
-    already there.
+    stream; larger ones are launched one by one (chol_factor + chol_rev), each on whichever of
+    the large-request streams has the fewest launches in flight.  Requests that arrive while
+    earlier launches are still running are admitted and launched as soon as memory allows, so
+    their work overlaps on the device with what is already there.
 Routing depends only on n and the precision mode, never on load, and every kernel is
 deterministic, so a request's result is bitwise the same alone and in any mix.
 
-Streams (all default priority): the large-request stream and the library's side stream for it,
-the small-request stream, and the caller's stream, on which the inputs are written (a request
-may carry an event that the launch waits for).  Precision 'f64' runs everything in FP64;
-'f64_trail_f32' runs the large requests with FP32-MFMA trailing contractions (the batched small
-requests stay FP64).
+Streams (all default priority): the large-request streams (two by default) and the library's side
+stream for each, the small-request stream, and the caller's stream, on which the inputs are
+written (a request may carry an event that the launch waits for).  Each library call enqueues its
+whole sequence under the library's lock and waits only on events it recorded itself, so streams
+that share a hardware queue cannot deadlock each other; sharing only costs overlap.  Precision
+'f64' runs everything in FP64; 'f64_trail_f32' runs the large requests with FP32-MFMA trailing
+contractions (the batched small requests stay FP64).
 """
 import time
 from collections import deque
@@ -94,7 +96,7 @@ def admit(pending, in_use, budget, small_max, max_group):
 
 
 class _Launch:
-    __slots__ = ("event", "requests", "workspace", "info", "footprint", "keep")
+    __slots__ = ("event", "requests", "workspace", "info", "footprint", "keep", "stream")
 
 
 def _device_array(values, device):
@@ -107,11 +109,14 @@ def _device_array(values, device):
 class Server:
     """See the module docstring.  Not thread-safe: drive it from one host thread."""
 
-    def __init__(self, device, hbm_budget, precision="f64", small_max=SMALL_MAX, max_group=256, nb=0):
+    def __init__(self, device, hbm_budget, precision="f64", small_max=SMALL_MAX, max_group=256, nb=0,
+                 large_streams=2):
         if precision not in ("f64", "f64_trail_f32"):
             raise ValueError("precision must be 'f64' or 'f64_trail_f32'")
         if not 1 <= small_max <= SMALL_MAX:
             raise ValueError(f"small_max must be in [1, {SMALL_MAX}]")
+        if not 1 <= large_streams <= 4:
+            raise ValueError("large_streams must be in [1, 4]")
         B.load_library()
         self.device = torch.device(device)
         self.hbm_budget = int(hbm_budget)
@@ -119,7 +124,7 @@ class Server:
         self.small_max = small_max
         self.max_group = max_group
         self.nb = nb or _DEFAULT_NB
-        self.stream_large = torch.cuda.Stream(self.device)
+        self.streams_large = [torch.cuda.Stream(self.device) for _ in range(large_streams)]
         self.stream_small = torch.cuda.Stream(self.device)
         self.pending = deque()
         self.running = deque()
@@ -201,6 +206,7 @@ class Server:
     def _launch_small(self, reqs):
         s = self.stream_small
         ln = _Launch()
+        ln.stream = -1
         with torch.cuda.stream(s):
             for r in reqs:
                 if r.ready is not None:
@@ -232,8 +238,14 @@ class Server:
         self.running.append(ln)
 
     def _launch_large(self, r):
-        s = self.stream_large
+        busy = [0] * len(self.streams_large)
+        for other in self.running:
+            if other.stream >= 0:
+                busy[other.stream] += 1
+        si = min(range(len(busy)), key=lambda i: busy[i])
+        s = self.streams_large[si]
         ln = _Launch()
+        ln.stream = si
         with torch.cuda.stream(s):
             if r.ready is not None:
                 s.wait_event(r.ready)

@@ -95,6 +95,29 @@ def test_factor_matches_oracle(cg, dev, N, nb):
     assert np.all(np.triu(Lg, 1) == 0)
 
 
+@pytest.mark.parametrize("nb", NBS)
+@pytest.mark.parametrize("N", SIZES)
+def test_factor_fwd_one_sweep(cg, dev, N, nb):
+    """chol_factor_fwd: L against the oracle's factor, L-dot against the oracle's forward propagation
+    on the oracle's L (the sweep uses its own L: these matrices have condition number below 5, so
+    the 1e-10 gate still holds end to end)."""
+    S, L, Lb, Sd, junk = spd_case(N, 6000 + N)
+    A, D, info = cg.chol_factor_fwd(to_dev(S + junk, dev), to_dev(np.tril(Sd) + junk, dev), nb=nb)
+    assert int(info.item()) == 0
+    Lg, Dg = A.cpu().numpy(), D.cpu().numpy()
+    Lo = O.chol(S)[0]
+    assert rel(Lg, Lo) <= TOL
+    assert rel(Dg, O.chol_fwd(Lo, Sd)) <= TOL
+    assert np.all(np.triu(Lg, 1) == 0) and np.all(np.triu(Dg, 1) == 0)
+
+
+def test_factor_fwd_reports_bad_pivot(cg, dev):
+    S, L, Lb, Sd, junk = spd_case(300, 6500)
+    S[130, 130] = -1.0
+    _, _, info = cg.chol_factor_fwd(to_dev(S, dev), to_dev(np.tril(Sd), dev), nb=128)
+    assert int(info.item()) == O.chol(S)[1] == 131
+
+
 @pytest.mark.parametrize("N,bad,nb", [(40, 0, 32), (40, 5, 32), (200, 64, 64), (200, 127, 64),
                                       (300, 299, 128), (300, 130, 128)])
 def test_factor_reports_first_bad_pivot(cg, dev, N, bad, nb):
@@ -155,6 +178,15 @@ def medium():
     c["rev"] = O.chol_rev(L, c["Lbar"], "sym")
     c["fwd"] = O.chol_fwd(L, c["Sdot"])
     return c
+
+
+def test_medium_case_one_sweep(cg, dev, medium):
+    """N = 4096 (kappa ~ 8e6) through chol_factor_fwd: L at 1e-10; L-dot, computed with the
+    sweep's own L, at the end-to-end gate max(1e-10, 100 kappa u) ~ 1e-7."""
+    A, D, info = cg.chol_factor_fwd(to_dev(medium["Sigma"], dev), to_dev(np.tril(medium["Sdot"]), dev), nb=128)
+    assert int(info.item()) == 0
+    assert rel(A.cpu().numpy(), medium["L"]) <= TOL
+    assert rel(D.cpu().numpy(), medium["fwd"]) <= 1e-7
 
 
 @pytest.mark.parametrize("nb", NBS)
