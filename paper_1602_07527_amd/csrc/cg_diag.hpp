@@ -206,6 +206,31 @@ __device__ int level2_potf2_wave(double *Dp, int a, int ib) {
   return bad;
 }
 
+// Row r (> the inner block) of the panel solve  X D^T = C  against the lower-triangular inner
+// block D = Dp[a:a+ib, a:a+ib], in place in packed Dp.  Called by the lane that owns row r.
+__device__ __noinline__ void panel_solve_row(double *Dp, int a, int ib, int r) {
+  double x[INNER];
+  const int base = pidx(r, a);
+#pragma unroll
+  for (int c = 0; c < INNER; ++c) x[c] = (c < ib) ? Dp[base + c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < INNER; ++c) {
+    if (c < ib) {
+      const int rc = pidx(a + c, a);
+      double s0 = x[c], s1 = 0.0;
+#pragma unroll
+      for (int l = 0; l < c; ++l) {
+        if (l & 1) s1 = fma(-x[l], Dp[rc + l], s1);
+        else s0 = fma(-x[l], Dp[rc + l], s0);
+      }
+      x[c] = (s0 + s1) / Dp[rc + c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < INNER; ++c)
+    if (c < ib) Dp[base + c] = x[c];
+}
+
 // Inverse of the lower-triangular 32 x 32 block of Dp at offset a, by ONE wave (D X = I by
 // forward substitution).  Lane i < 32 holds row i of D; lane c < 32 builds column c of X, taking
 // D[i][l] from lane i with v_readlane.  Writes the lower triangle of X into packed Xp at offset a.
@@ -617,32 +642,11 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
     }
     __syncthreads();
     if (rest > 0) {
-      // C <- C D_i^-T  with D_i^-1 from one wave's 32 x 32 inverse
-      if (wave == 0) wave_trinv32(Dp, Xp, a, ib);
-      __syncthreads();
-      const int trr = (rest + 15) / 16;
-      dbl4 acc[3];
-#pragma unroll
-      for (int sl = 0; sl < 3; ++sl) {
-        const int t = wave + DIAG_WAVES * sl;
-        if (t >= trr * 2) continue;
-        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
-        auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Dp[pidx(r, a + k)] : 0.0; };
-        auto B = [&](int k, int j) { return (c0 + j >= k) ? Xp[pidx(a + c0 + j, a + k)] : 0.0; };
-        acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, INNER);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int sl = 0; sl < 3; ++sl) {
-        const int t = wave + DIAG_WAVES * sl;
-        if (t >= trr * 2) continue;
-        const int r0 = b + (t >> 1) * 16, c0 = (t & 1) * 16;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = r0 + tile_row(e);
-          if (r < w) Dp[pidx(r, a + c0 + tile_col())] = acc[sl][e];
-        }
-      }
+      // C <- C D_i^-T by forward substitution, one row of C per lane (rows are independent):
+      // x_c = (c_c - sum_{l < c} x_l D_i[c][l]) / D_i[c][c]; every lane reads the same D_i entry,
+      // an LDS broadcast.  rest <= 96, so waves 0 and 1 cover all rows.
+      const int r = b + tid;
+      if (tid < rest) panel_solve_row(Dp, a, ib, r);
       __syncthreads();
     }
   }
