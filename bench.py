@@ -10,8 +10,9 @@ calls inside the timed steps; per-call figures for all three sweeps are reported
 Each step also runs the batched form once: 2048 SPD matrices (n log-uniform in [16, 512]) through
 factor + Gaussian-process loss + reverse sweep in one launch; its solves/s and launch-time
 percentiles are reported under "batched", and those of the same matrices in FP32 storage under
-"batched_f32".  The three sweeps in the reduced-precision mode (trailing contractions on FP32
-MFMA) are timed alone under "f64_trail_f32"; the headline value stays the FP64 path's.  Under
+"batched_f32".  The three sweeps in the reduced-precision modes (trailing contractions on FP32
+MFMA, or as split-bfloat16 MFMA products) are timed alone under "f64_trail_f32" and
+"f64_trail_bf16x3"; the headline value stays the FP64 path's.  Under
 "serving", a Poisson stream of factor + chol_rev requests of uneven size runs through the
 continuous-batching loop (paper_1602_07527_amd.serve) in both precision modes: p50/p99 latency and
 solves/s.
@@ -177,7 +178,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the served request stream (0 skips it)")
     ap.add_argument("--mixed-steps", type=int, default=3,
-                    help="timed passes of the f64_trail_f32 mode (0 skips it)")
+                    help="timed passes of each reduced-precision mode and of chol_factor_fwd (0 skips them)")
     ap.add_argument("--calibration-mib", type=int, default=0,
                     help="run one plain elementwise copy of this size first (PMC calibration)")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -284,40 +285,44 @@ def main():
                  "tflops": round(n ** 3 / (fused_ms * 1e-3) / 1e12, 3),
                  "separate_ms": None}
 
-    # The reduced-precision mode (trailing contractions on FP32 MFMA) on the same workload: the
-    # three sweeps timed alone, after one untimed pass.
-    mixed = None
-    if args.mixed_steps > 0:
-        log("[bench] f64_trail_f32 sweeps")
+    # The reduced-precision modes (trailing contractions on FP32 MFMA, or as three bfloat16 MFMA
+    # products of split operands) on the same workload: the three sweeps timed alone, after one
+    # untimed pass.
+    MODE_TEXT = {"f64_trail_f32": "FP64 storage; trailing contractions on FP32 MFMA",
+                 "f64_trail_bf16x3": "FP64 storage; trailing contractions as hi*hi + hi*lo + lo*hi "
+                                     "bfloat16 MFMA products with FP32 accumulation"}
+    mixed = {}
+    for mode in (MODE_TEXT if args.mixed_steps > 0 else ()):
+        log(f"[bench] {mode} sweeps")
         mt = {"f": 0.0, "r": 0.0, "d": 0.0}
         for i in range(args.mixed_steps + 1):
             A.copy_(Sigma)
             ev["f"][0].record()
-            cg.chol_factor(A, nb=nb, workspace=ws, info=info, precision="f64_trail_f32")
+            cg.chol_factor(A, nb=nb, workspace=ws, info=info, precision=mode)
             ev["f"][1].record()
             Ab.copy_(Lbar)
             ev["r"][0].record()
-            cg.chol_rev(A, Ab, nb=nb, workspace=ws, precision="f64_trail_f32")
+            cg.chol_rev(A, Ab, nb=nb, workspace=ws, precision=mode)
             ev["r"][1].record()
             Ad.copy_(Sdot)
             ev["d"][0].record()
-            cg.chol_fwd(A, Ad, nb=nb, workspace=ws, precision="f64_trail_f32")
+            cg.chol_fwd(A, Ad, nb=nb, workspace=ws, precision=mode)
             ev["d"][1].record()
             torch.cuda.synchronize()
             if i > 0:
                 for k in mt:
                     mt[k] += ev[k][0].elapsed_time(ev[k][1]) / args.mixed_steps
         if int(info.item()) != 0:
-            raise RuntimeError("f64_trail_f32 chol_factor failed")
-        mixed = {"mode": "FP64 storage; trailing contractions on FP32 MFMA; diagonal blocks and panel "
-                         "solves FP64 (accuracy stated and tested separately)",
-                 "steps": args.mixed_steps,
-                 "chol_rev_ms": round(mt["r"], 3),
-                 "chol_rev_tflops": round(2.0 / 3.0 * n ** 3 / (mt["r"] * 1e-3) / 1e12, 3),
-                 "chol_factor_ms": round(mt["f"], 3),
-                 "chol_factor_tflops": round(n ** 3 / 3.0 / (mt["f"] * 1e-3) / 1e12, 3),
-                 "chol_fwd_ms": round(mt["d"], 3),
-                 "chol_fwd_tflops": round(2.0 / 3.0 * n ** 3 / (mt["d"] * 1e-3) / 1e12, 3)}
+            raise RuntimeError(f"{mode} chol_factor failed")
+        mixed[mode] = {"mode": MODE_TEXT[mode] + "; diagonal blocks and panel solves FP64 (accuracy "
+                                                 "stated and tested separately)",
+                       "steps": args.mixed_steps,
+                       "chol_rev_ms": round(mt["r"], 3),
+                       "chol_rev_tflops": round(2.0 / 3.0 * n ** 3 / (mt["r"] * 1e-3) / 1e12, 3),
+                       "chol_factor_ms": round(mt["f"], 3),
+                       "chol_factor_tflops": round(n ** 3 / 3.0 / (mt["f"] * 1e-3) / 1e12, 3),
+                       "chol_fwd_ms": round(mt["d"], 3),
+                       "chol_fwd_tflops": round(2.0 / 3.0 * n ** 3 / (mt["d"] * 1e-3) / 1e12, 3)}
 
     # Launch-time distribution of the one-launch batched path (factor + loss + reverse sweep), for
     # FP64 storage (the bench workload) and FP32 storage of the same matrices.
@@ -422,7 +427,8 @@ def main():
         "batched": batched,
         "batched_f32": batched_f32,
         "factor_fwd_one_sweep": fused,
-        "f64_trail_f32": mixed,
+        "f64_trail_f32": mixed.get("f64_trail_f32"),
+        "f64_trail_bf16x3": mixed.get("f64_trail_bf16x3"),
         "serving": serving,
     }
     if args.cpu_sample > 0:

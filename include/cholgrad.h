@@ -60,17 +60,23 @@ extern "C" {
  *                   FP64 result for the float input to within float rounding.  Single-matrix
  *                   calls return CHOL_ERR_UNSUPPORTED for it.
  *   CHOL_PREC_F64_TRAIL_F32 : double storage, single-matrix calls only (batched calls return
- *                   CHOL_ERR_UNSUPPORTED).  The trailing contractions -- the block-column
+ *                   CHOL_ERR_UNSUPPORTED, as for the next mode).  The trailing contractions -- the block-column
  *                   updates of chol_factor and chol_fwd and the panel contraction and SYRK of
  *                   chol_rev -- round their operands to FP32 and run on FP32 MFMA with FP32
  *                   accumulation within one launch's K range; diagonal blocks, block inverses,
  *                   panel solves, split-K sums and every stored value stay FP64.  An
  *                   approximation of the FP64 result: on the N = 16384 squared-exponential
  *                   workload (condition number ~1e5) the stated relative Frobenius errors are
- *                   <= 3e-4 for L and <= 3e-3 for Sigma-bar and L-dot. */
+ *                   <= 3e-4 for L and <= 3e-3 for Sigma-bar and L-dot.
+ *   CHOL_PREC_F64_TRAIL_BF16X3 : as CHOL_PREC_F64_TRAIL_F32, but the trailing contractions split
+ *                   each operand into bfloat16 hi + lo parts (hi = bf16(fp32(x)),
+ *                   lo = bf16(fp32(x) - hi)) and take hi*hi + hi*lo + lo*hi on bfloat16 MFMA
+ *                   with FP32 accumulation (~16 significant bits per operand).  Stated relative
+ *                   errors on the same workload: <= 1e-3 for L, <= 1e-2 for Sigma-bar and L-dot. */
 #define CHOL_PREC_F64 0
 #define CHOL_PREC_F32 1
 #define CHOL_PREC_F64_TRAIL_F32 2
+#define CHOL_PREC_F64_TRAIL_BF16X3 3
 
 /* Which reverse-mode output (Sec. 3, eqns (symrev) and (symrevtril); S = L^-T Phi(L^T Lbar) L^-1):
  *   CHOL_SBAR_SYM  : (S + S^T)/2 in both triangles -- the symmetric gradient, for which

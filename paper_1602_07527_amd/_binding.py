@@ -15,8 +15,9 @@ LIB_PATH = os.path.join(PKG, "libcholgrad.so")
 PREC_F64 = 0
 PREC_F32 = 1
 PREC_F64_TRAIL_F32 = 2
+PREC_F64_TRAIL_BF16X3 = 3
 # Precision modes of the single-matrix calls (FP64 storage).
-_PRECS = {"f64": PREC_F64, "f64_trail_f32": PREC_F64_TRAIL_F32}
+_PRECS = {"f64": PREC_F64, "f64_trail_f32": PREC_F64_TRAIL_F32, "f64_trail_bf16x3": PREC_F64_TRAIL_BF16X3}
 SBAR_SYM, SBAR_TRIL = 0, 1
 OP_FACTOR, OP_REV, OP_FWD = 0, 1, 2
 _FORMS = {"sym": SBAR_SYM, "tril": SBAR_TRIL}
@@ -116,7 +117,8 @@ def _workspace(op, n, nb, device, workspace, precision="f64"):
 def chol_factor(A, nb=0, workspace=None, info=None, precision="f64"):
     """In place: tril(A) = Sigma -> tril(A) = L, strict upper set to 0.  Returns (A, info) where
     info is a device int32 tensor (0, or the 1-based column of the first non-positive pivot).
-    precision: 'f64', or 'f64_trail_f32' (trailing updates on FP32 MFMA)."""
+    precision: 'f64', 'f64_trail_f32' (trailing updates on FP32 MFMA) or 'f64_trail_bf16x3'
+    (trailing updates as split-bfloat16 products)."""
     lib = load_library()
     n = _square("A", A)
     if info is None:

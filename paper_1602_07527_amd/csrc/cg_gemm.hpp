@@ -1,7 +1,7 @@
 // MFMA contraction kernels for the Level-3 updates (Sec. 4.2 of Murray 2016: the GEMM-, SYRK- and
 // TRSM-shaped steps of the blocked factorisation and its derivatives).  Operands and results are
-// FP64 in memory; the products run on FP64 MFMA, or on FP32 MFMA for the reduced-precision
-// trailing updates (template parameter CP).
+// FP64 in memory; the products run on FP64 MFMA, or on FP32 MFMA or split-bfloat16 MFMA for the
+// reduced-precision trailing updates (template parameter CP).
 //
 //   C[m, n] = alpha * sum_k A(m, k) B(k, n) + beta * Cin[m, n]        (m < M, n < N, k < K)
 //
@@ -33,8 +33,41 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 //   CP_F32: operands rounded to FP32 as they leave LDS, v_mfma_f32_16x16x4_f32 with FP32
 //           accumulation over the K range of one launch (one split); the epilogue (alpha, beta,
 //           split sums) stays in FP64.
+//   CP_BF16X3: each operand split into bfloat16 hi + lo parts (hi = bf16(fp32(x)),
+//           lo = bf16(fp32(x) - hi), round to nearest even), the product taken as
+//           hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x16_bf16 and FP32 accumulation within
+//           one split; ~16 significant bits per operand.
 constexpr int CP_F64 = 0;
 constexpr int CP_F32 = 1;
+constexpr int CP_BF16X3 = 2;
+
+typedef short shrt4 __attribute__((ext_vector_type(4)));
+
+// bfloat16 bits of a float, round to nearest even (finite inputs).
+__device__ __forceinline__ unsigned bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Split four doubles into their bf16 hi and lo parts.
+__device__ __forceinline__ void bf16_split4(double x0, double x1, double x2, double x3, shrt4 &hi, shrt4 &lo) {
+  const double x[4] = {x0, x1, x2, x3};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float f = (float)x[i];
+    const unsigned h = bf16_rne(f);
+    const float r = f - __uint_as_float(h << 16);
+    hi[i] = (short)h;
+    lo[i] = (short)bf16_rne(r);
+  }
+}
+
+__device__ __forceinline__ flt4 mfma_bf16x3(const shrt4 &ah, const shrt4 &al, const shrt4 &bh, const shrt4 &bl,
+                                             flt4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+}
 
 template <int CP> struct Mfma;
 template <> struct Mfma<CP_F64> {
@@ -45,6 +78,11 @@ template <> struct Mfma<CP_F64> {
   }
   // Output layout of the 16 x 16 block: lane l, element i holds row 4*i + l/16, column l%16.
   static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+template <> struct Mfma<CP_BF16X3> {  // accumulator and output layout of the FP32 MFMAs
+  typedef flt4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 template <> struct Mfma<CP_F32> {
   typedef flt4 acc_t;
@@ -176,18 +214,34 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
     if (kt + 1 < nkt) load_tile(kbeg + (kt + 1) * BK);
     const double *as = As[buf];
     const double *bs = Bs[buf];
+    if constexpr (CP == CP_BF16X3) {
+      // one 16-deep bf16 MFMA per K-tile: the lanes of slot frag_k take k = 4 frag_k .. + 3
+      shrt4 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double af[4], bf[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) af[t] = as[(kk + frag_k) * LDA_S + wm * 64 + t * 16 + frag_i];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) bf[t] = bs[(kk + frag_k) * LDB_S + wn * 64 + t * 16 + frag_i];
+      for (int t = 0; t < 4; ++t) {
+        const double *pa = as + 4 * frag_k * LDA_S + wm * 64 + t * 16 + frag_i;
+        bf16_split4(pa[0], pa[LDA_S], pa[2 * LDA_S], pa[3 * LDA_S], ah[t], al[t]);
+        const double *pb = bs + 4 * frag_k * LDB_S + wn * 64 + t * 16 + frag_i;
+        bf16_split4(pb[0], pb[LDB_S], pb[2 * LDB_S], pb[3 * LDB_S], bh[t], bl[t]);
+      }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[a][b] = MM::step(af[a], bf[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16x3(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double af[4], bf[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) af[t] = as[(kk + frag_k) * LDA_S + wm * 64 + t * 16 + frag_i];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bf[t] = bs[(kk + frag_k) * LDB_S + wn * 64 + t * 16 + frag_i];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = MM::step(af[a], bf[b], acc[a][b]);
+      }
     }
     if (kt + 1 < nkt) store_tile(buf ^ 1);
     __syncthreads();
@@ -333,30 +387,69 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
     if (kt + 1 < nkt) issue(kt + 1, (kt + 1) & 1);
     const double *as = smem + (2 * (kt & 1)) * TILE;
     const double *bs = smem + (2 * (kt & 1) + 1) * TILE;
-#pragma unroll
-    for (int u = 0; u < BK / 8; ++u) {
-      const int g = 4 * u + fk;      // this lane's 16-byte chunk along k: k = 2g and 2g + 1
-      const int k0 = 2 * g;
-      dbl2v af[TMW], bf[TNW];
+    if constexpr (CP == CP_BF16X3) {
+      // one 16-deep bf16 MFMA per K-tile: the lanes of slot fk take k = 4 fk .. 4 fk + 3, i.e.
+      // 16-byte chunks 2 fk and 2 fk + 1 of a K-contiguous row
+      static_assert(BK == 16, "the split-bf16 path takes one 16-deep K-tile per MFMA");
+      shrt4 ah[TMW], al[TMW], bh[TNW], bl[TNW];
 #pragma unroll
       for (int t = 0; t < TMW; ++t) {
         const int m = wm * (BM / WM) + t * 16 + fi;
-        if (AT) af[t] = dbl2v{as[k0 * BM + m], as[(k0 + 1) * BM + m]};
-        else af[t] = *(const dbl2v *)&as[m * BK + ((g ^ (m % CH)) << 1)];
+        double x0, x1, x2, x3;
+        if (AT) {
+          x0 = as[(4 * fk) * BM + m]; x1 = as[(4 * fk + 1) * BM + m];
+          x2 = as[(4 * fk + 2) * BM + m]; x3 = as[(4 * fk + 3) * BM + m];
+        } else {
+          const dbl2v p0 = *(const dbl2v *)&as[m * BK + (((2 * fk) ^ (m % CH)) << 1)];
+          const dbl2v p1 = *(const dbl2v *)&as[m * BK + (((2 * fk + 1) ^ (m % CH)) << 1)];
+          x0 = p0[0]; x1 = p0[1]; x2 = p1[0]; x3 = p1[1];
+        }
+        bf16_split4(x0, x1, x2, x3, ah[t], al[t]);
       }
 #pragma unroll
       for (int t = 0; t < TNW; ++t) {
         const int n = wn * (BN / WN) + t * 16 + fi;
-        if (BT) bf[t] = *(const dbl2v *)&bs[n * BK + ((g ^ (n % CH)) << 1)];
-        else bf[t] = dbl2v{bs[k0 * BN + n], bs[(k0 + 1) * BN + n]};
+        double x0, x1, x2, x3;
+        if (BT) {
+          const dbl2v p0 = *(const dbl2v *)&bs[n * BK + (((2 * fk) ^ (n % CH)) << 1)];
+          const dbl2v p1 = *(const dbl2v *)&bs[n * BK + (((2 * fk + 1) ^ (n % CH)) << 1)];
+          x0 = p0[0]; x1 = p0[1]; x2 = p1[0]; x3 = p1[1];
+        } else {
+          x0 = bs[(4 * fk) * BN + n]; x1 = bs[(4 * fk + 1) * BN + n];
+          x2 = bs[(4 * fk + 2) * BN + n]; x3 = bs[(4 * fk + 3) * BN + n];
+        }
+        bf16_split4(x0, x1, x2, x3, bh[t], bl[t]);
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int a = 0; a < TMW; ++a)
 #pragma unroll
-        for (int a = 0; a < TMW; ++a)
+        for (int b = 0; b < TNW; ++b) acc[a][b] = mfma_bf16x3(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+    } else {
 #pragma unroll
-          for (int b = 0; b < TNW; ++b)
-            acc[a][b] = MM::step(af[a][h], bf[b][h], acc[a][b]);
+      for (int u = 0; u < BK / 8; ++u) {
+        const int g = 4 * u + fk;      // this lane's 16-byte chunk along k: k = 2g and 2g + 1
+        const int k0 = 2 * g;
+        dbl2v af[TMW], bf[TNW];
+#pragma unroll
+        for (int t = 0; t < TMW; ++t) {
+          const int m = wm * (BM / WM) + t * 16 + fi;
+          if (AT) af[t] = dbl2v{as[k0 * BM + m], as[(k0 + 1) * BM + m]};
+          else af[t] = *(const dbl2v *)&as[m * BK + ((g ^ (m % CH)) << 1)];
+        }
+#pragma unroll
+        for (int t = 0; t < TNW; ++t) {
+          const int n = wn * (BN / WN) + t * 16 + fi;
+          if (BT) bf[t] = *(const dbl2v *)&bs[n * BK + ((g ^ (n % CH)) << 1)];
+          else bf[t] = dbl2v{bs[k0 * BN + n], bs[(k0 + 1) * BN + n]};
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int a = 0; a < TMW; ++a)
+#pragma unroll
+            for (int b = 0; b < TNW; ++b)
+              acc[a][b] = MM::step(af[a][h], bf[b][h], acc[a][b]);
+      }
     }
   }
 

@@ -126,10 +126,11 @@ hipError_t side_for(hipStream_t caller, Side **out) {
 }
 
 // Precision modes of the single-matrix sweeps (FP64 storage): the trailing contractions run on
-// FP64 or FP32 MFMA; diagonal blocks and panel solves are FP64 in both.
+// FP64, FP32 or split-bfloat16 MFMA; diagonal blocks and panel solves are FP64 in all of them.
 bool single_prec(int precision, int *cp) {
   if (precision == CHOL_PREC_F64) { *cp = cg::CP_F64; return true; }
   if (precision == CHOL_PREC_F64_TRAIL_F32) { *cp = cg::CP_F32; return true; }
+  if (precision == CHOL_PREC_F64_TRAIL_BF16X3) { *cp = cg::CP_BF16X3; return true; }
   return false;
 }
 
@@ -174,6 +175,7 @@ void launch_gemm_cp(bool at, bool bt, bool fast, int tag, dim3 grid, const cg::G
 void launch_gemm(bool at, bool bt, bool fast, int tag, int cp, dim3 grid, const cg::GemmArgs &p,
                  hipStream_t s) {
   if (cp == cg::CP_F32) launch_gemm_cp<cg::CP_F32>(at, bt, fast, tag, grid, p, s);
+  else if (cp == cg::CP_BF16X3) launch_gemm_cp<cg::CP_BF16X3>(at, bt, fast, tag, grid, p, s);
   else launch_gemm_cp<cg::CP_F64>(at, bt, fast, tag, grid, p, s);
 }
 
@@ -788,7 +790,7 @@ size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max) {
 }
 
 static int batched_common_checks(int precision, int batch, int64_t n_max) {
-  if (precision == CHOL_PREC_F64_TRAIL_F32) return CHOL_ERR_UNSUPPORTED;
+  if (precision == CHOL_PREC_F64_TRAIL_F32 || precision == CHOL_PREC_F64_TRAIL_BF16X3) return CHOL_ERR_UNSUPPORTED;
   if (!batched_prec_ok(precision)) return -1;
   if (batch < 0) return -2;
   if (n_max < 0 || n_max > cg::BATCH_NMAX) return CHOL_ERR_UNSUPPORTED;

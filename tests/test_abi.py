@@ -73,17 +73,22 @@ def test_invalid_arguments_rejected_on_host():
 
 
 def test_precision_modes_on_host():
-    """FP32 storage exists only for the batched calls and the FP32-trailing mode only for the
-    single-matrix calls; the other combination is refused as unsupported before any launch."""
+    """FP32 storage exists only for the batched calls and the reduced-precision trailing modes
+    (FP32 and split-bf16) only for the single-matrix calls; the other combinations are refused as
+    unsupported before any launch."""
     lib = _lib()
     fake = ctypes.c_void_p(4096)
     ws = ctypes.c_void_p(1 << 20)
     big = 1 << 40
     assert lib.chol_workspace_bytes(1, 2, 1000, 0) == lib.chol_workspace_bytes(1, 0, 1000, 0) > 0
+    assert lib.chol_workspace_bytes(1, 3, 1000, 0) == lib.chol_workspace_bytes(1, 0, 1000, 0)
+    assert lib.chol_workspace_bytes(1, 4, 1000, 0) == 0       # no mode 4
     assert lib.chol_workspace_bytes(1, 1, 1000, 0) == 0
     assert lib.chol_rev(1, 10, fake, 10, fake, 10, 0, 0, ws, big, None) == -103
     assert lib.chol_factor(1, 10, fake, 10, 0, fake, ws, big, None) == -103
     assert lib.chol_batched_workspace_bytes(2, 1, 4) == 0
     assert lib.chol_batched_workspace_bytes(1, 1, 512) > lib.chol_batched_workspace_bytes(0, 1, 512) > 0
     assert lib.chol_factor_batched(2, 1, None, None, None, 4, None, None, 0, None) == -103
+    assert lib.chol_factor_batched(3, 1, None, None, None, 4, None, None, 0, None) == -103
+    assert lib.chol_batched_workspace_bytes(3, 1, 4) == 0
     assert lib.chol_factor_batched(7, 1, None, None, None, 4, None, None, 0, None) == -1
