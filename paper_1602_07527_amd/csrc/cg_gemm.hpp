@@ -120,6 +120,15 @@ struct GemmArgs {
   int64_t lda2;
   const double *B2;
   int64_t ldb2;
+  // Stream-K schedule (fast kernel only; sk_wgs == 0 selects the uniform splits above): the
+  // output's sk_tiles tiles (sk_tm along M, tile t at (t % sk_tm, t / sk_tm)) times their sk_kt
+  // K-tiles form T units in tile-major order, and workgroup w takes units
+  // [w T / sk_wgs, (w+1) T / sk_wgs).  Its piece of tile t goes to the 128 x 128 partial slot
+  // w + t of C (row stride ldc = 128, slot stride split_stride).
+  int sk_wgs = 0;
+  int sk_kt = 0;
+  int sk_tm = 0;
+  int sk_tiles = 0;
 };
 
 // K extent of the combined range: K, or 2K with a second operand pair.
@@ -314,13 +323,25 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
   __shared__ __attribute__((aligned(16))) double smem[2 * 2 * TILE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  if (p.lower_only && m0 + BM - 1 < n0) return;
-  const int z = blockIdx.z;
-  const int kbeg = z * p.kchunk;
-  const int kend = min(P2 ? 2 * p.K : p.K, kbeg + p.kchunk);
-  const int nkt = (kend > kbeg) ? (kend - kbeg) / BK : 0;
-  double *Cout = p.C + (int64_t)z * p.split_stride;
+  // Work of this workgroup: one (tile, K-range) piece under uniform splits, or the pieces of its
+  // stream-K unit range (at most two tiles, as the host keeps T / sk_wgs <= sk_kt).
+  int m0 = 0, n0 = 0, kbeg = 0, nkt = 0, cm0 = 0, cn0 = 0;
+  double *Cout = nullptr;
+  int64_t su = 0, su1 = 0;
+  if (p.sk_wgs) {
+    const int64_t T = (int64_t)p.sk_kt * p.sk_tiles;
+    su = (int64_t)blockIdx.x * T / p.sk_wgs;
+    su1 = (int64_t)(blockIdx.x + 1) * T / p.sk_wgs;
+  } else {
+    m0 = blockIdx.x * BM;
+    n0 = blockIdx.y * BN;
+    if (p.lower_only && m0 + BM - 1 < n0) return;
+    const int z = blockIdx.z;
+    kbeg = z * p.kchunk;
+    const int kend = min(P2 ? 2 * p.K : p.K, kbeg + p.kchunk);
+    nkt = (kend > kbeg) ? (kend - kbeg) / BK : 0;
+    Cout = p.C + (int64_t)z * p.split_stride;
+  }
 
   // Loop-invariant per-lane byte offsets inside a tile (per operand pair); the tile bases are
   // wave-uniform.  K is a multiple of BK, so no K-tile straddles the two pairs.  P2 (a second
@@ -370,6 +391,26 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
     }
   };
 
+  const int fk = lane >> 4, fi = lane & 15;
+  constexpr int W0 = waitcnt_vm(0);
+  for (int seg = 0;; ++seg) {
+  if (p.sk_wgs) {
+    if (su >= su1) break;
+    const int64_t t = su / p.sk_kt;
+    const int64_t e = min(su1, (t + 1) * (int64_t)p.sk_kt);
+    m0 = (int)(t % p.sk_tm) * BM;
+    n0 = (int)(t / p.sk_tm) * BN;
+    kbeg = (int)(su - t * p.sk_kt) * BK;
+    nkt = (int)(e - su);
+    cm0 = m0;
+    cn0 = n0;
+    Cout = p.C + ((int64_t)blockIdx.x + t) * p.split_stride;
+    su = e;
+    // every wave has finished reading the ring (and the previous piece's stores are queued)
+    if (seg > 0) __syncthreads();
+  } else if (seg > 0) {
+    break;
+  }
   typename MM::acc_t acc[TMW][TNW];
 #pragma unroll
   for (int a = 0; a < TMW; ++a)
@@ -377,8 +418,6 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
     for (int b = 0; b < TNW; ++b) acc[a][b] = MM::zero();
 
   if (nkt > 0) issue(0, 0);
-  const int fk = lane >> 4, fi = lane & 15;
-  constexpr int W0 = waitcnt_vm(0);
   for (int kt = 0; kt < nkt; ++kt) {
     // This wave's loads of tile kt are done; the barrier makes every wave's part visible and
     // guarantees the other stage is no longer being read before it is refilled.
@@ -464,9 +503,10 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
         const int gn = n0 + wn * (BN / WN) + b * 16 + (lane & 15);
         double v = alpha * (double)acc[a][b][i];
         if (beta != 0.0) v += beta * p.Cin[(int64_t)gm * p.ldcin + gn];
-        Cout[(int64_t)gm * p.ldc + gn] = v;
+        Cout[(int64_t)(gm - cm0) * p.ldc + (gn - cn0)] = v;
         if (p.Cm) p.Cm[(int64_t)gn * p.ldcm + gm] = v;
       }
+  }  // pieces
 }
 
 // The same sum for many splits of a small output: each element is shared by RG_GROUPS threads,
@@ -542,6 +582,32 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(int M, int N, const 
       for (int u = 0; u < 8; ++u) s += v[u];
     }
     for (; z < S; ++z) s += src[(int64_t)z * sstride];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * Cin[(int64_t)m * ldcin + n];
+    C[(int64_t)m * ldc + n] = v;
+    if (Cm) Cm[(int64_t)n * ldcm + m] = v;
+  }
+}
+
+// Sum of the stream-K pieces: element (m, n) lies in tile t = m / 128 + (n / 128) tm, whose units
+// [t KT, (t+1) KT) were taken by workgroups wf .. wl (w takes [w T / W, (w+1) T / W)); their partial
+// slots w + t are added in workgroup order, so the result is bitwise reproducible.
+__global__ __launch_bounds__(256) void reduce_streamk_kernel(int M, int N, const double *P, int64_t sstride,
+                                                             int64_t W, int64_t KT, int tm, double alpha,
+                                                             const double *Cin, int64_t ldcin, double beta,
+                                                             double *C, int64_t ldc, double *Cm, int64_t ldcm) {
+  const int64_t total = (int64_t)M * N;
+  const int64_t T = KT * tm * ((N + GEMM_BN - 1) / GEMM_BN);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(e / N), n = (int)(e % N);
+    const int64_t t = m / GEMM_BM + (int64_t)(n / GEMM_BN) * tm;
+    // last workgroup whose range starts at or before unit x: floor(((x + 1) W - 1) / T)
+    const int64_t wf = ((t * KT + 1) * W - 1) / T;
+    const int64_t wl = (((t + 1) * KT) * W - 1) / T;
+    const double *src = P + (wf + t) * sstride + (int64_t)(m % GEMM_BM) * GEMM_BN + (n % GEMM_BN);
+    double s = 0.0;
+    for (int64_t w = wf; w <= wl; ++w, src += sstride) s += *src;
     double v = alpha * s;
     if (beta != 0.0) v += beta * Cin[(int64_t)m * ldcin + n];
     C[(int64_t)m * ldc + n] = v;

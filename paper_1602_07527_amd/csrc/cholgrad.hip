@@ -22,8 +22,14 @@ namespace {
 
 constexpr size_t WS_ALIGN = 256;
 constexpr int DEFAULT_NB = 128;
-constexpr int TARGET_WGS = 512;  // two 256-thread workgroups per compute unit on 256 CUs
-constexpr int64_t PART_ELEMS = (int64_t)TARGET_WGS * cg::GEMM_BM * cg::GEMM_BN;
+constexpr int TARGET_WGS = 512;  // two contraction workgroups per compute unit on 256 CUs
+// Workgroups of a stream-K contraction: a little below the 512 resident slots.  The diagonal
+// block kernels of the sweeps run beside the contractions on the other stream and hold most of a
+// compute unit's LDS; with more workgroups than this, some of them wait for a slot until that
+// kernel ends (measured on MI355X in the N = 16384 sweeps: 480 beats 448, 464, 496 and 504).
+constexpr int SK_WGS = 480;
+constexpr int64_t PART_SLOTS = 2 * TARGET_WGS;  // 128 x 128 partial tiles per buffer
+constexpr int64_t PART_ELEMS = PART_SLOTS * cg::GEMM_BM * cg::GEMM_BN;
 
 // Benchmark instrumentation: event pairs around the panel contractions, per sweep (see
 // chol_profile_begin).  Process-global and not thread-safe; off unless a benchmark enables it.
@@ -212,9 +218,19 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
                     dma_ld_ok(lda) && dma_ld_ok(ldb) && aligned16(A) && aligned16(B) &&
                     (!q.A2 || (dma_ld_ok(q.lda2) && dma_ld_ok(q.ldb2) && aligned16(q.A2) && aligned16(q.B2)));
   const int kstep = fast ? cg::DMA_BK : cg::GEMM_BK;
+  // Stream-K on the fast kernel when the output has too few tiles: SK_WGS workgroups take equal
+  // shares of the (tile, K-tile) units, each piece deep enough (>= min_kchunk) to be worth a
+  // partial tile; the pieces are then summed per tile in workgroup order.
+  int64_t skw = 0;
+  if (part && fast && !lower_only && Kt > 0 && tiles >= 2) {
+    const int64_t units = (int64_t)tiles * (Kt / cg::DMA_BK);
+    skw = std::min<int64_t>(SK_WGS, units * cg::DMA_BK / std::max(min_kchunk, cg::DMA_BK));
+    skw = std::min<int64_t>(skw, PART_SLOTS - tiles + 1);
+    if (skw <= tiles) skw = 0;
+  }
   int S = 1;
   int kchunk = (int)(cdiv(Kt > 0 ? Kt : 1, kstep) * kstep);
-  if (part && Kt > 0) {
+  if (part && Kt > 0 && !skw) {
     int64_t s_want = TARGET_WGS / tiles;
     s_want = std::min<int64_t>(s_want, cdiv(Kt, min_kchunk));
     s_want = std::min<int64_t>(s_want, PART_ELEMS / ((int64_t)M * N));
@@ -229,8 +245,12 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   p.A2 = q.A2; p.lda2 = q.A2 ? q.lda2 : 0; p.B2 = q.A2 ? q.B2 : nullptr; p.ldb2 = q.A2 ? q.ldb2 : 0;
   p.kchunk = kchunk;
   p.lower_only = lower_only;
-  const dim3 grid(tm, tn, S);
-  if (S == 1) {
+  const dim3 grid = skw ? dim3((unsigned)skw, 1, 1) : dim3(tm, tn, S);
+  if (skw) {
+    p.C = part; p.ldc = cg::GEMM_BN; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
+    p.Cm = nullptr; p.ldcm = 0; p.split_stride = (int64_t)cg::GEMM_BM * cg::GEMM_BN;
+    p.sk_wgs = (int)skw; p.sk_kt = Kt / cg::DMA_BK; p.sk_tm = tm; p.sk_tiles = tiles;
+  } else if (S == 1) {
     p.C = C; p.ldc = ldc; p.Cin = Cin; p.ldcin = ldcin; p.alpha = alpha; p.beta = beta;
     p.Cm = Cm; p.ldcm = ldcm; p.split_stride = 0;
   } else {
@@ -254,8 +274,15 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
     ++g_prof.used;
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || S == 1) return e;
   const int64_t total = (int64_t)M * N;
+  if (e == hipSuccess && skw) {
+    const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 4096);
+    hipLaunchKernelGGL(cg::reduce_streamk_kernel, dim3(blocks), dim3(256), 0, s, M, N, part,
+                       (int64_t)cg::GEMM_BM * cg::GEMM_BN, skw, (int64_t)(Kt / cg::DMA_BK), tm, alpha,
+                       Cin, ldcin, beta, C, ldc, Cm, ldcm);
+    return hipGetLastError();
+  }
+  if (e != hipSuccess || S == 1) return e;
   if (S >= 4 * cg::RG_GROUPS && total <= (int64_t)64 * 1024) {  // many splits of a small output
     const int blocks = (int)std::min<int64_t>(cdiv(total, cg::RG_ELEMS), 4096);
     hipLaunchKernelGGL(cg::reduce_splits_grouped_kernel, dim3(blocks), dim3(256), 0, s, M, N, part,
