@@ -37,7 +37,7 @@ def test_ingest_pmc_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(tmp_path / "rec.json"))
-    tgt = "void cg::gemm_f64_dma_kernel<false, false, 1, 0>(cg::GemmArgs)"
+    tgt = "void cg::gemm_f64_dma_kernel<false, false, 1, 0, false>(cg::GemmArgs)"
     cal = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(...)>"
     # The calibration copy of 64 MiB reads as 32768 KiB: every raw value is half the truth.
     _write_counters(tmp_path / "f.csv", "FETCH_SIZE",
