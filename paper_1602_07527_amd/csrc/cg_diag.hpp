@@ -94,7 +94,9 @@ __device__ __forceinline__ int tile_col() { return threadIdx.x & 15; }
 // For j = 31 .. 0:  d-bar <- d-bar - c^T c-bar / d;  [d-bar; c-bar] /= d;
 // r-bar <- r-bar - [d-bar c-bar^T][r; B];  B-bar <- B-bar - c-bar r;  d-bar <- d-bar / 2.
 // Lane j owns (d, c, d-bar, c-bar); the lanes l < j own the entries of r, B, r-bar, B-bar and take
-// lane j's column with v_readlane.
+// lane j's column with v_readlane.  Lane j scales its column by 1/d before the broadcast, and a
+// lane l > j holds D[j][l] = 0 (the zero-padded upper triangle), so every lane runs the same two
+// FMAs per broadcast element with no per-element select.
 __device__ void level2_rev_wave(const double *Dp, double *Bp, int a, int ib) {
   const int c = threadIdx.x & 63;
   double Dc[INNER], Bc[INNER];
@@ -118,18 +120,25 @@ __device__ void level2_rev_wave(const double *Dp, double *Bp, int a, int ib) {
     }
     const double inv_d = wave_bcast(inv_own, j);
     const double dbar = wave_bcast((Bc[j] - (p0 + p1) * inv_d) * inv_d, j);
-    const bool below = c < j, owner = c == j;
-    const double r = Dc[j];  // D[j][c] on the lanes below
+    const bool owner = c == j;
+    // c-bar <- c-bar / d on the owner (the other lanes multiply by exactly 1), so that it is
+    // broadcast already scaled
+    const double sc = owner ? inv_d : 1.0;
+#pragma unroll
+    for (int i = j + 1; i < INNER; ++i) Bc[i] *= sc;
+    // D[j][c] on the lanes below; 0 on the owner (its column is final) and, from the zero-padded
+    // upper triangle, on the lanes above
+    const double r = owner ? 0.0 : Dc[j];
     double q0 = dbar * r, q1 = 0.0;
 #pragma unroll
     for (int i = j + 1; i < INNER; ++i) {
-      const double cbi = wave_bcast(Bc[i], j) * inv_d;
+      const double cbi = wave_bcast(Bc[i], j);
       if ((i - j) & 1) q1 = fma(cbi, Dc[i], q1);
       else q0 = fma(cbi, Dc[i], q0);
-      const double upd = fma(-cbi, r, Bc[i]);
-      Bc[i] = owner ? cbi : (below ? upd : Bc[i]);
+      Bc[i] = fma(-cbi, r, Bc[i]);
     }
-    Bc[j] = owner ? 0.5 * dbar : (below ? Bc[j] - (q0 + q1) : Bc[j]);
+    // lanes above change only their entry j, which lies above their diagonal and is never stored
+    Bc[j] = owner ? 0.5 * dbar : Bc[j] - (q0 + q1);
   }
 #pragma unroll
   for (int i = 0; i < INNER; ++i)
@@ -148,6 +157,11 @@ __device__ void level2_fwd_wave(const double *Dp, double *Ap, int a, int ib) {
     Dr[l] = ok ? Dp[pidx(a + i, a + l)] : (l == i ? 1.0 : 0.0);
     Ar[l] = ok ? Ap[pidx(a + i, a + l)] : 0.0;
   }
+  // 1 / D[i][i], once per lane: the divisions of every column become multiplications
+  double own = 1.0;
+#pragma unroll
+  for (int l = 0; l < INNER; ++l) own = (l == i) ? Dr[l] : own;
+  const double inv_own = 1.0 / own;
 #pragma unroll
   for (int j = 0; j < INNER; ++j) {
     double p0 = 0.0, p1 = 0.0;
@@ -156,8 +170,8 @@ __device__ void level2_fwd_wave(const double *Dp, double *Ap, int a, int ib) {
       if (l & 1) p1 = fma(Dr[l], Ar[l], p1);
       else p0 = fma(Dr[l], Ar[l], p0);
     }
-    const double d = wave_bcast(Dr[j], j);
-    const double ddot = wave_bcast((0.5 * Ar[j] - (p0 + p1)) / Dr[j], j);
+    const double inv_d = wave_bcast(inv_own, j);
+    const double ddot = wave_bcast((0.5 * Ar[j] - (p0 + p1)) * inv_own, j);
     double q0 = Ar[j], q1 = 0.0;
 #pragma unroll
     for (int l = 0; l < j; ++l) {
@@ -166,7 +180,7 @@ __device__ void level2_fwd_wave(const double *Dp, double *Ap, int a, int ib) {
       else       { q0 = fma(-Ar[l], r, q0); q0 = fma(-Dr[l], rd, q0); }
     }
     const double num = fma(-Dr[j], ddot, q0 + q1);
-    Ar[j] = (i > j) ? num / d : ((i == j) ? ddot : Ar[j]);
+    Ar[j] = (i > j) ? num * inv_d : ((i == j) ? ddot : Ar[j]);
   }
 #pragma unroll
   for (int l = 0; l < INNER; ++l)
