@@ -53,6 +53,71 @@ __device__ __forceinline__ void load_packed(double *dst, const double *src, int6
   }
 }
 
+typedef double dbl2d __attribute__((ext_vector_type(2)));
+
+// 16-byte accesses to a row-major block need a 16-byte aligned base, an even leading dimension
+// and an even width (so that a column pair never leaves the block).
+__device__ __forceinline__ bool pairs_ok(const void *p, int64_t ld, int w) {
+  return ((reinterpret_cast<uintptr_t>(p) & 15u) == 0) && ((ld & 1) == 0) && ((w & 1) == 0);
+}
+
+// Packed-lower load of two w x w blocks at once (src2 may be null), by column pairs with 16-byte
+// loads when both sources allow it (16 loads of each in flight per thread); element loads
+// otherwise.  A pair (c, c+1) with c <= r < w has c + 1 <= w - 1 for even w, so it stays inside
+// the block even when c + 1 lies above the diagonal (that element is not stored).
+__device__ __forceinline__ void load_packed2(double *dst, const double *src, int64_t ld, double *dst2,
+                                             const double *src2, int64_t ld2, int w) {
+  if (!pairs_ok(src, ld, w) || (src2 && !pairs_ok(src2, ld2, w))) {
+    load_packed(dst, src, ld, w);
+    if (src2) load_packed(dst2, src2, ld2, w);
+    return;
+  }
+  constexpr int BATCH = 16;
+  for (int e0 = 0; e0 < w * (DIAG_MAX / 2); e0 += BATCH * DIAG_THREADS) {
+    dbl2d v[BATCH], v2[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + u * DIAG_THREADS + (int)threadIdx.x;
+      const int r = e >> 6, c = (e & (DIAG_MAX / 2 - 1)) * 2;
+      const bool ok = r < w && c <= r;
+      v[u] = ok ? *(const dbl2d *)(src + (int64_t)r * ld + c) : dbl2d{0.0, 0.0};
+      if (src2) v2[u] = ok ? *(const dbl2d *)(src2 + (int64_t)r * ld2 + c) : dbl2d{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + u * DIAG_THREADS + (int)threadIdx.x;
+      const int r = e >> 6, c = (e & (DIAG_MAX / 2 - 1)) * 2;
+      if (r < w && c <= r) {
+        dst[pidx(r, c)] = v[u][0];
+        if (c + 1 <= r) dst[pidx(r, c + 1)] = v[u][1];
+        if (src2) {
+          dst2[pidx(r, c)] = v2[u][0];
+          if (c + 1 <= r) dst2[pidx(r, c + 1)] = v2[u][1];
+        }
+      }
+    }
+  }
+}
+
+// dst[r * ld + c] = val(r, c) for r < rows, c < cols (cols <= 128), by column pairs with 16-byte
+// stores when dst allows it, element stores otherwise.
+template <typename F>
+__device__ __forceinline__ void store_block(double *dst, int64_t ld, int rows, int cols, F val) {
+  if (pairs_ok(dst, ld, cols)) {
+#pragma unroll 4
+    for (int e = threadIdx.x; e < rows * (DIAG_MAX / 2); e += blockDim.x) {
+      const int r = e >> 6, c = (e & (DIAG_MAX / 2 - 1)) * 2;
+      if (c < cols) *(dbl2d *)(dst + (int64_t)r * ld + c) = dbl2d{val(r, c), val(r, c + 1)};
+    }
+  } else {
+#pragma unroll 4
+    for (int e = threadIdx.x; e < rows * DIAG_MAX; e += blockDim.x) {
+      const int r = e >> 7, c = e & (DIAG_MAX - 1);
+      if (c < cols) dst[(int64_t)r * ld + c] = val(r, c);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // One wave's 16 x 16 MFMA tile:  acc += sum_{k < K} A(i, k) B(k, j)  for i, j < 16.  A and B are
 // accessors returning 0 outside their valid range; K need not be a multiple of 4.
@@ -340,10 +405,7 @@ __device__ void block_inverse(const double *Dp, double *Xp, int w) {
 
 // Write the packed lower triangle of a w x w block to a row-major nb x nb buffer, zero elsewhere.
 __device__ __forceinline__ void store_lower_square(double *dst, int nb, const double *Xp, int w) {
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int r = e / nb, c = e - r * nb;
-    dst[e] = (r < w && c <= r) ? Xp[pidx(r, c)] : 0.0;
-  }
+  store_block(dst, nb, nb, nb, [&](int r, int c) { return (r < w && c <= r) ? Xp[pidx(r, c)] : 0.0; });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -352,7 +414,7 @@ __device__ __forceinline__ void store_lower_square(double *dst, int nb, const do
 // the w x w block.
 __device__ __forceinline__ void trinv_block(int w, const double *Ld, int64_t ldl, double *Dinv, int nb, double *Dp,
                             double *Xp) {
-  load_packed(Dp, Ld, ldl, w);
+  load_packed2(Dp, Ld, ldl, nullptr, nullptr, 0, w);
   __syncthreads();
   block_inverse(Dp, Xp, w);
   store_lower_square(Dinv, nb, Xp, w);
@@ -389,8 +451,7 @@ __device__ __forceinline__ void diag_rev_block(int w, const double *Ld, int64_t 
                                const double *Dinv, int nb, double *Aout, int64_t lda, double *Dp,
                                double *Bp, double *Xi) {
   const int tid = threadIdx.x, wave = tid >> 6;
-  load_packed(Dp, Ld, ldl, w);
-  load_packed(Bp, Dbar, ldd, w);
+  load_packed2(Dp, Ld, ldl, Bp, Dbar, ldd, w);
   __syncthreads();
 
   for (int a = ((w - 1) / INNER) * INNER; a >= 0; a -= INNER) {
@@ -486,14 +547,9 @@ __device__ __forceinline__ void diag_rev_block(int w, const double *Ld, int64_t 
     }
   }
 
-#pragma unroll 8
-  for (int e = tid; e < w * DIAG_MAX; e += DIAG_THREADS) {
-    const int r = e >> 7, cc = e & (DIAG_MAX - 1);
-    if (cc < w) {
-      const double v = (r > cc) ? 0.5 * Bp[pidx(r, cc)] : (r == cc ? Bp[pidx(r, r)] : 0.5 * Bp[pidx(cc, r)]);
-      Aout[(int64_t)r * lda + cc] = v;
-    }
-  }
+  store_block(Aout, lda, w, w, [&](int r, int cc) {
+    return (r > cc) ? 0.5 * Bp[pidx(r, cc)] : (r == cc ? Bp[pidx(r, r)] : 0.5 * Bp[pidx(cc, r)]);
+  });
   __syncthreads();
 }
 
@@ -518,8 +574,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const dou
 __device__ __forceinline__ void diag_fwd_block(int w, const double *Ld, int64_t ldl, const double *Dinv, int nb,
                                double *Ad, int64_t lda, double *Dp, double *Ap, double *Xi) {
   const int tid = threadIdx.x, wave = tid >> 6;
-  load_packed(Dp, Ld, ldl, w);
-  load_packed(Ap, Ad, lda, w);
+  load_packed2(Dp, Ld, ldl, Ap, Ad, lda, w);
   __syncthreads();
   for (int a = 0; a < w; a += INNER) {
     const int b = min(w, a + INNER);
@@ -599,10 +654,7 @@ __device__ __forceinline__ void diag_fwd_block(int w, const double *Ld, int64_t 
       __syncthreads();
     }
   }
-  for (int e = tid; e < w * w; e += blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    Ad[(int64_t)r * lda + c] = (c <= r) ? Ap[pidx(r, c)] : 0.0;
-  }
+  store_block(Ad, lda, w, w, [&](int r, int c) { return (c <= r) ? Ap[pidx(r, c)] : 0.0; });
   __syncthreads();
 }
 
@@ -626,7 +678,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const dou
 __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int nb, int *info,
                             int64_t col0, double *Dp, double *Xp, int &bad) {
   const int tid = threadIdx.x, wave = tid >> 6;
-  load_packed(Dp, Ad, lda, w);
+  load_packed2(Dp, Ad, lda, nullptr, nullptr, 0, w);
   if (tid == 0) bad = -1;
   __syncthreads();
   for (int a = 0; a < w; a += INNER) {
@@ -666,10 +718,7 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
   }
   if (tid == 0 && bad >= 0 && *info == 0) *info = (int)(col0 + bad + 1);
   block_inverse(Dp, Xp, w);
-  for (int e = tid; e < w * w; e += blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    Ad[(int64_t)r * lda + c] = (c <= r) ? Dp[pidx(r, c)] : 0.0;
-  }
+  store_block(Ad, lda, w, w, [&](int r, int c) { return (c <= r) ? Dp[pidx(r, c)] : 0.0; });
   store_lower_square(Dinv, nb, Xp, w);
   __syncthreads();
 }
