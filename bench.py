@@ -148,7 +148,7 @@ def batched_setup(dev, dtype=None):
     work = torch.empty_like(master)
     grad = torch.empty_like(master)
     views = lambda buf: [buf[offs[i]:offs[i + 1]].view(n, n) for i, n in enumerate(sizes)]
-    ys = [torch.from_numpy(y).to(dev).to(dtype) for y in case["y"]]
+    ys = cg.Vecs([torch.from_numpy(y).to(dev).to(dtype) for y in case["y"]])
     A, G = cg.Batch(views(work)), cg.Batch(views(grad))
     ws = torch.empty(cg.batched_workspace_bytes(len(sizes), max(sizes), A.prec), dtype=torch.uint8, device=dev)
     f = torch.empty(len(sizes), dtype=dtype, device=dev)

@@ -13,9 +13,9 @@ torch.autograd Functions; `serve` runs a continuous-batching request loop on top
 from ._binding import (Batch, CholError, LIB_PATH, batched_workspace_bytes, chol_factor,
                        chol_factor_batched, chol_factor_fwd, chol_factor_rev_batched, chol_fwd,
                        chol_fwd_batched, chol_gp_nll_batched, chol_rev, chol_rev_batched, load_library,
-                       profile_begin, profile_end, workspace_bytes)
+                       profile_begin, profile_end, Vecs, workspace_bytes)
 
 __all__ = ["Batch", "CholError", "LIB_PATH", "batched_workspace_bytes", "chol_factor",
            "chol_factor_batched", "chol_factor_fwd", "chol_factor_rev_batched", "chol_fwd",
            "chol_fwd_batched", "chol_gp_nll_batched", "chol_rev", "chol_rev_batched", "load_library",
-           "profile_begin", "profile_end", "workspace_bytes"]
+           "profile_begin", "profile_end", "Vecs", "workspace_bytes"]

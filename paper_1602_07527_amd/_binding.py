@@ -235,14 +235,32 @@ class Batch:
         return len(self.sizes)
 
 
+class Vecs:
+    """Device-side pointer table of a list of vectors (one per matrix of a Batch), built once and
+    reusable across calls on the same tensors, as Batch is for the matrices."""
+
+    def __init__(self, vecs):
+        if len(vecs) == 0:
+            raise ValueError("empty vector list")
+        self.device, self.dtype = vecs[0].device, vecs[0].dtype
+        for v in vecs:
+            if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == self.dtype and v.is_contiguous()
+                    and v.dim() == 1 and v.device == self.device):
+                raise ValueError("vectors must be contiguous 1-D device tensors of one dtype and device")
+        self.vecs = list(vecs)
+        self.sizes = [int(v.numel()) for v in vecs]
+        self.ptr = torch.tensor([v.data_ptr() for v in vecs], dtype=torch.int64).to(self.device)
+
+    def __len__(self):
+        return len(self.sizes)
+
+
 def _vec_ptrs(vecs, sizes, dev, dtype):
-    if len(vecs) != len(sizes):
-        raise ValueError("one vector per matrix")
-    for v, n in zip(vecs, sizes):
-        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == dtype and v.is_contiguous()
-                and v.numel() == n and v.device == dev):
-            raise ValueError(f"vectors must be contiguous {dtype} device tensors matching the sizes")
-    return torch.tensor([v.data_ptr() for v in vecs], dtype=torch.int64).to(dev)
+    if not isinstance(vecs, Vecs):
+        vecs = Vecs(list(vecs)) if len(vecs) else None
+    if vecs is None or vecs.sizes != list(sizes) or vecs.device != dev or vecs.dtype != dtype:
+        raise ValueError(f"vectors must be contiguous {dtype} device tensors matching the sizes")
+    return vecs.ptr
 
 
 def batched_workspace_bytes(batch, n_max, prec=PREC_F64):
@@ -325,7 +343,8 @@ def chol_factor_rev_batched(A, G, form="sym", info=None, workspace=None):
 
 def chol_gp_nll_batched(A, y, G, f=None, info=None, workspace=None):
     """Per problem b, in one launch: A[b] (Sigma -> L), f[b] = sum log L_ii + |L^-1 y_b|^2 / 2 and
-    G[b] = df_b/dSigma_b (symmetric).  Returns (f, info) device tensors."""
+    G[b] = df_b/dSigma_b (symmetric).  y is a list of vectors or a prebuilt Vecs.  Returns
+    (f, info) device tensors."""
     lib = load_library()
     A, G = _as_batch(A), _as_batch(G)
     if A.sizes != G.sizes or A.dtype != G.dtype or A.device != G.device:

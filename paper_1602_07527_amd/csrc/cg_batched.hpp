@@ -219,61 +219,120 @@ __device__ __noinline__ void batch_fwd_one(int n, const double *L, int64_t ldl, 
 // Gaussian-process style loss on one matrix, after batch_factor_one has replaced Sigma by L and
 // left the block inverses in the slot: z = L^-1 y and w = L^-T z by block substitution with the
 // block inverses, f = sum log L_ii + |z|^2 / 2, and L-bar = diag(1/L_ii) - tril(w z^T) into G.
+__device__ __forceinline__ double wave_sum(double v) {  // fixed xor-tree order: reproducible
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __noinline__ void batch_gp_loss_one(int n, const double *L, int64_t ldl, const double *y, double *G,
                                   int64_t ldg, double *f_out, double *slot, double *lds) {
   const double *dinv = slot;
   double *z = slot + SLOT_DINV + SLOT_PANEL + SLOT_DBLK, *wv = z + BATCH_NMAX;
-  double *t = lds;  // BATCH_NB doubles of staging
+  double *t = lds;                          // BATCH_NB doubles of staging
+  double *zl = lds + BATCH_NB;              // z, staged in LDS as it is produced
+  double *wl = zl + BATCH_NMAX;             // w, likewise
+  double *pt = wl + BATCH_NMAX;             // 2 x BATCH_NB partial sums
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = DIAG_THREADS / 64, RU = 4;
   const int nblk = (n + BATCH_NB - 1) / BATCH_NB;
-  for (int b = 0; b < nblk; ++b) {  // forward: z_b = D_b^-1 (y_b - L_{b,<b} z_<b)
+  // forward: z_b = D_b^-1 (y_b - L_{b,<b} z_<b).  Rows of L are contiguous, so a wave takes RU
+  // rows at a time with its lanes along them (coalesced loads) and reduces each with wave_sum.
+  for (int b = 0; b < nblk; ++b) {
     const int j = b * BATCH_NB, w = min(BATCH_NB, n - j);
-    for (int r = threadIdx.x; r < w; r += blockDim.x) {
-      double s = y[j + r];
-      for (int l = 0; l < j; ++l) s = fma(-L[(int64_t)(j + r) * ldl + l], z[l], s);
-      t[r] = s;
+    for (int r0 = wave * RU; r0 < w; r0 += NW * RU) {
+      double s[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) s[u] = 0.0;
+      for (int l = lane; l < j; l += 64) {
+        const double zv = zl[l];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+          if (r0 + u < w) s[u] = fma(L[(int64_t)(j + r0 + u) * ldl + l], zv, s[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const double tot = wave_sum(s[u]);
+        if (lane == 0 && r0 + u < w) t[r0 + u] = y[j + r0 + u] - tot;
+      }
     }
     __syncthreads();
     const double *Di = dinv + (int64_t)b * BATCH_NB * BATCH_NB;
-    for (int r = threadIdx.x; r < w; r += blockDim.x) {
-      double s = 0.0;
-      for (int q = 0; q <= r; ++q) s = fma(Di[r * BATCH_NB + q], t[q], s);
-      z[j + r] = s;
+    for (int r0 = wave * RU; r0 < w; r0 += NW * RU) {
+      double s[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) s[u] = 0.0;
+      for (int q = lane; q < w; q += 64) {
+        const double tv = t[q];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+          if (q <= r0 + u && r0 + u < w) s[u] = fma(Di[(r0 + u) * BATCH_NB + q], tv, s[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const double tot = wave_sum(s[u]);
+        if (lane == 0 && r0 + u < w) {
+          z[j + r0 + u] = tot;
+          zl[j + r0 + u] = tot;
+        }
+      }
     }
     __syncthreads();
   }
-  for (int b = nblk - 1; b >= 0; --b) {  // backward: w_b = D_b^-T (z_b - L_{>b,b}^T w_>b)
+  // backward: w_b = D_b^-T (z_b - L_{>b,b}^T w_>b).  Columns of L are strided, so thread (h, r)
+  // walks rows i = k + h, k + h + 2, ... of column j + r (loads coalesced over r) and the two
+  // halves are added in a fixed order.
+  const int r = threadIdx.x % BATCH_NB, h = threadIdx.x / BATCH_NB;
+  for (int b = nblk - 1; b >= 0; --b) {
     const int j = b * BATCH_NB, k = min(n, j + BATCH_NB), w = k - j;
-    for (int r = threadIdx.x; r < w; r += blockDim.x) {
-      double s = z[j + r];
-      for (int i = k; i < n; ++i) s = fma(-L[(int64_t)i * ldl + j + r], wv[i], s);
-      t[r] = s;
+    double s = 0.0;
+    if (r < w) {
+      int i = k + h;
+      for (; i + 6 < n; i += 8) {
+        const double l0 = L[(int64_t)i * ldl + j + r], l1 = L[(int64_t)(i + 2) * ldl + j + r];
+        const double l2 = L[(int64_t)(i + 4) * ldl + j + r], l3 = L[(int64_t)(i + 6) * ldl + j + r];
+        s = fma(l0, wl[i], s);
+        s = fma(l1, wl[i + 2], s);
+        s = fma(l2, wl[i + 4], s);
+        s = fma(l3, wl[i + 6], s);
+      }
+      for (; i < n; i += 2) s = fma(L[(int64_t)i * ldl + j + r], wl[i], s);
     }
+    pt[h * BATCH_NB + r] = s;
+    __syncthreads();
+    if (h == 0 && r < w) t[r] = zl[j + r] - (pt[r] + pt[BATCH_NB + r]);
     __syncthreads();
     const double *Di = dinv + (int64_t)b * BATCH_NB * BATCH_NB;
-    for (int r = threadIdx.x; r < w; r += blockDim.x) {
-      double s = 0.0;
-      for (int q = r; q < w; ++q) s = fma(Di[q * BATCH_NB + r], t[q], s);
-      wv[j + r] = s;
+    s = 0.0;
+    if (r < w)
+      for (int q = r + h; q < w; q += 2) s = fma(Di[q * BATCH_NB + r], t[q], s);
+    pt[h * BATCH_NB + r] = s;
+    __syncthreads();
+    if (h == 0 && r < w) {
+      const double v = pt[r] + pt[BATCH_NB + r];
+      wv[j + r] = v;
+      wl[j + r] = v;
     }
     __syncthreads();
   }
   // f: per-thread partial sums over a fixed stride, then a fixed-order tree in LDS
   double part = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) part += log(L[(int64_t)i * ldl + i]) + 0.5 * z[i] * z[i];
-  double *red = lds + BATCH_NB;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) part += log(L[(int64_t)i * ldl + i]) + 0.5 * zl[i] * zl[i];
+  double *red = pt;
   red[threadIdx.x] = part;
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+  for (int hh = blockDim.x / 2; hh > 0; hh >>= 1) {
+    if ((int)threadIdx.x < hh) red[threadIdx.x] += red[threadIdx.x + hh];
     __syncthreads();
   }
   if (threadIdx.x == 0) *f_out = red[0];
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int r = e / n, c = e - r * n;
-    double v = 0.0;
-    if (c <= r) v = -wv[r] * z[c] + ((r == c) ? 1.0 / L[(int64_t)r * ldl + r] : 0.0);
-    G[(int64_t)r * ldg + c] = v;
-  }
+  // L-bar = diag(1 / L_ii) - tril(w z^T), one wave per row
+  for (int rr = wave; rr < n; rr += NW)
+    for (int c = lane; c < n; c += 64) {
+      double v = 0.0;
+      if (c <= rr) v = -wl[rr] * zl[c] + ((rr == c) ? 1.0 / L[(int64_t)rr * ldl + rr] : 0.0);
+      G[(int64_t)rr * ldg + c] = v;
+    }
   __syncthreads();
 }
 

@@ -104,6 +104,27 @@ def test_gp_batched(cg, dev):
         assert rel(Gg, 0.5 * (np.linalg.inv(p["S"]) - np.outer(a, a))) <= 1e-9
 
 
+def test_gp_batched_prebuilt_tables(cg, dev):
+    """Prebuilt Batch / Vecs pointer tables give bitwise the same losses and gradients as plain
+    tensor lists, on repeated calls."""
+    import torch
+    P = problems(SIZES, 401)
+    S = [to_dev(p["S"], dev) for p in P]
+    ys = [to_dev(p["y"], dev) for p in P]
+    A1, G1 = [s.clone() for s in S], [torch.empty_like(s) for s in S]
+    f1, i1 = cg.chol_gp_nll_batched(A1, ys, G1)
+    A2, G2 = [s.clone() for s in S], [torch.empty_like(s) for s in S]
+    Ab, Gb, yv = cg.Batch(A2), cg.Batch(G2), cg.Vecs(ys)
+    for _ in range(2):
+        for a, s in zip(A2, S):
+            a.copy_(s)
+        f2, i2 = cg.chol_gp_nll_batched(Ab, yv, Gb)
+        assert torch.equal(i1, i2) and torch.equal(f1, f2)
+        assert all(torch.equal(g1, g2) for g1, g2 in zip(G1, G2))
+    with pytest.raises(ValueError):
+        cg.chol_gp_nll_batched(Ab, cg.Vecs(ys[:-1]), Gb)
+
+
 def test_batched_info_and_isolation(cg, dev):
     """A non-SPD problem gets its LAPACK-style info without disturbing its neighbours."""
     sizes = [150, 40, 300]
