@@ -65,20 +65,20 @@ __host__ __device__ constexpr int64_t stage_doubles(int64_t n_max) {
 // matrix kernels inline them).
 __device__ __noinline__ void nl_trinv_block(int w, const double *Ld, int64_t ldl, double *Dinv, int nb,
                                             double *Dp, double *Xp) {
-  trinv_block(w, Ld, ldl, Dinv, nb, Dp, Xp);
+  trinv_block(w, Ld, ldl, Dinv, nb, as_lds(Dp), as_lds(Xp));
 }
 __device__ __noinline__ void nl_diag_rev_block(int w, const double *Ld, int64_t ldl, const double *Dbar,
                                                int64_t ldd, const double *Dinv, int nb, double *Aout,
                                                int64_t lda, double *Dp, double *Bp, double *Xi) {
-  diag_rev_block(w, Ld, ldl, Dbar, ldd, Dinv, nb, Aout, lda, Dp, Bp, Xi);
+  diag_rev_block(w, Ld, ldl, Dbar, ldd, Dinv, nb, Aout, lda, as_lds(Dp), as_lds(Bp), as_lds(Xi));
 }
 __device__ __noinline__ void nl_diag_fwd_block(int w, const double *Ld, int64_t ldl, const double *Dinv, int nb,
                                                double *Ad, int64_t lda, double *Dp, double *Ap, double *Xi) {
-  diag_fwd_block(w, Ld, ldl, Dinv, nb, Ad, lda, Dp, Ap, Xi);
+  diag_fwd_block(w, Ld, ldl, Dinv, nb, Ad, lda, as_lds(Dp), as_lds(Ap), as_lds(Xi));
 }
 __device__ __noinline__ void nl_potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int nb, int *info,
                                             int64_t col0, double *Dp, double *Xp, int &bad) {
-  potf2_block(w, Ad, lda, Dinv, nb, info, col0, Dp, Xp, bad);
+  potf2_block(w, Ad, lda, Dinv, nb, info, col0, as_lds(Dp), as_lds(Xp), bad);
 }
 
 // C = alpha op(A) op(B) + beta Cin over all 128 x 128 output tiles, by the whole workgroup.
@@ -92,7 +92,7 @@ __device__ __noinline__ void wg_gemm(int M, int N, int K, const double *A, int64
   p.C = C; p.ldc = ldc; p.Cin = Cin; p.ldcin = ldcin; p.alpha = alpha; p.beta = beta;
   p.Cm = Cm; p.ldcm = ldcm; p.kchunk = K; p.split_stride = 0; p.lower_only = 0;
   for (int m0 = 0; m0 < M; m0 += GEMM_BM)
-    for (int n0 = 0; n0 < N; n0 += GEMM_BN) gemm_tile<AT, BT>(p, m0, n0, 0, K, C, lds);
+    for (int n0 = 0; n0 < N; n0 += GEMM_BN) gemm_tile<AT, BT>(p, m0, n0, 0, K, C, as_lds(lds));
 }
 
 // FP32 storage: the lower triangle of a float input is widened into a compact FP64 copy (leading
@@ -125,6 +125,7 @@ __device__ void wg_zero_upper(int n, double *A, int64_t lda) {
 // Sec. 4.2 chol_blocked on one matrix (n <= 512).  Block inverses are left in the slot.
 __device__ __noinline__ void batch_factor_one(int n, double *A, int64_t lda, int *info, double *slot, double *lds,
                                  int &bad) {
+  lds = as_lds(lds);
   double *dinv = slot;
   const int nblk = (n + BATCH_NB - 1) / BATCH_NB;
   double *Dp = lds, *Xp = lds + DIAG_PACKED;
@@ -143,6 +144,7 @@ __device__ __noinline__ void batch_factor_one(int n, double *A, int64_t lda, int
 }
 
 __device__ __noinline__ void batch_block_inverses(int n, const double *L, int64_t ldl, double *dinv, double *lds) {
+  lds = as_lds(lds);
   const int nblk = (n + BATCH_NB - 1) / BATCH_NB;
   for (int b = 0; b < nblk; ++b) {
     const int j = b * BATCH_NB, w = min(BATCH_NB, n - j);
@@ -155,6 +157,7 @@ __device__ __noinline__ void batch_block_inverses(int n, const double *L, int64_
 // on one matrix; dinv must hold the block inverses of L.
 __device__ __noinline__ void batch_rev_one(int n, const double *L, int64_t ldl, double *A, int64_t lda, int form,
                               double *slot, double *lds) {
+  lds = as_lds(lds);
   double *dinv = slot, *panel = slot + SLOT_DINV, *dblk = panel + SLOT_PANEL;
   const int nblk = (n + BATCH_NB - 1) / BATCH_NB;
   for (int b = nblk - 1; b >= 0; --b) {
@@ -193,6 +196,7 @@ __device__ __noinline__ void batch_rev_one(int n, const double *L, int64_t ldl, 
 // Forward sweep (Sec. 4.2 chol_blocked_fwd) on one matrix; dinv must hold the block inverses of L.
 __device__ __noinline__ void batch_fwd_one(int n, const double *L, int64_t ldl, double *A, int64_t lda, double *slot,
                               double *lds) {
+  lds = as_lds(lds);
   double *dinv = slot, *panel = slot + SLOT_DINV;
   const int nblk = (n + BATCH_NB - 1) / BATCH_NB;
   for (int b = 0; b < nblk; ++b) {
@@ -227,6 +231,7 @@ __device__ __forceinline__ double wave_sum(double v) {  // fixed xor-tree order:
 
 __device__ __noinline__ void batch_gp_loss_one(int n, const double *L, int64_t ldl, const double *y, double *G,
                                   int64_t ldg, double *f_out, double *slot, double *lds) {
+  lds = as_lds(lds);
   const double *dinv = slot;
   double *z = slot + SLOT_DINV + SLOT_PANEL + SLOT_DBLK, *wv = z + BATCH_NMAX;
   double *t = lds;                          // BATCH_NB doubles of staging

@@ -24,6 +24,13 @@ constexpr int XLD = INNER + 1;  // leading dimension of a staged 32 x 32 inverse
 
 __device__ __forceinline__ int pidx(int r, int c) { return (r * (r + 1)) / 2 + c; }  // r >= c
 
+// A pointer known to address LDS, re-typed so that the compiler sees it.  Out-of-line functions
+// receive LDS arrays as plain pointers; without this their accesses compile to flat loads and
+// stores (global-memory latency, counted with the vector-memory operations) instead of LDS ones.
+__device__ __forceinline__ double *as_lds(double *p) {
+  return (double *)(__attribute__((address_space(3))) double *)p;
+}
+
 // Uniform copy of lane `src`'s value (two 32-bit v_readlane).  src must be wave-uniform.
 __device__ __forceinline__ double wave_bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -288,6 +295,7 @@ __device__ int level2_potf2_wave(double *Dp, int a, int ib) {
 // Row r (> the inner block) of the panel solve  X D^T = C  against the lower-triangular inner
 // block D = Dp[a:a+ib, a:a+ib], in place in packed Dp.  Called by the lane that owns row r.
 __device__ __noinline__ void panel_solve_row(double *Dp, int a, int ib, int r) {
+  Dp = as_lds(Dp);
   double x[INNER];
   const int base = pidx(r, a);
 #pragma unroll

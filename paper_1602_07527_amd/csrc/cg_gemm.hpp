@@ -148,8 +148,11 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
   typedef Mfma<CP> MM;
   constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = GEMM_BK, LDA_S = BM + GEMM_PAD,
                 LDB_S = BN + GEMM_PAD;
-  double *As[2] = {lds, lds + GEMM_LDS_A};
-  double *Bs[2] = {lds + 2 * GEMM_LDS_A, lds + 2 * GEMM_LDS_A + GEMM_LDS_B};
+  // lds addresses LDS; re-typed so that a caller that passes it as a plain pointer (an
+  // out-of-line function) still gets LDS instructions rather than flat ones
+  double *const lb = (double *)(__attribute__((address_space(3))) double *)lds;
+  auto As = [&](int buf) { return lb + buf * GEMM_LDS_A; };
+  auto Bs = [&](int buf) { return lb + 2 * GEMM_LDS_A + buf * GEMM_LDS_B; };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -200,14 +203,14 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
       const int e = it * GEMM_THREADS + tid;
       int m, k;
       if (!AT) { m = e >> 4; k = e & 15; } else { k = e >> 7; m = e & 127; }
-      As[buf][k * LDA_S + m] = ra[it];
+      As(buf)[k * LDA_S + m] = ra[it];
     }
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
       const int e = it * GEMM_THREADS + tid;
       int n, k;
       if (!BT) { k = e >> 7; n = e & 127; } else { n = e >> 4; k = e & 15; }
-      Bs[buf][k * LDB_S + n] = rb[it];
+      Bs(buf)[k * LDB_S + n] = rb[it];
     }
   };
 
@@ -221,8 +224,8 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
   for (int kt = 0; kt < nkt; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nkt) load_tile(kbeg + (kt + 1) * BK);
-    const double *as = As[buf];
-    const double *bs = Bs[buf];
+    const double *as = As(buf);
+    const double *bs = Bs(buf);
     if constexpr (CP == CP_BF16X3) {
       // one 16-deep bf16 MFMA per K-tile: the lanes of slot frag_k take k = 4 frag_k .. + 3
       shrt4 ah[4], al[4], bh[4], bl[4];
