@@ -576,7 +576,7 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
       if (m > 0) {
         CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
         CG_TRY(gemm(false, true, m, w, nb, A + k * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + k * lda + j,
-                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
+                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 64, s, 2, cp));
         CG_TRY(hipEventRecord(side->low, s));
       }
     }
@@ -662,7 +662,7 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       if (m > 0) {
         CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
         CG_TRY(gemm(false, true, m, w, nb, A + k * lda + jp, lda, L + j * ldl + jp, ldl, -1.0, A + k * lda + j,
-                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 3, cp,
+                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 64, s, 3, cp,
                     Pair2{L + k * ldl + jp, ldl, A + j * lda + jp, lda}));
         CG_TRY(hipEventRecord(side->low, s));
       }
@@ -764,9 +764,9 @@ int chol_factor_fwd(int precision, int64_t n, void *Av, int64_t lda, void *Dv, i
       if (m > 0) {
         CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
         CG_TRY(gemm(false, true, m, w, nb, A + k * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + k * lda + j,
-                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
+                    lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 64, s, 2, cp));
         CG_TRY(gemm(false, true, m, w, nb, D + k * ldd + jp, ldd, A + j * lda + jp, lda, -1.0, D + k * ldd + j,
-                    ldd, 1.0, D + k * ldd + j, ldd, nullptr, 0, 0, ws.part, 256, s, 3, cp,
+                    ldd, 1.0, D + k * ldd + j, ldd, nullptr, 0, 0, ws.part, 64, s, 3, cp,
                     Pair2{A + k * lda + jp, lda, D + j * ldd + jp, ldd}));
         CG_TRY(hipEventRecord(side->low, s));
       }
