@@ -12,7 +12,9 @@ factor + Gaussian-process loss + reverse sweep in one launch; its solves/s and l
 percentiles are reported under "batched", and those of the same matrices in FP32 storage under
 "batched_f32".  The three sweeps in the reduced-precision modes (trailing contractions on FP32
 MFMA, or as split-bfloat16 MFMA products) are timed alone under "f64_trail_f32" and
-"f64_trail_bf16x3"; the headline value stays the FP64 path's.  Under
+"f64_trail_bf16x3"; the headline value stays the FP64 path's.  The three sweeps on the
+N = 4096 workload (lengthscale 0.3, nugget 1e-4) are timed for nb = 32, 64 and 128 under
+"n4096_by_nb".  Under
 "serving", a Poisson stream of factor + chol_rev requests of uneven size runs through the
 continuous-batching loop (paper_1602_07527_amd.serve) in both precision modes: p50/p99 latency and
 solves/s.
@@ -177,6 +179,8 @@ def main():
                     help="leading-block size for the CPU oracle baseline (0 skips it)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the served request stream (0 skips it)")
+    ap.add_argument("--n4096-steps", type=int, default=5,
+                    help="timed passes of the N=4096 sweeps for each nb (0 skips them)")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed passes of each reduced-precision mode and of chol_factor_fwd (0 skips them)")
     ap.add_argument("--calibration-mib", type=int, default=0,
@@ -264,6 +268,49 @@ def main():
         raise RuntimeError("non-finite result")
     if int((bat["info"] != 0).sum()) != 0 or not bool(torch.isfinite(bat["f"]).all()):
         raise RuntimeError("batched factorisation failed")
+
+    # The N = 4096 workload (3-D squared-exponential kernel, lengthscale 0.3, nugget 1e-4, built on
+    # the device) for each block width nb: the three sweeps timed alone (median of the timed
+    # passes, after one untimed pass).
+    by_nb = None
+    if args.n4096_steps > 0:
+        import statistics
+        log("[bench] N=4096 sweeps by nb")
+        m = workloads.se_case_device(4096, workloads.SEED_MEDIUM, 0.3, 1e-4, dev)
+        n2 = 4096
+        A2, B2, D2 = torch.empty_like(m["Sigma"]), torch.empty_like(m["Sigma"]), torch.empty_like(m["Sigma"])
+        ws2 = torch.empty(max(cg.workspace_bytes(op, n2, nbv) for op in ("factor", "rev", "fwd") for nbv in (32, 64, 128)),
+                          dtype=torch.uint8, device=dev)
+        info2 = torch.empty(1, dtype=torch.int32, device=dev)
+        by_nb = {"workload": "squared-exponential kernel matrix N=4096 (3-D inputs, lengthscale 0.3, nugget "
+                             "1e-4, built on the device); median of the timed passes per nb"}
+        for nbv in (32, 64, 128):
+            t = {"f": [], "r": [], "d": []}
+            for i in range(args.n4096_steps + 1):
+                A2.copy_(m["Sigma"])
+                ev["f"][0].record()
+                cg.chol_factor(A2, nb=nbv, workspace=ws2, info=info2)
+                ev["f"][1].record()
+                B2.copy_(m["Lbar"])
+                ev["r"][0].record()
+                cg.chol_rev(A2, B2, nb=nbv, workspace=ws2)
+                ev["r"][1].record()
+                D2.copy_(m["Sdot"])
+                ev["d"][0].record()
+                cg.chol_fwd(A2, D2, nb=nbv, workspace=ws2)
+                ev["d"][1].record()
+                torch.cuda.synchronize()
+                if i > 0:
+                    for k in t:
+                        t[k].append(ev[k][0].elapsed_time(ev[k][1]))
+            if int(info2.item()) != 0:
+                raise RuntimeError(f"N=4096 chol_factor failed at nb={nbv}")
+            med = {k: statistics.median(v) for k, v in t.items()}
+            by_nb[f"nb{nbv}"] = {
+                "chol_factor_ms": round(med["f"], 3), "chol_factor_tflops": round(n2 ** 3 / 3.0 / (med["f"] * 1e-3) / 1e12, 2),
+                "chol_rev_ms": round(med["r"], 3), "chol_rev_tflops": round(2.0 / 3.0 * n2 ** 3 / (med["r"] * 1e-3) / 1e12, 2),
+                "chol_fwd_ms": round(med["d"], 3), "chol_fwd_tflops": round(2.0 / 3.0 * n2 ** 3 / (med["d"] * 1e-3) / 1e12, 2)}
+        del m, A2, B2, D2, ws2
 
     # chol_factor_fwd: potrf and the forward sweep in one pass, timed alone after one untimed pass.
     fused = None
@@ -426,6 +473,7 @@ def main():
         "roofline": roofline,
         "batched": batched,
         "batched_f32": batched_f32,
+        "n4096_by_nb": by_nb,
         "factor_fwd_one_sweep": fused,
         "f64_trail_f32": mixed.get("f64_trail_f32"),
         "f64_trail_bf16x3": mixed.get("f64_trail_bf16x3"),

@@ -754,6 +754,45 @@ __global__ void set_int_kernel(int *p, int v) { *p = v; }
 
 // Convert the symmetric gradient held in both triangles to the paper's lower-triangular form
 // T = Phi(S + S^T) (eqn (symrevtril)): strict lower doubled, diagonal kept, strict upper zeroed.
+// Operands of the symbolic diagonal adjoint (w x w): T = tril(D) with a zero strict upper
+// triangle, and the strict upper triangle of Dbar cleared (both have leading dimension ld; D is
+// read with leading dimension ldd).
+__global__ __launch_bounds__(256) void diag_sym_prep_kernel(int w, const double *D, int64_t ldd, double *T,
+                                                            double *Dbar, int64_t ld) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
+    const int r = e / w, c = e - r * w;
+    T[(int64_t)r * ld + c] = (c <= r) ? D[(int64_t)r * ldd + c] : 0.0;
+    if (c > r) Dbar[(int64_t)r * ld + c] = 0.0;
+  }
+}
+
+// Y = (Phi(P) + Phi(P)^T) / 2 in place (w x w, leading dimension ld): Phi keeps the lower
+// triangle and halves the diagonal, so Y[r][c] = Y[c][r] = P[r][c] / 2 for r >= c.  Only lower
+// entries are read, and each is read and written by its own thread.
+__global__ __launch_bounds__(256) void diag_sym_phi_kernel(int w, double *P, int64_t ld) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
+    const int r = e / w, c = e - r * w;
+    if (c <= r) {
+      const double v = 0.5 * P[(int64_t)r * ld + c];
+      P[(int64_t)r * ld + c] = v;
+      P[(int64_t)c * ld + r] = v;
+    }
+  }
+}
+
+// A[r][c] = A[c][r] = S[r][c] for r >= c (w x w): the lower triangle of S to both triangles of A.
+__global__ __launch_bounds__(256) void diag_sym_out_kernel(int w, const double *S, int64_t lds, double *A,
+                                                           int64_t lda) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
+    const int r = e / w, c = e - r * w;
+    if (c <= r) {
+      const double v = S[(int64_t)r * lds + c];
+      A[(int64_t)r * lda + c] = v;
+      A[(int64_t)c * lda + r] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void sym_to_tril_kernel(int64_t n, double *A, int64_t lda) {
   const int64_t total = n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;

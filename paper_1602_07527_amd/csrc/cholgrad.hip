@@ -65,6 +65,7 @@ struct SweepWs {
   double *dblk = nullptr;   // one diagonal block: nb x nb
   double *part = nullptr;   // split-K partial tiles of the main stream: PART_ELEMS
   double *part2 = nullptr;  // split-K partial tiles of the side stream: PART_ELEMS
+  double *tmp = nullptr;    // two nb x nb blocks for the symbolic diagonal adjoint
 };
 
 size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
@@ -75,6 +76,7 @@ size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
   w->dblk = c.take((size_t)nb * nb);
   w->part = c.take((size_t)PART_ELEMS);
   w->part2 = c.take((size_t)PART_ELEMS);
+  w->tmp = c.take((size_t)2 * nb * nb);
   return c.off;
 }
 
@@ -431,6 +433,13 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
   return carve(n, nb, nullptr, &w);
 }
 
+// Which diagonal-block adjoint chol_rev uses (see the sweep): the symbolic one on the caller's
+// stream, or the Level-2 one on the side stream.  Measured on MI355X (same GPU, alternating
+// builds): at n = 4096, nb = 128 the sweep is bound by its per-step chain and the symbolic form
+// takes 4.9 ms against 6.0 ms; at n = 16384 the Level-2 form, hidden behind the bulk products,
+// is about 1% faster; with nb = 32 or 64 the Level-2 blocks are short and win at n = 4096 too.
+bool rev_symbolic_diag(int64_t n, int nb) { return nb == 128 && n <= 8192; }
+
 int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
@@ -455,25 +464,36 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   double *A = static_cast<double *>(Av);
   const int64_t nblk = cdiv(n, nb);
 
+  // Diagonal-block adjoint variant (Sec. 4.2 leaves the choice open; the listing itself uses the
+  // symbolic form on the diagonal block).  Symbolic: D-bar <- D^-T Phi(D^T D-bar) D^-1 (symmetric
+  // part) as three small MFMA products with the block inverse on the caller's stream, so the whole
+  // sweep is one stream.  Level-2: Sec. 4.1's unblocked sweep in one workgroup on the side stream,
+  // overlapped with the next step's bulk product.
+  const bool sym_diag = rev_symbolic_diag(n, nb);
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
-  CG_TRY(side_for(s, &side));
-  hipStream_t s2 = side->s;
+  hipStream_t s2 = nullptr;
+  if (!sym_diag) {
+    CG_TRY(side_for(s, &side));
+    s2 = side->s;
+  }
 
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
                      ldl, ws.dinv);
   CG_TRY(hipGetLastError());
-  CG_TRY(hipEventRecord(side->start, s));
-  CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
+  if (!sym_diag) {
+    CG_TRY(hipEventRecord(side->start, s));
+    CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
+  }
 
   // Reverse sweep over block columns, right to left, in left-looking ("lazy") order: when block
   // [j, k) is reached, everything right of it is final and is stored as the symmetric gradient
   // S_sym in both triangles of A[k:, k:].  The accumulated knock-on terms of Sec. 4.2's
   // B-bar / R-bar updates then collapse to one product:
   //   C-bar = L-bar_C - (T + T^T)[k:, k:] L[k:, j:k] = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k].
-  // Look-ahead: the rows of that product below block b+1 need only block b+1's panel, so they run
-  // on the caller's stream while block b+1's diagonal adjoint runs on the side stream; only block
-  // b+1's own rows wait for its diagonal block.
+  // Look-ahead (Level-2 variant): the rows of that product below block b+1 need only block b+1's
+  // panel, so they run on the caller's stream while block b+1's diagonal adjoint runs on the side
+  // stream; only block b+1's own rows wait for its diagonal block.
   for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
@@ -486,7 +506,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
         CG_TRY(gemm(false, false, m2, w, m, A + (k + m1) * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                     A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0,
                     ws.part, 256, s, 1, cp));
-      CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
+      if (!sym_diag) CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
       // From here to the next diagonal adjoint every product is on the sweep's critical path and
       // has a single 128-wide tile column: fine K-splits spread it over many compute units.
       CG_TRY(gemm(false, false, m1, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
@@ -504,15 +524,39 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     } else {
       CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s));
     }
-    CG_TRY(hipEventRecord(side->panel, s));
-    CG_TRY(hipStreamWaitEvent(s2, side->panel, 0));
-    hipLaunchKernelGGL(cg::diag_rev_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w,
-                       L + j * ldl + j, ldl, (const double *)ws.dblk, (int64_t)nb,
-                       (const double *)(ws.dinv + b * nb * nb), nb, A + j * lda + j, lda);
-    CG_TRY(hipGetLastError());
-    CG_TRY(hipEventRecord(side->diag, s2));
+    if (sym_diag) {
+      // Symbolic diagonal adjoint with D = L[j:k, j:k], its inverse from trinv, and T = tril(D):
+      //   P = T^T tril(D-bar);  Y = (Phi(P) + Phi(P)^T) / 2;  Q = D^-T Y;  S_sym = Q D^-1,
+      // whose lower triangle is written to both triangles of A's diagonal block (so the block is
+      // exactly symmetric).
+      double *tT = ws.tmp, *tP = ws.tmp + (int64_t)nb * nb;
+      const double *dinv_b = ws.dinv + b * nb * nb;
+      const int eb = (int)std::min<int64_t>(cdiv((int64_t)w * w, 256), 64);
+      hipLaunchKernelGGL(cg::diag_sym_prep_kernel, dim3(eb), dim3(256), 0, s, w, L + j * ldl + j, ldl, tT,
+                         ws.dblk, (int64_t)nb);
+      CG_TRY(hipGetLastError());
+      CG_TRY(gemm(true, false, w, w, w, tT, nb, ws.dblk, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
+                  ws.part, 16, s));
+      hipLaunchKernelGGL(cg::diag_sym_phi_kernel, dim3(eb), dim3(256), 0, s, w, tP, (int64_t)nb);
+      CG_TRY(hipGetLastError());
+      CG_TRY(gemm(true, false, w, w, w, dinv_b, nb, tP, nb, 1.0, nullptr, 0, 0.0, tT, nb, nullptr, 0, 0,
+                  ws.part, 16, s));
+      CG_TRY(gemm(false, false, w, w, w, tT, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
+                  ws.part, 16, s));
+      hipLaunchKernelGGL(cg::diag_sym_out_kernel, dim3(eb), dim3(256), 0, s, w, (const double *)tP,
+                         (int64_t)nb, A + j * lda + j, lda);
+      CG_TRY(hipGetLastError());
+    } else {
+      CG_TRY(hipEventRecord(side->panel, s));
+      CG_TRY(hipStreamWaitEvent(s2, side->panel, 0));
+      hipLaunchKernelGGL(cg::diag_rev_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w,
+                         L + j * ldl + j, ldl, (const double *)ws.dblk, (int64_t)nb,
+                         (const double *)(ws.dinv + b * nb * nb), nb, A + j * lda + j, lda);
+      CG_TRY(hipGetLastError());
+      CG_TRY(hipEventRecord(side->diag, s2));
+    }
   }
-  CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
+  if (!sym_diag) CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
   if (sbar_form == CHOL_SBAR_TRIL) {
     const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
     hipLaunchKernelGGL(cg::sym_to_tril_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);

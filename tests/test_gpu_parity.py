@@ -66,6 +66,26 @@ def test_rev_matches_oracle(cg, dev, N, nb):
     assert np.array_equal(A, A.T)
 
 
+@pytest.mark.parametrize("N", [128, 300, 1000, 2048])
+def test_rev_diagonal_variants_agree(cg, dev, N):
+    """chol_rev picks the diagonal-block adjoint by size: the symbolic form (products with the
+    block inverse) at nb = 128 for these N, the Level-2 form otherwise.  Both match the oracle
+    and each other to rounding, on the squared-exponential kernel (worse conditioned than
+    spd_case)."""
+    c = W.se_case(N, 4000 + N, 0.3, 1e-3, with_sdot=False)
+    L = O.chol(c["Sigma"])[0]
+    Lb = c["Lbar"]
+    want = O.chol_rev(L, Lb, "sym")
+    sym = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=128).cpu().numpy()
+    lev2 = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=64).cpu().numpy()
+    kappa = np.linalg.cond(c["Sigma"])
+    tol = max(TOL, 100 * kappa * np.finfo(np.float64).eps)
+    print(f"N={N} kappa={kappa:.1e}: symbolic {rel(sym, want):.2e}  Level-2 {rel(lev2, want):.2e}  "
+          f"between {rel(sym, lev2):.2e}")
+    assert rel(sym, want) <= tol and rel(lev2, want) <= tol and rel(sym, lev2) <= tol
+    assert np.array_equal(sym, sym.T) and np.array_equal(lev2, lev2.T)
+
+
 @pytest.mark.parametrize("N,nb", [(1, 32), (65, 32), (257, 64), (300, 128)])
 def test_rev_tril_form(cg, dev, N, nb):
     S, L, Lb, Sd, junk = spd_case(N, 2000 + N)
