@@ -780,6 +780,30 @@ __global__ __launch_bounds__(256) void diag_sym_phi_kernel(int w, double *P, int
   }
 }
 
+// Operands of the symbolic forward diagonal block (w x w, leading dimension ld): Ds = the
+// symmetric matrix whose lower triangle is that of Ad (read with leading dimension lda), and
+// T = tril(D) with a zero strict upper triangle (D read with leading dimension ldd).
+__global__ __launch_bounds__(256) void diag_fwd_sym_prep_kernel(int w, const double *Ad, int64_t lda,
+                                                                const double *D, int64_t ldd, double *Ds,
+                                                                double *T, int64_t ld) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
+    const int r = e / w, c = e - r * w;
+    Ds[(int64_t)r * ld + c] = (c <= r) ? Ad[(int64_t)r * lda + c] : Ad[(int64_t)c * lda + r];
+    T[(int64_t)r * ld + c] = (c <= r) ? D[(int64_t)r * ldd + c] : 0.0;
+  }
+}
+
+// Phi in place (w x w, leading dimension ld): keep the lower triangle, halve the diagonal, zero
+// the strict upper triangle.
+__global__ __launch_bounds__(256) void phi_kernel(int w, double *Q, int64_t ld) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
+    const int r = e / w, c = e - r * w;
+    double *q = Q + (int64_t)r * ld + c;
+    if (c > r) *q = 0.0;
+    else if (c == r) *q = 0.5 * *q;
+  }
+}
+
 // A[r][c] = A[c][r] = S[r][c] for r >= c (w x w): the lower triangle of S to both triangles of A.
 __global__ __launch_bounds__(256) void diag_sym_out_kernel(int w, const double *S, int64_t lds, double *A,
                                                            int64_t lda) {

@@ -65,7 +65,7 @@ struct SweepWs {
   double *dblk = nullptr;   // one diagonal block: nb x nb
   double *part = nullptr;   // split-K partial tiles of the main stream: PART_ELEMS
   double *part2 = nullptr;  // split-K partial tiles of the side stream: PART_ELEMS
-  double *tmp = nullptr;    // two nb x nb blocks for the symbolic diagonal adjoint
+  double *tmp = nullptr;    // three nb x nb blocks for the symbolic diagonal-block variants
 };
 
 size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
@@ -76,7 +76,7 @@ size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
   w->dblk = c.take((size_t)nb * nb);
   w->part = c.take((size_t)PART_ELEMS);
   w->part2 = c.take((size_t)PART_ELEMS);
-  w->tmp = c.take((size_t)2 * nb * nb);
+  w->tmp = c.take((size_t)3 * nb * nb);
   return c.off;
 }
 
@@ -649,6 +649,10 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   return CHOL_SUCCESS;
 }
 
+// The same choice for chol_fwd's diagonal block (symbolic: L-dot_D = D Phi(D^-1 D-dot D^-T) with
+// the block inverse, the whole sweep on the caller's stream).
+bool fwd_symbolic_diag(int64_t n, int nb) { return nb == 128 && n <= 8192; }
+
 int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
@@ -678,6 +682,51 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
                      ldl, ws.dinv);
   CG_TRY(hipGetLastError());
+  if (fwd_symbolic_diag(n, nb)) {
+    // Sec. 4.2 chol_blocked_fwd, left to right, on the caller's stream only, with the symbolic
+    // diagonal block: per step the update of block b's column over all older columns, then
+    //   Ds = sym(D-dot);  P = D^-1 Ds;  Q = P D^-T;  L-dot_D = tril(D) Phi(Q),
+    // then the panel solve C-dot <- (C-dot - C L-dot_D^T) D^-T of every row below.
+    double *tDs = ws.tmp, *tT = ws.tmp + (int64_t)nb * nb, *tP = ws.tmp + 2 * (int64_t)nb * nb;
+    for (int64_t b = 0; b < nblk; ++b) {
+      const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
+      const int w = (int)(k - j);
+      const int m = (int)(n - k);
+      const double *dinv_b = ws.dinv + b * nb * nb;
+      if (j > 0) {
+        // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T over all columns [0, j)
+        CG_TRY(gemm(false, true, w, w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0, A + j * lda + j, lda,
+                    1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
+                    Pair2{L + j * ldl, ldl, A + j * lda, lda}));
+        if (m > 0)
+          CG_TRY(gemm(false, true, m, w, (int)j, A + k * lda, lda, L + j * ldl, ldl, -1.0, A + k * lda + j, lda,
+                      1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 64, s, 3, cp,
+                      Pair2{L + k * ldl, ldl, A + j * lda, lda}));
+      }
+      const int eb = (int)std::min<int64_t>(cdiv((int64_t)w * w, 256), 64);
+      hipLaunchKernelGGL(cg::diag_fwd_sym_prep_kernel, dim3(eb), dim3(256), 0, s, w,
+                         (const double *)(A + j * lda + j), lda, L + j * ldl + j, ldl, tDs, tT, (int64_t)nb);
+      CG_TRY(hipGetLastError());
+      CG_TRY(gemm(false, false, w, w, w, dinv_b, nb, tDs, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
+                  ws.part, 16, s));
+      CG_TRY(gemm(false, true, w, w, w, tP, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, tDs, nb, nullptr, 0, 0,
+                  ws.part, 16, s));
+      hipLaunchKernelGGL(cg::phi_kernel, dim3(eb), dim3(256), 0, s, w, tDs, (int64_t)nb);
+      CG_TRY(hipGetLastError());
+      CG_TRY(gemm(false, false, w, w, w, tT, nb, tDs, nb, 1.0, nullptr, 0, 0.0, A + j * lda + j, lda, nullptr,
+                  0, 0, ws.part, 16, s));
+      if (m > 0) {
+        CG_TRY(gemm(false, true, m, w, w, L + k * ldl + j, ldl, A + j * lda + j, lda, -1.0, A + k * lda + j, lda,
+                    1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 32, s));
+        CG_TRY(gemm(false, true, m, w, w, ws.panel, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, A + k * lda + j, lda,
+                    nullptr, 0, 0, ws.part, 32, s));
+      }
+    }
+    const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
+    hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
+    CG_TRY(hipGetLastError());
+    return CHOL_SUCCESS;
+  }
   CG_TRY(hipEventRecord(side->start, s));
   CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
   // Sec. 4.2 chol_blocked_fwd, left to right, with the same look-ahead as chol_factor: the chain
