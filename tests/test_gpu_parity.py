@@ -86,6 +86,24 @@ def test_rev_diagonal_variants_agree(cg, dev, N):
     assert np.array_equal(sym, sym.T) and np.array_equal(lev2, lev2.T)
 
 
+@pytest.mark.parametrize("N", [128, 300, 1000, 2048])
+def test_fwd_diagonal_variants_agree(cg, dev, N):
+    """chol_fwd's diagonal-block variants (symbolic at nb = 128 for these N, Level-2 at nb = 64)
+    match the oracle and each other to rounding; the strict upper triangle is zero in both."""
+    c = W.se_case(N, 5000 + N, 0.3, 1e-3)
+    L = O.chol(c["Sigma"])[0]
+    Sd = c["Sdot"]
+    want = O.chol_fwd(L, Sd)
+    sym = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=128).cpu().numpy()
+    lev2 = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=64).cpu().numpy()
+    kappa = np.linalg.cond(c["Sigma"])
+    tol = max(TOL, 100 * kappa * np.finfo(np.float64).eps)
+    print(f"N={N} kappa={kappa:.1e}: symbolic {rel(sym, want):.2e}  Level-2 {rel(lev2, want):.2e}  "
+          f"between {rel(sym, lev2):.2e}")
+    assert rel(sym, want) <= tol and rel(lev2, want) <= tol and rel(sym, lev2) <= tol
+    assert np.all(np.triu(sym, 1) == 0) and np.all(np.triu(lev2, 1) == 0)
+
+
 @pytest.mark.parametrize("N,nb", [(1, 32), (65, 32), (257, 64), (300, 128)])
 def test_rev_tril_form(cg, dev, N, nb):
     S, L, Lb, Sd, junk = spd_case(N, 2000 + N)
