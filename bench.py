@@ -14,7 +14,7 @@ percentiles are reported under "batched", and those of the same matrices in FP32
 MFMA, or as split-bfloat16 MFMA products) are timed alone under "f64_trail_f32" and
 "f64_trail_bf16x3"; the headline value stays the FP64 path's.  The three sweeps on the
 N = 4096 workload (lengthscale 0.3, nugget 1e-4) are timed for nb = 32, 64 and 128 under
-"n4096_by_nb".  Under
+"n4096_by_nb", and one call of each on the N = 256 dense case under "n256_latency".  Under
 "serving", a Poisson stream of factor + chol_rev requests of uneven size runs through the
 continuous-batching loop (paper_1602_07527_amd.serve) in both precision modes: p50/p99 latency and
 solves/s.
@@ -269,6 +269,47 @@ def main():
     if int((bat["info"] != 0).sum()) != 0 or not bool(torch.isfinite(bat["f"]).all()):
         raise RuntimeError("batched factorisation failed")
 
+    # Latency of one call on the N = 256 dense workload (A A^T/N + I, host-built, nb = 128):
+    # median of 20 event-timed calls each.
+    small = None
+    if args.n4096_steps > 0:
+        import statistics
+        log("[bench] N=256 call latency")
+        c = workloads.small_case()
+        S256 = torch.from_numpy(c["Sigma"]).to(dev)
+        Lb256 = torch.from_numpy(c["Lbar"]).to(dev)
+        Sd256 = torch.from_numpy(c["Sdot"]).to(dev).tril()
+        A3, B3, D3 = torch.empty_like(S256), torch.empty_like(S256), torch.empty_like(S256)
+        ws3 = torch.empty(max(cg.workspace_bytes(op, 256, 128) for op in ("factor", "rev", "fwd")),
+                          dtype=torch.uint8, device=dev)
+        info3 = torch.empty(1, dtype=torch.int32, device=dev)
+        t = {"f": [], "r": [], "d": []}
+        for i in range(21):
+            A3.copy_(S256)
+            B3.copy_(Lb256)
+            D3.copy_(Sd256)
+            torch.cuda.synchronize()
+            ev["f"][0].record()
+            cg.chol_factor(A3, nb=128, workspace=ws3, info=info3)
+            ev["f"][1].record()
+            ev["r"][0].record()
+            cg.chol_rev(A3, B3, nb=128, workspace=ws3)
+            ev["r"][1].record()
+            ev["d"][0].record()
+            cg.chol_fwd(A3, D3, nb=128, workspace=ws3)
+            ev["d"][1].record()
+            torch.cuda.synchronize()
+            if i > 0:
+                for k in t:
+                    t[k].append(ev[k][0].elapsed_time(ev[k][1]) * 1e3)
+        if int(info3.item()) != 0:
+            raise RuntimeError("N=256 chol_factor failed")
+        small = {"workload": "dense SPD N=256 (A A^T/N + I), nb=128; median of 20 event-timed calls",
+                 "chol_factor_us": round(statistics.median(t["f"]), 1),
+                 "chol_rev_us": round(statistics.median(t["r"]), 1),
+                 "chol_fwd_us": round(statistics.median(t["d"]), 1)}
+        del A3, B3, D3, ws3
+
     # The N = 4096 workload (3-D squared-exponential kernel, lengthscale 0.3, nugget 1e-4, built on
     # the device) for each block width nb: the three sweeps timed alone (median of the timed
     # passes, after one untimed pass).
@@ -473,6 +514,7 @@ def main():
         "roofline": roofline,
         "batched": batched,
         "batched_f32": batched_f32,
+        "n256_latency": small,
         "n4096_by_nb": by_nb,
         "factor_fwd_one_sweep": fused,
         "f64_trail_f32": mixed.get("f64_trail_f32"),

@@ -112,7 +112,9 @@ int chol_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int *inf
 /*
  * chol_rev -- reverse-mode propagation Sigma-bar(L, L-bar), Sec. 4.2 chol_blocked_rev, with the
  * Level-2 adjoint of Sec. 4.1 (chol_unblocked_rev, including the final Phi halving of the
- * diagonal) on each diagonal block.
+ * diagonal) on each diagonal block, or, for nb = 128 and n <= 8192, its symbolic form
+ * D^-T Phi(D^T D-bar) D^-1 (eqn (symrev) on the block) from the block inverse; the two agree to
+ * rounding.
  *   L     in : lower-triangular factor with positive diagonal (n x n, ldl); not modified.
  *   A     in : tril(A) = L-bar.   out: Sigma-bar in the form selected by sbar_form.
  *   L and A must not overlap.  A non-positive diagonal in L gives Inf/NaN, never a hang.
@@ -124,7 +126,8 @@ int chol_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int6
 
 /*
  * chol_fwd -- forward-mode propagation L-dot(L, Sigma-dot), Sec. 4.2 chol_blocked_fwd, with the
- * Level-2 chol_unblocked_fwd of Sec. 4.1 on each diagonal block:
+ * Level-2 chol_unblocked_fwd of Sec. 4.1 on each diagonal block (for nb = 128 and n <= 8192 its
+ * symbolic form D Phi(D^-1 D-dot D^-T), eqn (E8) on the block, from the block inverse):
  *   D-dot <- D-dot - tril(R-dot R^T + R R-dot^T); D-dot <- chol_unblocked_fwd(D, D-dot);
  *   C-dot <- C-dot - B-dot R^T - B R-dot^T;  C-dot <- (C-dot - C D-dot^T) D^-T.
  *   L     in : lower-triangular factor with positive diagonal (n x n, ldl); not modified.
