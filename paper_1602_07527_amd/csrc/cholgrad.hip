@@ -27,7 +27,11 @@ constexpr int TARGET_WGS = 512;  // two contraction workgroups per compute unit 
 // block kernels of the sweeps run beside the contractions on the other stream and hold most of a
 // compute unit's LDS; with more workgroups than this, some of them wait for a slot until that
 // kernel ends (measured on MI355X in the N = 16384 sweeps: 480 beats 448, 464, 496 and 504).
+// Short launches (under SK_SHORT_KTILES K-tiles per workgroup) lose the most to such a wait, and
+// take SK_WGS_SHORT workgroups (chol_rev 64.9 -> 64.2 ms, chol_factor 39.6 -> 38.8 ms, same GPU).
 constexpr int SK_WGS = 480;
+constexpr int SK_WGS_SHORT = 448;
+constexpr int64_t SK_SHORT_KTILES = 48;
 constexpr int64_t PART_SLOTS = 2 * TARGET_WGS;  // 128 x 128 partial tiles per buffer
 constexpr int64_t PART_ELEMS = PART_SLOTS * cg::GEMM_BM * cg::GEMM_BN;
 
@@ -220,13 +224,15 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
                     dma_ld_ok(lda) && dma_ld_ok(ldb) && aligned16(A) && aligned16(B) &&
                     (!q.A2 || (dma_ld_ok(q.lda2) && dma_ld_ok(q.ldb2) && aligned16(q.A2) && aligned16(q.B2)));
   const int kstep = fast ? cg::DMA_BK : cg::GEMM_BK;
-  // Stream-K on the fast kernel when the output has too few tiles: SK_WGS workgroups take equal
-  // shares of the (tile, K-tile) units, each piece deep enough (>= min_kchunk) to be worth a
-  // partial tile; the pieces are then summed per tile in workgroup order.
+  // Stream-K on the fast kernel when the output has too few tiles: SK_WGS (or SK_WGS_SHORT)
+  // workgroups take equal shares of the (tile, K-tile) units, each piece deep enough
+  // (>= min_kchunk) to be worth a partial tile; the pieces are then summed per tile in workgroup
+  // order.
   int64_t skw = 0;
   if (part && fast && !lower_only && Kt > 0 && tiles >= 2) {
     const int64_t units = (int64_t)tiles * (Kt / cg::DMA_BK);
-    skw = std::min<int64_t>(SK_WGS, units * cg::DMA_BK / std::max(min_kchunk, cg::DMA_BK));
+    skw = units < SK_SHORT_KTILES * SK_WGS ? SK_WGS_SHORT : SK_WGS;
+    skw = std::min<int64_t>(skw, units * cg::DMA_BK / std::max(min_kchunk, cg::DMA_BK));
     skw = std::min<int64_t>(skw, PART_SLOTS - tiles + 1);
     if (skw <= tiles) skw = 0;
   }
