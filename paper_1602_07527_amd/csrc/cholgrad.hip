@@ -445,6 +445,10 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
 // takes 4.9 ms against 6.0 ms; at n = 16384 the Level-2 form, hidden behind the bulk products,
 // is about 1% faster; with nb = 32 or 64 the Level-2 blocks are short and win at n = 4096 too.
 bool rev_symbolic_diag(int64_t n, int nb) { return nb == 128 && n <= 8192; }
+// Per step of a larger chol_rev: the first steps (right to left) have short trailing parts and
+// are chain-bound like a small sweep, so they take the symbolic form too, up to this many rows
+// below the block; the Level-2 form takes over once the bulk products can hide it.
+constexpr int64_t REV_SYM_ROWS = 4096;
 
 int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
@@ -475,11 +479,13 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   // part) as three small MFMA products with the block inverse on the caller's stream, so the whole
   // sweep is one stream.  Level-2: Sec. 4.1's unblocked sweep in one workgroup on the side stream,
   // overlapped with the next step's bulk product.
-  const bool sym_diag = rev_symbolic_diag(n, nb);
+  const bool sym_all = rev_symbolic_diag(n, nb);
+  auto sym_step = [&](int64_t m_below) { return sym_all || (nb == 128 && m_below <= REV_SYM_ROWS); };
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
   hipStream_t s2 = nullptr;
-  if (!sym_diag) {
+  const bool any_level2 = !sym_step(n - std::min<int64_t>(n, nb));  // the last step has the most rows
+  if (any_level2) {
     CG_TRY(side_for(s, &side));
     s2 = side->s;
   }
@@ -487,10 +493,11 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
                      ldl, ws.dinv);
   CG_TRY(hipGetLastError());
-  if (!sym_diag) {
+  if (any_level2) {
     CG_TRY(hipEventRecord(side->start, s));
     CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
   }
+  bool prev_level2 = false;  // the previous step (block b+1) left its diagonal adjoint on s2
 
   // Reverse sweep over block columns, right to left, in left-looking ("lazy") order: when block
   // [j, k) is reached, everything right of it is final and is stored as the symmetric gradient
@@ -512,7 +519,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
         CG_TRY(gemm(false, false, m2, w, m, A + (k + m1) * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                     A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0,
                     ws.part, 256, s, 1, cp));
-      if (!sym_diag) CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
+      if (prev_level2) CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
       // From here to the next diagonal adjoint every product is on the sweep's critical path and
       // has a single 128-wide tile column: fine K-splits spread it over many compute units.
       CG_TRY(gemm(false, false, m1, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
@@ -530,7 +537,8 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     } else {
       CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s));
     }
-    if (sym_diag) {
+    prev_level2 = !sym_step(m);
+    if (!prev_level2) {
       // Symbolic diagonal adjoint with D = L[j:k, j:k], its inverse from trinv, and T = tril(D):
       //   P = T^T tril(D-bar);  Y = (Phi(P) + Phi(P)^T) / 2;  Q = D^-T Y;  S_sym = Q D^-1,
       // whose lower triangle is written to both triangles of A's diagonal block (so the block is
@@ -562,7 +570,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       CG_TRY(hipEventRecord(side->diag, s2));
     }
   }
-  if (!sym_diag) CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
+  if (prev_level2) CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
   if (sbar_form == CHOL_SBAR_TRIL) {
     const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
     hipLaunchKernelGGL(cg::sym_to_tril_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
