@@ -793,14 +793,14 @@ __global__ __launch_bounds__(256) void diag_fwd_sym_prep_kernel(int w, const dou
   }
 }
 
-// Phi in place (w x w, leading dimension ld): keep the lower triangle, halve the diagonal, zero
-// the strict upper triangle.
-__global__ __launch_bounds__(256) void phi_kernel(int w, double *Q, int64_t ld) {
+// scale * Phi in place (w x w, leading dimension ld): scale the lower triangle, halve the diagonal
+// as well, zero the strict upper triangle.
+__global__ __launch_bounds__(256) void phi_kernel(int w, double *Q, int64_t ld, double scale) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
     const int r = e / w, c = e - r * w;
     double *q = Q + (int64_t)r * ld + c;
     if (c > r) *q = 0.0;
-    else if (c == r) *q = 0.5 * *q;
+    else *q = (c == r ? 0.5 * scale : scale) * *q;
   }
 }
 

@@ -515,14 +515,17 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       const int m1 = std::min(m, nb);  // rows of block b+1
       const int m2 = m - m1;           // rows below block b+1
       // X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k]   -> panel (m x w), rows below block b+1 first
-      if (m2 > 0)
-        CG_TRY(gemm(false, false, m2, w, m, A + (k + m1) * lda + k, lda, L + k * ldl + j, ldl, -2.0,
+      // After a symbolic diagonal adjoint (caller's stream) all of S_sym[k:, k:] is final: one
+      // product over all m rows.  After a Level-2 one, the rows below block b+1 go first.
+      const int mb = prev_level2 ? m2 : 0;
+      if (mb > 0)
+        CG_TRY(gemm(false, false, mb, w, m, A + (k + m1) * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                     A + (k + m1) * lda + j, lda, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0,
                     ws.part, 256, s, 1, cp));
       if (prev_level2) CG_TRY(hipStreamWaitEvent(s, side->diag, 0));
       // From here to the next diagonal adjoint every product is on the sweep's critical path and
       // has a single 128-wide tile column: fine K-splits spread it over many compute units.
-      CG_TRY(gemm(false, false, m1, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
+      CG_TRY(gemm(false, false, m - mb, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                   A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 64, s, 1, cp));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
       // triangles.
@@ -698,9 +701,13 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   CG_TRY(hipGetLastError());
   if (fwd_symbolic_diag(n, nb)) {
     // Sec. 4.2 chol_blocked_fwd, left to right, on the caller's stream only, with the symbolic
-    // diagonal block: per step the update of block b's column over all older columns, then
+    // diagonal block: per step the update of block b's column (its own rows and every row below,
+    // one contraction) over all older columns, then
     //   Ds = sym(D-dot);  P = D^-1 Ds;  Q = P D^-T;  L-dot_D = tril(D) Phi(Q),
-    // then the panel solve C-dot <- (C-dot - C L-dot_D^T) D^-T of every row below.
+    // then the panel solve C-dot <- (C-dot - C L-dot_D^T) D^-T of every row below.  Since
+    // D^-1 L-dot_D = Phi(Q), that solve is the single paired product
+    //   C-dot <- C-dot D^-T + C (-Phi(Q))^T,
+    // which reads each row of C-dot once and writes it once, in the same workgroup.
     double *tDs = ws.tmp, *tT = ws.tmp + (int64_t)nb * nb, *tP = ws.tmp + 2 * (int64_t)nb * nb;
     for (int64_t b = 0; b < nblk; ++b) {
       const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
@@ -709,13 +716,9 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
       const double *dinv_b = ws.dinv + b * nb * nb;
       if (j > 0) {
         // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T over all columns [0, j)
-        CG_TRY(gemm(false, true, w, w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0, A + j * lda + j, lda,
-                    1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
+        CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0,
+                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
                     Pair2{L + j * ldl, ldl, A + j * lda, lda}));
-        if (m > 0)
-          CG_TRY(gemm(false, true, m, w, (int)j, A + k * lda, lda, L + j * ldl, ldl, -1.0, A + k * lda + j, lda,
-                      1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 64, s, 3, cp,
-                      Pair2{L + k * ldl, ldl, A + j * lda, lda}));
       }
       const int eb = (int)std::min<int64_t>(cdiv((int64_t)w * w, 256), 64);
       hipLaunchKernelGGL(cg::diag_fwd_sym_prep_kernel, dim3(eb), dim3(256), 0, s, w,
@@ -725,16 +728,15 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
                   ws.part, 16, s));
       CG_TRY(gemm(false, true, w, w, w, tP, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, tDs, nb, nullptr, 0, 0,
                   ws.part, 16, s));
-      hipLaunchKernelGGL(cg::phi_kernel, dim3(eb), dim3(256), 0, s, w, tDs, (int64_t)nb);
+      // tDs <- -Phi(Q);  L-dot_D = tril(D) Phi(Q) = -(tril(D) tDs)
+      hipLaunchKernelGGL(cg::phi_kernel, dim3(eb), dim3(256), 0, s, w, tDs, (int64_t)nb, -1.0);
       CG_TRY(hipGetLastError());
-      CG_TRY(gemm(false, false, w, w, w, tT, nb, tDs, nb, 1.0, nullptr, 0, 0.0, A + j * lda + j, lda, nullptr,
+      CG_TRY(gemm(false, false, w, w, w, tT, nb, tDs, nb, -1.0, nullptr, 0, 0.0, A + j * lda + j, lda, nullptr,
                   0, 0, ws.part, 16, s));
-      if (m > 0) {
-        CG_TRY(gemm(false, true, m, w, w, L + k * ldl + j, ldl, A + j * lda + j, lda, -1.0, A + k * lda + j, lda,
-                    1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 32, s));
-        CG_TRY(gemm(false, true, m, w, w, ws.panel, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, A + k * lda + j, lda,
-                    nullptr, 0, 0, ws.part, 32, s));
-      }
+      if (m > 0)
+        CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, dinv_b, nb, 1.0, nullptr, 0, 0.0,
+                    A + k * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 0, cg::CP_F64,
+                    Pair2{L + k * ldl + j, ldl, tDs, nb}));
     }
     const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
     hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
