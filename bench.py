@@ -214,7 +214,7 @@ def main():
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     ws_bytes = max(cg.workspace_bytes(op, n, nb) for op in ("factor", "rev", "fwd"))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d", "b")}
+    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d", "b", "r2", "d2")}
     times = {"f": 0.0, "r": 0.0, "d": 0.0, "b": 0.0}
     if args.calibration_mib > 0:
         src = torch.ones(args.calibration_mib * 2 ** 17, dtype=torch.float64, device=dev)
@@ -324,7 +324,9 @@ def main():
                           dtype=torch.uint8, device=dev)
         info2 = torch.empty(1, dtype=torch.int32, device=dev)
         by_nb = {"workload": "squared-exponential kernel matrix N=4096 (3-D inputs, lengthscale 0.3, nugget "
-                             "1e-4, built on the device); median of the timed passes per nb"}
+                             "1e-4, built on the device); median of the timed passes per nb; chol_rev/chol_fwd "
+                             "with the default (symbolic) diagonal-block variant and, as *_level2_ms, with the "
+                             "Level-2 one"}
         for nbv in (32, 64, 128):
             t = {"f": [], "r": [], "d": []}
             for i in range(args.n4096_steps + 1):
@@ -351,6 +353,24 @@ def main():
                 "chol_factor_ms": round(med["f"], 3), "chol_factor_tflops": round(n2 ** 3 / 3.0 / (med["f"] * 1e-3) / 1e12, 2),
                 "chol_rev_ms": round(med["r"], 3), "chol_rev_tflops": round(2.0 / 3.0 * n2 ** 3 / (med["r"] * 1e-3) / 1e12, 2),
                 "chol_fwd_ms": round(med["d"], 3), "chol_fwd_tflops": round(2.0 / 3.0 * n2 ** 3 / (med["d"] * 1e-3) / 1e12, 2)}
+        # The Level-2 diagonal-block variant, in a pass of its own on the last factor (A2).
+        for nbv in (32, 64, 128):
+            t = {"r2": [], "d2": []}
+            for i in range(args.n4096_steps + 1):
+                B2.copy_(m["Lbar"])
+                ev["r2"][0].record()
+                cg.chol_rev(A2, B2, nb=nbv, workspace=ws2, diag="level2")
+                ev["r2"][1].record()
+                D2.copy_(m["Sdot"])
+                ev["d2"][0].record()
+                cg.chol_fwd(A2, D2, nb=nbv, workspace=ws2, diag="level2")
+                ev["d2"][1].record()
+                torch.cuda.synchronize()
+                if i > 0:
+                    for k in t:
+                        t[k].append(ev[k][0].elapsed_time(ev[k][1]))
+            by_nb[f"nb{nbv}"]["chol_rev_level2_ms"] = round(statistics.median(t["r2"]), 3)
+            by_nb[f"nb{nbv}"]["chol_fwd_level2_ms"] = round(statistics.median(t["d2"]), 3)
         del m, A2, B2, D2, ws2
 
     # chol_factor_fwd: potrf and the forward sweep in one pass, timed alone after one untimed pass.

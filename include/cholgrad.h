@@ -86,6 +86,21 @@ extern "C" {
 #define CHOL_SBAR_SYM 0
 #define CHOL_SBAR_TRIL 1
 
+/* Diagonal-block variant of chol_rev_ex and chol_fwd_ex (Sec. 4.2 leaves the routine for the
+ * diagonal block open; both variants give the same result up to rounding):
+ *   CHOL_DIAG_SYMBOLIC : the block's own symbolic form from its inverse D^-1 -- reverse
+ *                        D-bar <- D^-T Phi(D^T D-bar) D^-1 (eqn (symrev) on the block), forward
+ *                        D-dot <- D Phi(D^-1 D-dot D^-T) (eqn (symfwd)) -- as small MFMA products;
+ *                        every launch of the sweep on the caller's stream.
+ *   CHOL_DIAG_LEVEL2   : Sec. 4.1's unblocked chol_unblocked_rev / chol_unblocked_fwd (with the Phi
+ *                        halving of the diagonal) in one workgroup per block, on a side stream
+ *                        overlapped with the next step's trailing products.
+ *   CHOL_DIAG_AUTO     : the library's choice; currently the symbolic form for every n and nb,
+ *                        the faster of the two on MI355X at n = 256 to 16384, nb = 32, 64, 128. */
+#define CHOL_DIAG_AUTO 0
+#define CHOL_DIAG_SYMBOLIC 1
+#define CHOL_DIAG_LEVEL2 2
+
 /* Operation codes for chol_workspace_bytes. */
 #define CHOL_OP_FACTOR 0
 #define CHOL_OP_REV 1
@@ -110,11 +125,10 @@ int chol_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int *inf
                 void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * chol_rev -- reverse-mode propagation Sigma-bar(L, L-bar), Sec. 4.2 chol_blocked_rev, with the
- * Level-2 adjoint of Sec. 4.1 (chol_unblocked_rev, including the final Phi halving of the
- * diagonal) on each diagonal block, or, for nb = 128 and n <= 8192, its symbolic form
- * D^-T Phi(D^T D-bar) D^-1 (eqn (symrev) on the block) from the block inverse; the two agree to
- * rounding.
+ * chol_rev -- reverse-mode propagation Sigma-bar(L, L-bar), Sec. 4.2 chol_blocked_rev, right to
+ * left: per block C-bar <- C-bar D^-1 (panel solve), D-bar <- D-bar - tril(C-bar^T C), the
+ * diagonal block's adjoint (CHOL_DIAG_AUTO's variant), and the knock-on updates of everything to
+ * the left, gathered into one product per step.
  *   L     in : lower-triangular factor with positive diagonal (n x n, ldl); not modified.
  *   A     in : tril(A) = L-bar.   out: Sigma-bar in the form selected by sbar_form.
  *   L and A must not overlap.  A non-positive diagonal in L gives Inf/NaN, never a hang.
@@ -124,10 +138,15 @@ int chol_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int *inf
 int chol_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream);
 
+/* chol_rev with the diagonal-block variant chosen by the caller (CHOL_DIAG_*; argument 9, any
+ * other value returns -9); the remaining arguments as chol_rev's, shifted by one from workspace
+ * on.  chol_rev(...) is chol_rev_ex(..., CHOL_DIAG_AUTO, ...). */
+int chol_rev_ex(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda,
+                int sbar_form, int nb, int diag, void *workspace, size_t workspace_bytes, void *stream);
+
 /*
- * chol_fwd -- forward-mode propagation L-dot(L, Sigma-dot), Sec. 4.2 chol_blocked_fwd, with the
- * Level-2 chol_unblocked_fwd of Sec. 4.1 on each diagonal block (for nb = 128 and n <= 8192 its
- * symbolic form D Phi(D^-1 D-dot D^-T), eqn (E8) on the block, from the block inverse):
+ * chol_fwd -- forward-mode propagation L-dot(L, Sigma-dot), Sec. 4.2 chol_blocked_fwd, left to
+ * right, with the diagonal block's tangent in CHOL_DIAG_AUTO's variant:
  *   D-dot <- D-dot - tril(R-dot R^T + R R-dot^T); D-dot <- chol_unblocked_fwd(D, D-dot);
  *   C-dot <- C-dot - B-dot R^T - B R-dot^T;  C-dot <- (C-dot - C D-dot^T) D^-T.
  *   L     in : lower-triangular factor with positive diagonal (n x n, ldl); not modified.
@@ -138,6 +157,11 @@ int chol_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int6
  */
 int chol_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream);
+
+/* chol_fwd with the diagonal-block variant chosen by the caller (CHOL_DIAG_*; argument 8, any
+ * other value returns -8); chol_fwd(...) is chol_fwd_ex(..., CHOL_DIAG_AUTO, ...). */
+int chol_fwd_ex(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb,
+                int diag, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * chol_factor_fwd -- chol_factor and chol_fwd in ONE left-to-right sweep (Sec. 4.2: the forward

@@ -21,6 +21,8 @@ _PRECS = {"f64": PREC_F64, "f64_trail_f32": PREC_F64_TRAIL_F32, "f64_trail_bf16x
 SBAR_SYM, SBAR_TRIL = 0, 1
 OP_FACTOR, OP_REV, OP_FWD = 0, 1, 2
 _FORMS = {"sym": SBAR_SYM, "tril": SBAR_TRIL}
+DIAG_AUTO, DIAG_SYMBOLIC, DIAG_LEVEL2 = 0, 1, 2
+_DIAGS = {"auto": DIAG_AUTO, "symbolic": DIAG_SYMBOLIC, "level2": DIAG_LEVEL2}
 _OPS = {"factor": OP_FACTOR, "rev": OP_REV, "fwd": OP_FWD}
 
 _lib = None
@@ -47,8 +49,10 @@ def load_library():
     lib.chol_factor.argtypes = [i32, i64, vp, i64, i32, vp, vp, sz, vp]
     lib.chol_factor.restype = i32
     lib.chol_rev.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, vp, sz, vp]
+    lib.chol_rev_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, i32, vp, sz, vp]
     lib.chol_rev.restype = i32
     lib.chol_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, sz, vp]
+    lib.chol_fwd_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, vp, sz, vp]
     lib.chol_fwd.restype = i32
     lib.chol_factor_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, vp, sz, vp]
     lib.chol_factor_fwd.restype = i32
@@ -131,31 +135,33 @@ def chol_factor(A, nb=0, workspace=None, info=None, precision="f64"):
     return A, info
 
 
-def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64"):
-    """In place: tril(A) = L-bar -> A = Sigma-bar in the chosen form ('sym' or 'tril')."""
+def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64", diag="auto"):
+    """In place: tril(A) = L-bar -> A = Sigma-bar in the chosen form ('sym' or 'tril').
+    diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*)."""
     lib = load_library()
     n = _square("L", L)
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("rev", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_rev", lib.chol_rev(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
-                                        A.data_ptr(), A.stride(0) if n else 1, _FORMS[form], nb,
-                                        ws.data_ptr(), ws.numel(), _stream(A.device)))
+        _check("chol_rev", lib.chol_rev_ex(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
+                                           A.data_ptr(), A.stride(0) if n else 1, _FORMS[form], nb,
+                                           _DIAGS[diag], ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
 
-def chol_fwd(L, A, nb=0, workspace=None, precision="f64"):
-    """In place: tril(A) = tril(Sigma-dot) -> tril(A) = L-dot, strict upper set to 0."""
+def chol_fwd(L, A, nb=0, workspace=None, precision="f64", diag="auto"):
+    """In place: tril(A) = tril(Sigma-dot) -> tril(A) = L-dot, strict upper set to 0.
+    diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*)."""
     lib = load_library()
     n = _square("L", L)
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("fwd", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_fwd", lib.chol_fwd(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
-                                        A.data_ptr(), A.stride(0) if n else 1, nb, ws.data_ptr(),
-                                        ws.numel(), _stream(A.device)))
+        _check("chol_fwd", lib.chol_fwd_ex(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
+                                           A.data_ptr(), A.stride(0) if n else 1, nb, _DIAGS[diag],
+                                           ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
 

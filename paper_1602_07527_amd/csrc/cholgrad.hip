@@ -439,19 +439,17 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
   return carve(n, nb, nullptr, &w);
 }
 
-// Which diagonal-block adjoint chol_rev uses (see the sweep): the symbolic one on the caller's
-// stream, or the Level-2 one on the side stream.  Measured on MI355X (same GPU, alternating
-// builds): at n = 4096, nb = 128 the sweep is bound by its per-step chain and the symbolic form
-// takes 4.9 ms against 6.0 ms; at n = 16384 the Level-2 form, hidden behind the bulk products,
-// is about 1% faster; with nb = 32 or 64 the Level-2 blocks are short and win at n = 4096 too.
-bool rev_symbolic_diag(int64_t n, int nb) { return nb == 128 && n <= 8192; }
-// Per step of a larger chol_rev: the first steps (right to left) have short trailing parts and
-// are chain-bound like a small sweep, so they take the symbolic form too, up to this many rows
-// below the block; the Level-2 form takes over once the bulk products can hide it.
-constexpr int64_t REV_SYM_ROWS = 4096;
+// Diagonal-block variant of both sweeps (Sec. 4.2 leaves it open; the listing uses the symbolic
+// form).  CHOL_DIAG_AUTO takes the symbolic form: on MI355X (same GPU, alternating builds) it is
+// faster at every size measured, n = 256 to 16384 with nb = 32, 64 and 128.  With it each sweep is
+// one stream of launches, so the trailing rows of a step need no split around the diagonal block,
+// and its cost per block is three small MFMA products against the Level-2 routine's nb dependent
+// column steps in one workgroup.
+bool diag_ok(int diag) { return diag == CHOL_DIAG_AUTO || diag == CHOL_DIAG_SYMBOLIC || diag == CHOL_DIAG_LEVEL2; }
+bool diag_symbolic(int diag) { return diag != CHOL_DIAG_LEVEL2; }
 
-int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
-             int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
+int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
+                int sbar_form, int nb, int diag, void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   int cp = cg::CP_F64;
   if (!single_prec(precision, &cp)) return -1;
@@ -463,6 +461,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   if (lda < n) return -6;
   if (sbar_form != CHOL_SBAR_SYM && sbar_form != CHOL_SBAR_TRIL) return -7;
   if (!nb_ok(nb)) return -8;
+  if (!diag_ok(diag)) return -9;
   if (nb == 0) nb = DEFAULT_NB;
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws);
@@ -474,17 +473,15 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   double *A = static_cast<double *>(Av);
   const int64_t nblk = cdiv(n, nb);
 
-  // Diagonal-block adjoint variant (Sec. 4.2 leaves the choice open; the listing itself uses the
-  // symbolic form on the diagonal block).  Symbolic: D-bar <- D^-T Phi(D^T D-bar) D^-1 (symmetric
-  // part) as three small MFMA products with the block inverse on the caller's stream, so the whole
-  // sweep is one stream.  Level-2: Sec. 4.1's unblocked sweep in one workgroup on the side stream,
-  // overlapped with the next step's bulk product.
-  const bool sym_all = rev_symbolic_diag(n, nb);
-  auto sym_step = [&](int64_t m_below) { return sym_all || (nb == 128 && m_below <= REV_SYM_ROWS); };
+  // Diagonal-block adjoint.  Symbolic: D-bar <- D^-T Phi(D^T D-bar) D^-1 (symmetric part) as three
+  // small MFMA products with the block inverse on the caller's stream, so the whole sweep is one
+  // stream.  Level-2: Sec. 4.1's unblocked sweep in one workgroup on the side stream, overlapped
+  // with the next step's bulk product.
+  const bool sym = diag_symbolic(diag);
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
   hipStream_t s2 = nullptr;
-  const bool any_level2 = !sym_step(n - std::min<int64_t>(n, nb));  // the last step has the most rows
+  const bool any_level2 = !sym;
   if (any_level2) {
     CG_TRY(side_for(s, &side));
     s2 = side->s;
@@ -540,7 +537,7 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     } else {
       CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s));
     }
-    prev_level2 = !sym_step(m);
+    prev_level2 = !sym;
     if (!prev_level2) {
       // Symbolic diagonal adjoint with D = L[j:k, j:k], its inverse from trinv, and T = tril(D):
       //   P = T^T tril(D-bar);  Y = (Phi(P) + Phi(P)^T) / 2;  Q = D^-T Y;  S_sym = Q D^-1,
@@ -580,6 +577,12 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     CG_TRY(hipGetLastError());
   }
   return CHOL_SUCCESS;
+}
+
+int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
+             int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
+  return chol_rev_ex(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_AUTO, workspace,
+                     workspace_bytes, stream);
 }
 
 int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *info,
@@ -666,12 +669,8 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   return CHOL_SUCCESS;
 }
 
-// The same choice for chol_fwd's diagonal block (symbolic: L-dot_D = D Phi(D^-1 D-dot D^-T) with
-// the block inverse, the whole sweep on the caller's stream).
-bool fwd_symbolic_diag(int64_t n, int nb) { return nb == 128 && n <= 8192; }
-
-int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
-             void *workspace, size_t workspace_bytes, void *stream) {
+int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
+                int diag, void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   int cp = cg::CP_F64;
   if (!single_prec(precision, &cp)) return -1;
@@ -682,6 +681,7 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   if (!Av || !aligned8(Av)) return -5;
   if (lda < n) return -6;
   if (!nb_ok(nb)) return -7;
+  if (!diag_ok(diag)) return -8;
   if (nb == 0) nb = DEFAULT_NB;
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws);
@@ -692,63 +692,27 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
   const double *L = static_cast<const double *>(Lv);
   double *A = static_cast<double *>(Av);
   const int64_t nblk = cdiv(n, nb);
+  // Steps [0, b0) take the Level-2 diagonal block on the side stream with look-ahead, steps
+  // [b0, nblk) the symbolic one on the caller's stream: all steps one way or the other.
+  const int64_t b0 = diag_symbolic(diag) ? 0 : nblk;
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
-  CG_TRY(side_for(s, &side));
-  hipStream_t s2 = side->s;
+  hipStream_t s2 = nullptr;
+  if (b0 > 0) {
+    CG_TRY(side_for(s, &side));
+    s2 = side->s;
+  }
   hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
                      ldl, ws.dinv);
   CG_TRY(hipGetLastError());
-  if (fwd_symbolic_diag(n, nb)) {
-    // Sec. 4.2 chol_blocked_fwd, left to right, on the caller's stream only, with the symbolic
-    // diagonal block: per step the update of block b's column (its own rows and every row below,
-    // one contraction) over all older columns, then
-    //   Ds = sym(D-dot);  P = D^-1 Ds;  Q = P D^-T;  L-dot_D = tril(D) Phi(Q),
-    // then the panel solve C-dot <- (C-dot - C L-dot_D^T) D^-T of every row below.  Since
-    // D^-1 L-dot_D = Phi(Q), that solve is the single paired product
-    //   C-dot <- C-dot D^-T + C (-Phi(Q))^T,
-    // which reads each row of C-dot once and writes it once, in the same workgroup.
-    double *tDs = ws.tmp, *tT = ws.tmp + (int64_t)nb * nb, *tP = ws.tmp + 2 * (int64_t)nb * nb;
-    for (int64_t b = 0; b < nblk; ++b) {
-      const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
-      const int w = (int)(k - j);
-      const int m = (int)(n - k);
-      const double *dinv_b = ws.dinv + b * nb * nb;
-      if (j > 0) {
-        // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T over all columns [0, j)
-        CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0,
-                    A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
-                    Pair2{L + j * ldl, ldl, A + j * lda, lda}));
-      }
-      const int eb = (int)std::min<int64_t>(cdiv((int64_t)w * w, 256), 64);
-      hipLaunchKernelGGL(cg::diag_fwd_sym_prep_kernel, dim3(eb), dim3(256), 0, s, w,
-                         (const double *)(A + j * lda + j), lda, L + j * ldl + j, ldl, tDs, tT, (int64_t)nb);
-      CG_TRY(hipGetLastError());
-      CG_TRY(gemm(false, false, w, w, w, dinv_b, nb, tDs, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
-                  ws.part, 16, s));
-      CG_TRY(gemm(false, true, w, w, w, tP, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, tDs, nb, nullptr, 0, 0,
-                  ws.part, 16, s));
-      // tDs <- -Phi(Q);  L-dot_D = tril(D) Phi(Q) = -(tril(D) tDs)
-      hipLaunchKernelGGL(cg::phi_kernel, dim3(eb), dim3(256), 0, s, w, tDs, (int64_t)nb, -1.0);
-      CG_TRY(hipGetLastError());
-      CG_TRY(gemm(false, false, w, w, w, tT, nb, tDs, nb, -1.0, nullptr, 0, 0.0, A + j * lda + j, lda, nullptr,
-                  0, 0, ws.part, 16, s));
-      if (m > 0)
-        CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, dinv_b, nb, 1.0, nullptr, 0, 0.0,
-                    A + k * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 0, cg::CP_F64,
-                    Pair2{L + k * ldl + j, ldl, tDs, nb}));
-    }
-    const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
-    hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
-    CG_TRY(hipGetLastError());
-    return CHOL_SUCCESS;
+  if (b0 > 0) {
+    CG_TRY(hipEventRecord(side->start, s));
+    CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
   }
-  CG_TRY(hipEventRecord(side->start, s));
-  CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
   // Sec. 4.2 chol_blocked_fwd, left to right, with the same look-ahead as chol_factor: the chain
   // is panel step of the next block's rows -> update of those rows over block b-1's columns ->
   // diagonal block, everything else beside it.
-  for (int64_t b = 0; b < nblk; ++b) {
+  for (int64_t b = 0; b < b0; ++b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
     const int m = (int)(n - k);
@@ -799,7 +763,45 @@ int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
     }
     CG_TRY(hipEventRecord(side->panel, s2));
   }
-  CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+  if (b0 > 0) CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+  // Symbolic steps, on the caller's stream only (after block b0-1's panel where Level-2 steps came
+  // first): per step the update of block b's column (its own rows and every row below, one
+  // contraction) over all older columns, then
+  //   Ds = sym(D-dot);  P = D^-1 Ds;  Q = P D^-T;  L-dot_D = tril(D) Phi(Q),
+  // then the panel solve C-dot <- (C-dot - C L-dot_D^T) D^-T of every row below.  Since
+  // D^-1 L-dot_D = Phi(Q), that solve is the single paired product
+  //   C-dot <- C-dot D^-T + C (-Phi(Q))^T,
+  // which reads each row of C-dot once and writes it once, in the same workgroup.
+  double *tDs = ws.tmp, *tT = ws.tmp + (int64_t)nb * nb, *tP = ws.tmp + 2 * (int64_t)nb * nb;
+  for (int64_t b = b0; b < nblk; ++b) {
+    const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
+    const int w = (int)(k - j);
+    const int m = (int)(n - k);
+    const double *dinv_b = ws.dinv + b * nb * nb;
+    if (j > 0) {
+      // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T over all columns [0, j)
+      CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0,
+                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
+                  Pair2{L + j * ldl, ldl, A + j * lda, lda}));
+    }
+    const int eb = (int)std::min<int64_t>(cdiv((int64_t)w * w, 256), 64);
+    hipLaunchKernelGGL(cg::diag_fwd_sym_prep_kernel, dim3(eb), dim3(256), 0, s, w,
+                       (const double *)(A + j * lda + j), lda, L + j * ldl + j, ldl, tDs, tT, (int64_t)nb);
+    CG_TRY(hipGetLastError());
+    CG_TRY(gemm(false, false, w, w, w, dinv_b, nb, tDs, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
+                ws.part, 16, s));
+    CG_TRY(gemm(false, true, w, w, w, tP, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, tDs, nb, nullptr, 0, 0,
+                ws.part, 16, s));
+    // tDs <- -Phi(Q);  L-dot_D = tril(D) Phi(Q) = -(tril(D) tDs)
+    hipLaunchKernelGGL(cg::phi_kernel, dim3(eb), dim3(256), 0, s, w, tDs, (int64_t)nb, -1.0);
+    CG_TRY(hipGetLastError());
+    CG_TRY(gemm(false, false, w, w, w, tT, nb, tDs, nb, -1.0, nullptr, 0, 0.0, A + j * lda + j, lda, nullptr,
+                0, 0, ws.part, 16, s));
+    if (m > 0)
+      CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, dinv_b, nb, 1.0, nullptr, 0, 0.0,
+                  A + k * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 0, cg::CP_F64,
+                  Pair2{L + k * ldl + j, ldl, tDs, nb}));
+  }
   const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
   hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
   CG_TRY(hipGetLastError());
@@ -964,6 +966,11 @@ int chol_rev_batched(int precision, int batch, const int64_t *n, const void *con
   a.op = cg::BATCH_REV; a.batch = batch; a.f32 = precision == CHOL_PREC_F32; a.n = n; a.L = reinterpret_cast<const double *const *>(L);
   a.ldl = ldl; a.A = reinterpret_cast<double *const *>(A); a.lda = lda; a.sbar_form = sbar_form;
   return run_batched(a, n_max, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
+             void *workspace, size_t workspace_bytes, void *stream) {
+  return chol_fwd_ex(precision, n, Lv, ldl, Av, lda, nb, CHOL_DIAG_AUTO, workspace, workspace_bytes, stream);
 }
 
 int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *const *L, const int64_t *ldl,

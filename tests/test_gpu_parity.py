@@ -56,28 +56,29 @@ SIZES = [1, 2, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256, 257, 3
 NBS = [32, 64, 128]
 
 
+@pytest.mark.parametrize("diag", ["auto", "level2"])
 @pytest.mark.parametrize("nb", NBS)
 @pytest.mark.parametrize("N", SIZES)
-def test_rev_matches_oracle(cg, dev, N, nb):
+def test_rev_matches_oracle(cg, dev, N, nb, diag):
     S, L, Lb, Sd, junk = spd_case(N, 1000 + N)
-    A = cg.chol_rev(to_dev(L, dev), to_dev(Lb + junk, dev), form="sym", nb=nb).cpu().numpy()
+    A = cg.chol_rev(to_dev(L, dev), to_dev(Lb + junk, dev), form="sym", nb=nb, diag=diag).cpu().numpy()
     want = O.chol_rev(L, Lb, "sym")
     assert rel(A, want) <= TOL
     assert np.array_equal(A, A.T)
 
 
+@pytest.mark.parametrize("nb", [64, 128])
 @pytest.mark.parametrize("N", [128, 300, 1000, 2048])
-def test_rev_diagonal_variants_agree(cg, dev, N):
-    """chol_rev picks the diagonal-block adjoint by size: the symbolic form (products with the
-    block inverse) at nb = 128 for these N, the Level-2 form otherwise.  Both match the oracle
-    and each other to rounding, on the squared-exponential kernel (worse conditioned than
-    spd_case)."""
+def test_rev_diagonal_variants_agree(cg, dev, N, nb):
+    """chol_rev's diagonal-block adjoint variants, the symbolic form (products with the block
+    inverse) and the Level-2 form (Sec. 4.1's unblocked sweep), match the oracle and each other to
+    rounding, on the squared-exponential kernel (worse conditioned than spd_case)."""
     c = W.se_case(N, 4000 + N, 0.3, 1e-3, with_sdot=False)
     L = O.chol(c["Sigma"])[0]
     Lb = c["Lbar"]
     want = O.chol_rev(L, Lb, "sym")
-    sym = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=128).cpu().numpy()
-    lev2 = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=64).cpu().numpy()
+    sym = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=nb, diag="symbolic").cpu().numpy()
+    lev2 = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=nb, diag="level2").cpu().numpy()
     kappa = np.linalg.cond(c["Sigma"])
     tol = max(TOL, 100 * kappa * np.finfo(np.float64).eps)
     print(f"N={N} kappa={kappa:.1e}: symbolic {rel(sym, want):.2e}  Level-2 {rel(lev2, want):.2e}  "
@@ -86,16 +87,34 @@ def test_rev_diagonal_variants_agree(cg, dev, N):
     assert np.array_equal(sym, sym.T) and np.array_equal(lev2, lev2.T)
 
 
+def test_both_variants_large_ragged(cg, dev):
+    """Both diagonal-block variants of both sweeps at n = 8300, nb = 128 (ragged last block; the
+    Level-2 sweeps' look-ahead splits of the trailing rows; junk in the ignored upper triangles)
+    against the oracle."""
+    N = 8300
+    S, L, Lb, Sd, junk = spd_case(N, 6000)
+    Lt = to_dev(L, dev)
+    want_rev, want_fwd = O.chol_rev(L, Lb, "sym"), O.chol_fwd(L, Sd)
+    for diag in ("symbolic", "level2"):
+        A = cg.chol_rev(Lt, to_dev(Lb + junk, dev), nb=128, diag=diag).cpu().numpy()
+        assert rel(A, want_rev) <= TOL, diag
+        assert np.array_equal(A, A.T)
+        D = cg.chol_fwd(Lt, to_dev(np.tril(Sd) + junk, dev), nb=128, diag=diag).cpu().numpy()
+        assert rel(D, want_fwd) <= TOL, diag
+        assert np.all(np.triu(D, 1) == 0)
+
+
+@pytest.mark.parametrize("nb", [64, 128])
 @pytest.mark.parametrize("N", [128, 300, 1000, 2048])
-def test_fwd_diagonal_variants_agree(cg, dev, N):
-    """chol_fwd's diagonal-block variants (symbolic at nb = 128 for these N, Level-2 at nb = 64)
-    match the oracle and each other to rounding; the strict upper triangle is zero in both."""
+def test_fwd_diagonal_variants_agree(cg, dev, N, nb):
+    """chol_fwd's diagonal-block variants (symbolic and Level-2) match the oracle and each other to
+    rounding; the strict upper triangle is zero in both."""
     c = W.se_case(N, 5000 + N, 0.3, 1e-3)
     L = O.chol(c["Sigma"])[0]
     Sd = c["Sdot"]
     want = O.chol_fwd(L, Sd)
-    sym = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=128).cpu().numpy()
-    lev2 = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=64).cpu().numpy()
+    sym = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=nb, diag="symbolic").cpu().numpy()
+    lev2 = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=nb, diag="level2").cpu().numpy()
     kappa = np.linalg.cond(c["Sigma"])
     tol = max(TOL, 100 * kappa * np.finfo(np.float64).eps)
     print(f"N={N} kappa={kappa:.1e}: symbolic {rel(sym, want):.2e}  Level-2 {rel(lev2, want):.2e}  "
@@ -112,11 +131,12 @@ def test_rev_tril_form(cg, dev, N, nb):
     assert np.all(np.triu(A, 1) == 0)
 
 
+@pytest.mark.parametrize("diag", ["auto", "level2"])
 @pytest.mark.parametrize("nb", NBS)
 @pytest.mark.parametrize("N", SIZES)
-def test_fwd_matches_oracle(cg, dev, N, nb):
+def test_fwd_matches_oracle(cg, dev, N, nb, diag):
     S, L, Lb, Sd, junk = spd_case(N, 3000 + N)
-    A = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd) + junk, dev), nb=nb).cpu().numpy()
+    A = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd) + junk, dev), nb=nb, diag=diag).cpu().numpy()
     assert rel(A, O.chol_fwd(L, Sd)) <= TOL
     assert np.all(np.triu(A, 1) == 0)
 
@@ -229,14 +249,17 @@ def test_medium_case_one_sweep(cg, dev, medium):
 
 @pytest.mark.parametrize("nb", NBS)
 def test_medium_case(cg, dev, medium, nb):
-    """N = 4096 squared-exponential kernel (kappa ~ 8e6): factor, and rev/fwd on the oracle's L."""
+    """N = 4096 squared-exponential kernel (kappa ~ 8e6): factor, and rev/fwd on the oracle's L with
+    both diagonal-block variants."""
     A, info = cg.chol_factor(to_dev(medium["Sigma"], dev), nb=nb)
     assert int(info.item()) == 0
     assert rel(A.cpu().numpy(), medium["L"]) <= TOL
     Lt = to_dev(medium["L"], dev)
-    assert rel(cg.chol_rev(Lt, to_dev(medium["Lbar"], dev), nb=nb).cpu().numpy(), medium["rev"]) <= TOL
-    assert rel(cg.chol_fwd(Lt, to_dev(np.tril(medium["Sdot"]), dev), nb=nb).cpu().numpy(),
-               medium["fwd"]) <= TOL
+    for diag in ("auto", "level2"):
+        Sb = cg.chol_rev(Lt, to_dev(medium["Lbar"], dev), nb=nb, diag=diag).cpu().numpy()
+        assert rel(Sb, medium["rev"]) <= TOL, diag
+        Ld = cg.chol_fwd(Lt, to_dev(np.tril(medium["Sdot"]), dev), nb=nb, diag=diag).cpu().numpy()
+        assert rel(Ld, medium["fwd"]) <= TOL, diag
 
 
 def test_repeatable_bitwise(cg, dev):
