@@ -44,21 +44,30 @@ METRIC = "chol_rev TFLOP/s at N=16384 (% MFMA peak); batched solves/s + p99 late
 FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 matrix (MFMA) peak
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_rev_panel_contraction.json")
 GEMM_SOURCE = os.path.join(ROOT, "paper_1602_07527_amd", "csrc", "cg_gemm.hpp")
+SCHEDULE_SOURCE = os.path.join(ROOT, "paper_1602_07527_amd", "csrc", "cholgrad.hip")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def traffic_for(kernel_hash):
+def source_hashes():
+    """SHA-256 of the contraction kernel's source and of the sweep code that chooses its launches
+    (shapes, splits): a traffic record is valid only for the pair it was taken with."""
+    return {"kernel_source_sha256": hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest(),
+            "schedule_source_sha256": hashlib.sha256(open(SCHEDULE_SOURCE, "rb").read()).hexdigest()}
+
+
+def traffic_for(hashes):
     """HBM bytes per launch of the reverse-sweep contraction from the committed rocprofv3 PMC
-    record, or None when there is none or the kernel source has changed since it was taken."""
+    record, or None when there is none or the kernel or its launch schedule has changed since it
+    was taken."""
     try:
         with open(TRAFFIC_RECORD) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != kernel_hash:
+    if any(rec.get(k) != v for k, v in hashes.items()):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -84,7 +93,7 @@ def ingest_pmc(fetch_csv, write_csv, calibration_mib):
     """Scale FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what they read for the calibration copy
     of known size and record the per-launch HBM bytes of the reverse-sweep contraction."""
     known = calibration_mib * 2 ** 20
-    rec = {"kernel": TARGET_KERNEL, "kernel_source_sha256": hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest(),
+    rec = {"kernel": TARGET_KERNEL, **source_hashes(),
            "calibration": f"torch.neg of {calibration_mib} MiB float64 (reads and writes {known} bytes)"}
     per = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -507,8 +516,7 @@ def main():
 
     k_ms, k_flops, k_bytes, k_launch = prof["rev"]
     achieved = k_flops / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
-    kernel_hash = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
-    traffic = traffic_for(kernel_hash)
+    traffic = traffic_for(source_hashes())
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": traffic,

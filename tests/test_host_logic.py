@@ -48,5 +48,7 @@ def test_ingest_pmc_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     assert rec["counters"]["FETCH_SIZE"]["scale"] == pytest.approx(2.0)
     assert rec["counters"]["WRITE_SIZE"]["scale"] == pytest.approx(4.0)
     assert rec["hbm_bytes_per_launch"] == pytest.approx(2.0 * 200 * 1024 + 4.0 * 50 * 1024)
-    assert bench.traffic_for(rec["kernel_source_sha256"]) == pytest.approx(rec["hbm_bytes_per_launch"])
-    assert bench.traffic_for("0" * 64) is None
+    assert bench.traffic_for(bench.source_hashes()) == pytest.approx(rec["hbm_bytes_per_launch"])
+    # a changed kernel or a changed launch schedule invalidates the record
+    for key in ("kernel_source_sha256", "schedule_source_sha256"):
+        assert bench.traffic_for({**bench.source_hashes(), key: "0" * 64}) is None
