@@ -754,66 +754,206 @@ __global__ void set_int_kernel(int *p, int v) { *p = v; }
 
 // Convert the symmetric gradient held in both triangles to the paper's lower-triangular form
 // T = Phi(S + S^T) (eqn (symrevtril)): strict lower doubled, diagonal kept, strict upper zeroed.
-// Operands of the symbolic diagonal adjoint (w x w): T = tril(D) with a zero strict upper
-// triangle, and the strict upper triangle of Dbar cleared (both have leading dimension ld; D is
-// read with leading dimension ldd).
-__global__ __launch_bounds__(256) void diag_sym_prep_kernel(int w, const double *D, int64_t ldd, double *T,
-                                                            double *Dbar, int64_t ld) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    T[(int64_t)r * ld + c] = (c <= r) ? D[(int64_t)r * ldd + c] : 0.0;
-    if (c > r) Dbar[(int64_t)r * ld + c] = 0.0;
+// ---------------------------------------------------------------------------------------------
+// Symbolic diagonal block (w x w, w <= DIAG_MAX): three small products per sweep step, each one
+// launch with one 16 x 16 output tile per workgroup (grid = ceil(w / 16)^2, tile (blockIdx.x /
+// nt, blockIdx.x % nt)).  The four waves of a workgroup take consecutive quarters of the tile's
+// K range and their partial tiles are summed through LDS in wave order (deterministic), so each
+// workgroup reads only its own strips of the operands.  The element-wise steps between the
+// products (the triangle masks, Phi, the symmetric output) are folded into the operand accessors
+// and the epilogues, and triangular operands start the K range where their nonzeros start.
+constexpr int SYM_TILE = 16;
+
+// Sum over k in [k0, k1) of A(i, k) B(k, j) for the workgroup's 16 x 16 tile; the result is
+// valid in wave 0 only (tile_mma's layout).  `red` is 3 * 256 doubles of LDS.  Every thread of
+// the workgroup must call it.
+template <class FA, class FB>
+__device__ __forceinline__ dbl4 wg_tile16(FA A, FB B, int k0, int k1, double *red) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int span = (((k1 - k0) + 15) / 16) * 4;  // per wave, a multiple of 4
+  const int ka = k0 + wave * span, kb = min(k1, ka + span);
+  dbl4 acc{0, 0, 0, 0};
+  if (kb > ka)
+    acc = tile_mma(acc, [&](int i, int k) { return A(i, ka + k); }, [&](int k, int j) { return B(ka + k, j); },
+                   kb - ka);
+  double *r = as_lds(red);
+  if (wave > 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[(wave - 1) * 256 + e * 64 + lane] = acc[e];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += r[q * 256 + e * 64 + lane];
+  }
+  return acc;
+}
+
+// Reverse (eqn (symrev) on the block), product 1:  P = tril(D)^T tril(Dbar), lower tiles only
+// (the rest of P is never read).  D: the factor's diagonal block (ldd); Dbar: the block's
+// sensitivities (ldb; lower triangle read); P: ldp.  tril(D)^T[r][k] = D[k][r] needs k >= r and
+// tril(Dbar)[k][c] needs k >= c, so k starts at the tile's row offset.
+__global__ __launch_bounds__(256) void sym_rev_p_kernel(int w, const double *D, int64_t ldd,
+                                                        const double *Dbar, int64_t ldb, double *P,
+                                                        int64_t ldp) {
+  __shared__ double red[3 * 256];
+  const int nt = (w + SYM_TILE - 1) / SYM_TILE;
+  const int r0 = (blockIdx.x / nt) * SYM_TILE, c0 = (blockIdx.x % nt) * SYM_TILE;
+  if (c0 > r0) return;  // strictly upper tile (workgroup-uniform)
+  auto A = [&](int i, int k) {
+    const int r = r0 + i;
+    return (r < w && k < w && k >= r) ? D[(int64_t)k * ldd + r] : 0.0;
+  };
+  auto B = [&](int k, int j) {
+    const int c = c0 + j;
+    return (c < w && k < w && k >= c) ? Dbar[(int64_t)k * ldb + c] : 0.0;
+  };
+  const dbl4 acc = wg_tile16(A, B, r0, w, red);
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < w && c <= r) P[(int64_t)r * ldp + c] = acc[e];
   }
 }
 
-// Y = (Phi(P) + Phi(P)^T) / 2 in place (w x w, leading dimension ld): Phi keeps the lower
-// triangle and halves the diagonal, so Y[r][c] = Y[c][r] = P[r][c] / 2 for r >= c.  Only lower
-// entries are read, and each is read and written by its own thread.
-__global__ __launch_bounds__(256) void diag_sym_phi_kernel(int w, double *P, int64_t ld) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    if (c <= r) {
-      const double v = 0.5 * P[(int64_t)r * ld + c];
-      P[(int64_t)r * ld + c] = v;
-      P[(int64_t)c * ld + r] = v;
+// Reverse, product 2:  Q = D^-T Y with Y = (Phi(P) + Phi(P)^T) / 2, i.e. Y[k][c] =
+// P[max(k,c)][min(k,c)] / 2 read from P's lower triangle.  D^-T[r][k] = Dinv[k][r] needs k >= r.
+// Dinv: the block's inverse (ldi, lower); Q: ldq, all tiles.
+__global__ __launch_bounds__(256) void sym_rev_q_kernel(int w, const double *P, int64_t ldp,
+                                                        const double *Dinv, int64_t ldi, double *Q,
+                                                        int64_t ldq) {
+  __shared__ double red[3 * 256];
+  const int nt = (w + SYM_TILE - 1) / SYM_TILE;
+  const int r0 = (blockIdx.x / nt) * SYM_TILE, c0 = (blockIdx.x % nt) * SYM_TILE;
+  auto A = [&](int i, int k) {
+    const int r = r0 + i;
+    return (r < w && k < w && k >= r) ? Dinv[(int64_t)k * ldi + r] : 0.0;
+  };
+  auto B = [&](int k, int j) {
+    const int c = c0 + j;
+    if (c >= w || k >= w) return 0.0;
+    return 0.5 * P[k >= c ? (int64_t)k * ldp + c : (int64_t)c * ldp + k];
+  };
+  const dbl4 acc = wg_tile16(A, B, r0, w, red);
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < w && c < w) Q[(int64_t)r * ldq + c] = acc[e];
+  }
+}
+
+// Reverse, product 3:  S = Q D^-1 (D^-1[k][c] needs k >= c), lower tiles; each lower entry goes
+// to both triangles of A (lda), so the block of the symmetric gradient is exactly symmetric.
+__global__ __launch_bounds__(256) void sym_rev_s_kernel(int w, const double *Q, int64_t ldq,
+                                                        const double *Dinv, int64_t ldi, double *A,
+                                                        int64_t lda) {
+  __shared__ double red[3 * 256];
+  const int nt = (w + SYM_TILE - 1) / SYM_TILE;
+  const int r0 = (blockIdx.x / nt) * SYM_TILE, c0 = (blockIdx.x % nt) * SYM_TILE;
+  if (c0 > r0) return;
+  auto Am = [&](int i, int k) {
+    const int r = r0 + i;
+    return (r < w && k < w) ? Q[(int64_t)r * ldq + k] : 0.0;
+  };
+  auto Bm = [&](int k, int j) {
+    const int c = c0 + j;
+    return (c < w && k < w && k >= c) ? Dinv[(int64_t)k * ldi + c] : 0.0;
+  };
+  const dbl4 acc = wg_tile16(Am, Bm, c0, w, red);
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < w && c <= r) {
+      A[(int64_t)r * lda + c] = acc[e];
+      A[(int64_t)c * lda + r] = acc[e];
     }
   }
 }
 
-// Operands of the symbolic forward diagonal block (w x w, leading dimension ld): Ds = the
-// symmetric matrix whose lower triangle is that of Ad (read with leading dimension lda), and
-// T = tril(D) with a zero strict upper triangle (D read with leading dimension ldd).
-__global__ __launch_bounds__(256) void diag_fwd_sym_prep_kernel(int w, const double *Ad, int64_t lda,
-                                                                const double *D, int64_t ldd, double *Ds,
-                                                                double *T, int64_t ld) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    Ds[(int64_t)r * ld + c] = (c <= r) ? Ad[(int64_t)r * lda + c] : Ad[(int64_t)c * lda + r];
-    T[(int64_t)r * ld + c] = (c <= r) ? D[(int64_t)r * ldd + c] : 0.0;
+// Forward (eqn (symfwd) on the block), product 1:  P = D^-1 Ds, Ds the symmetric matrix with the
+// lower triangle of Ad (lda).  D^-1[r][k] needs k <= r.  P: ldp, all tiles.
+__global__ __launch_bounds__(256) void sym_fwd_p_kernel(int w, const double *Ad, int64_t lda,
+                                                        const double *Dinv, int64_t ldi, double *P,
+                                                        int64_t ldp) {
+  __shared__ double red[3 * 256];
+  const int nt = (w + SYM_TILE - 1) / SYM_TILE;
+  const int r0 = (blockIdx.x / nt) * SYM_TILE, c0 = (blockIdx.x % nt) * SYM_TILE;
+  auto Am = [&](int i, int k) {
+    const int r = r0 + i;
+    return (r < w && k <= r) ? Dinv[(int64_t)r * ldi + k] : 0.0;
+  };
+  auto Bm = [&](int k, int j) {
+    const int c = c0 + j;
+    if (c >= w || k >= w) return 0.0;
+    return Ad[k >= c ? (int64_t)k * lda + c : (int64_t)c * lda + k];
+  };
+  const dbl4 acc = wg_tile16(Am, Bm, 0, min(w, r0 + SYM_TILE), red);
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < w && c < w) P[(int64_t)r * ldp + c] = acc[e];
   }
 }
 
-// scale * Phi in place (w x w, leading dimension ld): scale the lower triangle, halve the diagonal
-// as well, zero the strict upper triangle.
-__global__ __launch_bounds__(256) void phi_kernel(int w, double *Q, int64_t ld, double scale) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    double *q = Q + (int64_t)r * ld + c;
-    if (c > r) *q = 0.0;
-    else *q = (c == r ? 0.5 * scale : scale) * *q;
+// Forward, product 2:  Q = P D^-T (D^-T[k][c] = Dinv[c][k] needs k <= c) and N = -Phi(Q) in full
+// (N: ldn): strict upper 0 (upper tiles write zeros without a product), diagonal -Q/2, strict
+// lower -Q.
+__global__ __launch_bounds__(256) void sym_fwd_n_kernel(int w, const double *P, int64_t ldp,
+                                                        const double *Dinv, int64_t ldi, double *N,
+                                                        int64_t ldn) {
+  __shared__ double red[3 * 256];
+  const int nt = (w + SYM_TILE - 1) / SYM_TILE;
+  const int r0 = (blockIdx.x / nt) * SYM_TILE, c0 = (blockIdx.x % nt) * SYM_TILE;
+  dbl4 acc{0, 0, 0, 0};
+  if (c0 <= r0) {
+    auto Am = [&](int i, int k) {
+      const int r = r0 + i;
+      return (r < w && k < w) ? P[(int64_t)r * ldp + k] : 0.0;
+    };
+    auto Bm = [&](int k, int j) {
+      const int c = c0 + j;
+      return (c < w && k <= c) ? Dinv[(int64_t)c * ldi + k] : 0.0;
+    };
+    acc = wg_tile16(Am, Bm, 0, min(w, c0 + SYM_TILE), red);
+  }
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < w && c < w) N[(int64_t)r * ldn + c] = c < r ? -acc[e] : (c == r ? -0.5 * acc[e] : 0.0);
   }
 }
 
-// A[r][c] = A[c][r] = S[r][c] for r >= c (w x w): the lower triangle of S to both triangles of A.
-__global__ __launch_bounds__(256) void diag_sym_out_kernel(int w, const double *S, int64_t lds, double *A,
-                                                           int64_t lda) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < w * w; e += gridDim.x * blockDim.x) {
-    const int r = e / w, c = e - r * w;
-    if (c <= r) {
-      const double v = S[(int64_t)r * lds + c];
-      A[(int64_t)r * lda + c] = v;
-      A[(int64_t)c * lda + r] = v;
-    }
+// Forward, product 3:  L-dot_D = tril(D) Phi(Q) = -(tril(D) N), lower tiles, lower entries written
+// to Ad (lda); D: the factor's diagonal block (ldd).  tril(D)[r][k] needs k <= r and N[k][c]
+// needs k >= c.  The strict upper triangle of Ad is left as it is.
+__global__ __launch_bounds__(256) void sym_fwd_l_kernel(int w, const double *D, int64_t ldd,
+                                                        const double *N, int64_t ldn, double *Ad,
+                                                        int64_t lda) {
+  __shared__ double red[3 * 256];
+  const int nt = (w + SYM_TILE - 1) / SYM_TILE;
+  const int r0 = (blockIdx.x / nt) * SYM_TILE, c0 = (blockIdx.x % nt) * SYM_TILE;
+  if (c0 > r0) return;
+  auto Am = [&](int i, int k) {
+    const int r = r0 + i;
+    return (r < w && k <= r) ? D[(int64_t)r * ldd + k] : 0.0;
+  };
+  auto Bm = [&](int k, int j) {
+    const int c = c0 + j;
+    return (c < w && k < w) ? N[(int64_t)k * ldn + c] : 0.0;
+  };
+  const dbl4 acc = wg_tile16(Am, Bm, c0, min(w, r0 + SYM_TILE), red);
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < w && c <= r) Ad[(int64_t)r * lda + c] = -acc[e];
   }
 }
 

@@ -69,7 +69,7 @@ struct SweepWs {
   double *dblk = nullptr;   // one diagonal block: nb x nb
   double *part = nullptr;   // split-K partial tiles of the main stream: PART_ELEMS
   double *part2 = nullptr;  // split-K partial tiles of the side stream: PART_ELEMS
-  double *tmp = nullptr;    // three nb x nb blocks for the symbolic diagonal-block variants
+  double *tmp = nullptr;    // two nb x nb blocks for the symbolic diagonal-block variants
 };
 
 size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
@@ -80,7 +80,7 @@ size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
   w->dblk = c.take((size_t)nb * nb);
   w->part = c.take((size_t)PART_ELEMS);
   w->part2 = c.take((size_t)PART_ELEMS);
-  w->tmp = c.take((size_t)3 * nb * nb);
+  w->tmp = c.take((size_t)2 * nb * nb);
   return c.off;
 }
 
@@ -539,26 +539,21 @@ int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
     }
     prev_level2 = !sym;
     if (!prev_level2) {
-      // Symbolic diagonal adjoint with D = L[j:k, j:k], its inverse from trinv, and T = tril(D):
-      //   P = T^T tril(D-bar);  Y = (Phi(P) + Phi(P)^T) / 2;  Q = D^-T Y;  S_sym = Q D^-1,
-      // whose lower triangle is written to both triangles of A's diagonal block (so the block is
-      // exactly symmetric).
-      double *tT = ws.tmp, *tP = ws.tmp + (int64_t)nb * nb;
+      // Symbolic diagonal adjoint with D = L[j:k, j:k] and its inverse from trinv, three tiled
+      // launches:  P = tril(D)^T tril(D-bar);  Q = D^-T Y with Y = (Phi(P) + Phi(P)^T) / 2;
+      // S_sym = Q D^-1, whose lower triangle is written to both triangles of A's diagonal block
+      // (so the block is exactly symmetric).
+      double *tP = ws.tmp, *tQ = ws.tmp + (int64_t)nb * nb;
       const double *dinv_b = ws.dinv + b * nb * nb;
-      const int eb = (int)std::min<int64_t>(cdiv((int64_t)w * w, 256), 64);
-      hipLaunchKernelGGL(cg::diag_sym_prep_kernel, dim3(eb), dim3(256), 0, s, w, L + j * ldl + j, ldl, tT,
-                         ws.dblk, (int64_t)nb);
+      const unsigned tiles = (unsigned)(cdiv(w, cg::SYM_TILE) * cdiv(w, cg::SYM_TILE));
+      hipLaunchKernelGGL(cg::sym_rev_p_kernel, dim3(tiles), dim3(256), 0, s, w, L + j * ldl + j, ldl,
+                         (const double *)ws.dblk, (int64_t)nb, tP, (int64_t)nb);
       CG_TRY(hipGetLastError());
-      CG_TRY(gemm(true, false, w, w, w, tT, nb, ws.dblk, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
-                  ws.part, 16, s));
-      hipLaunchKernelGGL(cg::diag_sym_phi_kernel, dim3(eb), dim3(256), 0, s, w, tP, (int64_t)nb);
+      hipLaunchKernelGGL(cg::sym_rev_q_kernel, dim3(tiles), dim3(256), 0, s, w, (const double *)tP,
+                         (int64_t)nb, dinv_b, (int64_t)nb, tQ, (int64_t)nb);
       CG_TRY(hipGetLastError());
-      CG_TRY(gemm(true, false, w, w, w, dinv_b, nb, tP, nb, 1.0, nullptr, 0, 0.0, tT, nb, nullptr, 0, 0,
-                  ws.part, 16, s));
-      CG_TRY(gemm(false, false, w, w, w, tT, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
-                  ws.part, 16, s));
-      hipLaunchKernelGGL(cg::diag_sym_out_kernel, dim3(eb), dim3(256), 0, s, w, (const double *)tP,
-                         (int64_t)nb, A + j * lda + j, lda);
+      hipLaunchKernelGGL(cg::sym_rev_s_kernel, dim3(tiles), dim3(256), 0, s, w, (const double *)tQ,
+                         (int64_t)nb, dinv_b, (int64_t)nb, A + j * lda + j, lda);
       CG_TRY(hipGetLastError());
     } else {
       CG_TRY(hipEventRecord(side->panel, s));
@@ -772,7 +767,7 @@ int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
   // D^-1 L-dot_D = Phi(Q), that solve is the single paired product
   //   C-dot <- C-dot D^-T + C (-Phi(Q))^T,
   // which reads each row of C-dot once and writes it once, in the same workgroup.
-  double *tDs = ws.tmp, *tT = ws.tmp + (int64_t)nb * nb, *tP = ws.tmp + 2 * (int64_t)nb * nb;
+  double *tN = ws.tmp, *tP = ws.tmp + (int64_t)nb * nb;  // tN = -Phi(Q)
   for (int64_t b = b0; b < nblk; ++b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
@@ -784,23 +779,22 @@ int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
                   A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
                   Pair2{L + j * ldl, ldl, A + j * lda, lda}));
     }
-    const int eb = (int)std::min<int64_t>(cdiv((int64_t)w * w, 256), 64);
-    hipLaunchKernelGGL(cg::diag_fwd_sym_prep_kernel, dim3(eb), dim3(256), 0, s, w,
-                       (const double *)(A + j * lda + j), lda, L + j * ldl + j, ldl, tDs, tT, (int64_t)nb);
+    // Three tiled launches: tP = D^-1 Ds;  tN = -Phi(tP D^-T);  L-dot_D = -(tril(D) tN) into A's
+    // diagonal block.
+    const unsigned tiles = (unsigned)(cdiv(w, cg::SYM_TILE) * cdiv(w, cg::SYM_TILE));
+    hipLaunchKernelGGL(cg::sym_fwd_p_kernel, dim3(tiles), dim3(256), 0, s, w, (const double *)(A + j * lda + j),
+                       lda, dinv_b, (int64_t)nb, tP, (int64_t)nb);
     CG_TRY(hipGetLastError());
-    CG_TRY(gemm(false, false, w, w, w, dinv_b, nb, tDs, nb, 1.0, nullptr, 0, 0.0, tP, nb, nullptr, 0, 0,
-                ws.part, 16, s));
-    CG_TRY(gemm(false, true, w, w, w, tP, nb, dinv_b, nb, 1.0, nullptr, 0, 0.0, tDs, nb, nullptr, 0, 0,
-                ws.part, 16, s));
-    // tDs <- -Phi(Q);  L-dot_D = tril(D) Phi(Q) = -(tril(D) tDs)
-    hipLaunchKernelGGL(cg::phi_kernel, dim3(eb), dim3(256), 0, s, w, tDs, (int64_t)nb, -1.0);
+    hipLaunchKernelGGL(cg::sym_fwd_n_kernel, dim3(tiles), dim3(256), 0, s, w, (const double *)tP, (int64_t)nb,
+                       dinv_b, (int64_t)nb, tN, (int64_t)nb);
     CG_TRY(hipGetLastError());
-    CG_TRY(gemm(false, false, w, w, w, tT, nb, tDs, nb, -1.0, nullptr, 0, 0.0, A + j * lda + j, lda, nullptr,
-                0, 0, ws.part, 16, s));
+    hipLaunchKernelGGL(cg::sym_fwd_l_kernel, dim3(tiles), dim3(256), 0, s, w, L + j * ldl + j, ldl,
+                       (const double *)tN, (int64_t)nb, A + j * lda + j, lda);
+    CG_TRY(hipGetLastError());
     if (m > 0)
       CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, dinv_b, nb, 1.0, nullptr, 0, 0.0,
                   A + k * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 0, cg::CP_F64,
-                  Pair2{L + k * ldl + j, ldl, tDs, nb}));
+                  Pair2{L + k * ldl + j, ldl, tN, nb}));
   }
   const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
   hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
