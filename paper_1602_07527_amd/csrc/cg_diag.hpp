@@ -957,6 +957,41 @@ __global__ __launch_bounds__(256) void sym_fwd_l_kernel(int w, const double *D, 
   }
 }
 
+// Reverse-sweep panel solve C-bar/2 = alpha X D^-1 (X: M x w panel, ldx; D^-1 lower, ldi, so
+// k >= c), written to C (ldc) and mirrored to Cm (ldcm: Cm[c][r] = C[r][c]).  One 16 x 16 output
+// tile per workgroup with the K range split over its waves, so there are no partial tiles to
+// reduce.  The w/16 column tiles of one 16-row strip go to workgroups 8 apart in launch order
+// (one XCD under round-robin dispatch), so each strip of the panel is fetched into one L2; grid =
+// ceil(ceil(M/16) / 8) * 8 * ceil(w/16).
+__global__ __launch_bounds__(256) void rev_panel_solve_kernel(int M, int w, const double *X, int64_t ldx,
+                                                              const double *Dinv, int64_t ldi, double alpha,
+                                                              double *C, int64_t ldc, double *Cm, int64_t ldcm) {
+  __shared__ double red[3 * 256];
+  const int nct = (w + SYM_TILE - 1) / SYM_TILE;
+  const int g = blockIdx.x;
+  const int r0 = ((g / (8 * nct)) * 8 + (g % 8)) * SYM_TILE, c0 = ((g / 8) % nct) * SYM_TILE;
+  if (r0 >= M) return;  // padding of the last group of strips (workgroup-uniform)
+  auto A = [&](int i, int k) {
+    const int r = r0 + i;
+    return (r < M && k < w) ? X[(int64_t)r * ldx + k] : 0.0;
+  };
+  auto B = [&](int k, int j) {
+    const int c = c0 + j;
+    return (c < w && k < w && k >= c) ? Dinv[(int64_t)k * ldi + c] : 0.0;
+  };
+  const dbl4 acc = wg_tile16(A, B, c0, w, red);
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < M && c < w) {
+      const double v = alpha * acc[e];
+      C[(int64_t)r * ldc + c] = v;
+      if (Cm) Cm[(int64_t)c * ldcm + r] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void sym_to_tril_kernel(int64_t n, double *A, int64_t lda) {
   const int64_t total = n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;

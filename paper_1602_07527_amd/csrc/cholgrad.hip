@@ -526,8 +526,14 @@ int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
                   A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 64, s, 1, cp));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
       // triangles.
-      CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0,
-                  0.0, A + k * lda + j, lda, A + j * lda + k, lda, 0, ws.part, 32, s));
+      {
+        const int64_t nct = cdiv(w, cg::SYM_TILE);
+        const unsigned grid = (unsigned)(cdiv(cdiv(m, cg::SYM_TILE), 8) * 8 * nct);
+        hipLaunchKernelGGL(cg::rev_panel_solve_kernel, dim3(grid), dim3(256), 0, s, m, w, (const double *)ws.panel,
+                           (int64_t)nb, (const double *)(ws.dinv + b * nb * nb), (int64_t)nb, 0.5,
+                           A + k * lda + j, lda, A + j * lda + k, lda);
+        CG_TRY(hipGetLastError());
+      }
       // D-bar = tril(L-bar_D) - tril(C-bar^T C), C-bar = 2 * A[k:, j:k]   -> dblk (w x w).  On the
       // caller's stream, before the next step's bulk product is queued: a small split-K product
       // that runs fastest with the whole GPU to itself, and the diagonal adjoint released after
