@@ -992,6 +992,42 @@ __global__ __launch_bounds__(256) void rev_panel_solve_kernel(int M, int w, cons
   }
 }
 
+// Forward-sweep panel solve with the symbolic diagonal block:  Out = Cd D^-T + Cl N^T  (M x w),
+// N = -Phi(Q) and D^-1 both lower, so both terms run over k <= c; Cd (ldcd) is the updated
+// C-dot, Cl (ldcl) the factor's panel C, Out (ldo) must not overlap Cd.  Same tiling and
+// strip-to-XCD mapping as rev_panel_solve_kernel; the two terms form one K range of 2 kq.
+__global__ __launch_bounds__(256) void fwd_panel_solve_kernel(int M, int w, const double *Cd, int64_t ldcd,
+                                                              const double *Cl, int64_t ldcl,
+                                                              const double *Dinv, int64_t ldi,
+                                                              const double *N, int64_t ldn, double *Out,
+                                                              int64_t ldo) {
+  __shared__ double red[3 * 256];
+  const int nct = (w + SYM_TILE - 1) / SYM_TILE;
+  const int g = blockIdx.x;
+  const int r0 = ((g / (8 * nct)) * 8 + (g % 8)) * SYM_TILE, c0 = ((g / 8) % nct) * SYM_TILE;
+  if (r0 >= M) return;  // padding of the last group of strips (workgroup-uniform)
+  const int kq = min(w, c0 + SYM_TILE);
+  auto A = [&](int i, int k) {
+    const int r = r0 + i;
+    if (r >= M) return 0.0;
+    return k < kq ? Cd[(int64_t)r * ldcd + k] : Cl[(int64_t)r * ldcl + (k - kq)];
+  };
+  auto B = [&](int k, int j) {
+    const int c = c0 + j;
+    if (c >= w) return 0.0;
+    const int kk = k < kq ? k : k - kq;
+    if (kk > c) return 0.0;
+    return k < kq ? Dinv[(int64_t)c * ldi + kk] : N[(int64_t)c * ldn + kk];
+  };
+  const dbl4 acc = wg_tile16(A, B, 0, 2 * kq, red);
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < M && c < w) Out[(int64_t)r * ldo + c] = acc[e];
+  }
+}
+
 __global__ __launch_bounds__(256) void sym_to_tril_kernel(int64_t n, double *A, int64_t lda) {
   const int64_t total = n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;

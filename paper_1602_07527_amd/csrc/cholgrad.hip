@@ -771,25 +771,33 @@ int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
   //   Ds = sym(D-dot);  P = D^-1 Ds;  Q = P D^-T;  L-dot_D = tril(D) Phi(Q),
   // then the panel solve C-dot <- (C-dot - C L-dot_D^T) D^-T of every row below.  Since
   // D^-1 L-dot_D = Phi(Q), that solve is the single paired product
-  //   C-dot <- C-dot D^-T + C (-Phi(Q))^T,
-  // which reads each row of C-dot once and writes it once, in the same workgroup.
+  //   L-dot_C = C-dot D^-T + C (-Phi(Q))^T.
   double *tN = ws.tmp, *tP = ws.tmp + (int64_t)nb * nb;  // tN = -Phi(Q)
   for (int64_t b = b0; b < nblk; ++b) {
     const int64_t j = b * nb, k = std::min<int64_t>(n, j + nb);
     const int w = (int)(k - j);
     const int m = (int)(n - k);
     const double *dinv_b = ws.dinv + b * nb * nb;
+    // Panel solve for nb < 128: the tiled kernel, which reads C-dot from the workspace panel
+    // (ld nb) and writes L-dot_C to A, so the update puts the block column [D-dot; C-dot] there.
+    // For nb = 128 the paired product on 128 x 128 tiles is faster (it reuses each operand strip
+    // across all columns): the update and the solve then work in place in A.
+    const bool tiled = nb < 128;
+    double *const col = tiled ? ws.panel : A + j * lda + j;
+    const int64_t ldcol = tiled ? (int64_t)nb : lda;
     if (j > 0) {
-      // [D-dot; C-dot] -= [R-dot; B-dot] R^T + [R; B] R-dot^T over all columns [0, j)
+      // [D-dot; C-dot] = Sigma-dot's block column - [R-dot; B-dot] R^T - [R; B] R-dot^T over [0, j)
       CG_TRY(gemm(false, true, (int)(n - j), w, (int)j, A + j * lda, lda, L + j * ldl, ldl, -1.0,
-                  A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 3, cp,
+                  A + j * lda + j, lda, 1.0, col, ldcol, nullptr, 0, 0, ws.part, 32, s, 3, cp,
                   Pair2{L + j * ldl, ldl, A + j * lda, lda}));
+    } else if (tiled) {
+      CG_TRY(copy_scaled((int)n, w, A, lda, 1.0, col, ldcol, 0, s));  // first column: no update
     }
     // Three tiled launches: tP = D^-1 Ds;  tN = -Phi(tP D^-T);  L-dot_D = -(tril(D) tN) into A's
     // diagonal block.
     const unsigned tiles = (unsigned)(cdiv(w, cg::SYM_TILE) * cdiv(w, cg::SYM_TILE));
-    hipLaunchKernelGGL(cg::sym_fwd_p_kernel, dim3(tiles), dim3(256), 0, s, w, (const double *)(A + j * lda + j),
-                       lda, dinv_b, (int64_t)nb, tP, (int64_t)nb);
+    hipLaunchKernelGGL(cg::sym_fwd_p_kernel, dim3(tiles), dim3(256), 0, s, w, (const double *)col, ldcol, dinv_b,
+                       (int64_t)nb, tP, (int64_t)nb);
     CG_TRY(hipGetLastError());
     hipLaunchKernelGGL(cg::sym_fwd_n_kernel, dim3(tiles), dim3(256), 0, s, w, (const double *)tP, (int64_t)nb,
                        dinv_b, (int64_t)nb, tN, (int64_t)nb);
@@ -797,10 +805,19 @@ int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
     hipLaunchKernelGGL(cg::sym_fwd_l_kernel, dim3(tiles), dim3(256), 0, s, w, L + j * ldl + j, ldl,
                        (const double *)tN, (int64_t)nb, A + j * lda + j, lda);
     CG_TRY(hipGetLastError());
-    if (m > 0)
+    if (m > 0 && tiled) {
+      const int64_t nct = cdiv(w, cg::SYM_TILE);
+      const unsigned grid = (unsigned)(cdiv(cdiv(m, cg::SYM_TILE), 8) * 8 * nct);
+      hipLaunchKernelGGL(cg::fwd_panel_solve_kernel, dim3(grid), dim3(256), 0, s, m, w,
+                         (const double *)(col + w * ldcol), ldcol, L + k * ldl + j, ldl, dinv_b, (int64_t)nb,
+                         (const double *)tN, (int64_t)nb, A + k * lda + j, lda);
+      CG_TRY(hipGetLastError());
+    } else if (m > 0) {
+      // in place: each 128-row tile's workgroup reads its rows of C-dot before it writes them
       CG_TRY(gemm(false, true, m, w, w, A + k * lda + j, lda, dinv_b, nb, 1.0, nullptr, 0, 0.0,
                   A + k * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 0, cg::CP_F64,
                   Pair2{L + k * ldl + j, ldl, tN, nb}));
+    }
   }
   const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
   hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
