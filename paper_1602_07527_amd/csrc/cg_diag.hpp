@@ -7,6 +7,12 @@
 //   diag_rev_kernel : D-bar <- chol_unblocked_rev(D, D-bar)     (Sec. 4.1, Phi halving included)
 //   diag_fwd_kernel : D-dot <- chol_unblocked_fwd(D, D-dot)     (Sec. 4.1, eqns (dub1), (dub2))
 //   potf2_kernel    : D <- chol_unblocked(D) (Sec. 4.1, DPOTF2) and D^-1
+// and the symbolic diagonal-block forms (three tiled MFMA launches per block, one 16 x 16 output
+// tile per workgroup) plus the tiled panel solves of both sweeps:
+//   sym_rev_{p,q,s}_kernel : D-bar <- D^-T Phi(D^T D-bar) D^-1, symmetric part (eqn (symrev))
+//   sym_fwd_{p,n,l}_kernel : D-dot <- D Phi(D^-1 D-dot D^-T)                  (eqn (symfwd))
+//   rev_panel_solve_kernel : C-bar/2 = X D^-1 / 2 with its mirrored store
+//   fwd_panel_solve_kernel : L-dot_C = C-dot D^-T + C (-Phi(Q))^T
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
