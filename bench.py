@@ -19,6 +19,11 @@ N = 4096 workload (lengthscale 0.3, nugget 1e-4) are timed for nb = 32, 64 and 1
 continuous-batching loop (paper_1602_07527_amd.serve) in both precision modes: p50/p99 latency and
 solves/s.
 
+Roofline: the dominant kernel (chol_rev's panel contraction) is timed per launch by HIP events the
+library records around each launch on the call's stream, in a kernel-timing pass of one or two
+extra steps after the timed ones (the events leave the GPU idle for a few microseconds per launch,
+so the timed steps run without them).
+
 Output: one JSON line on stdout.  `--gpus` above 1 is refused (single-GPU build).
 
 HBM traffic of the dominant kernel: run this script twice under `rocprofv3 --pmc FETCH_SIZE` and
@@ -26,7 +31,7 @@ HBM traffic of the dominant kernel: run this script twice under `rocprofv3 --pmc
 --calibration-mib 1024` (the calibration is one plain elementwise copy, torch.neg, of a known
 size, whose counters give the scale factor), then `--ingest-pmc FETCH.csv WRITE.csv
 --calibration-mib 1024` writes the per-launch record that later runs report as roofline.traffic
-while the kernel source is unchanged.
+while the kernel source and the sweep code that chooses its launches are unchanged.
 """
 import csv
 import argparse
@@ -259,7 +264,6 @@ def main():
     if int(info.item()) != 0:
         raise RuntimeError(f"chol_factor reported info={int(info.item())}")
 
-    cg.profile_begin()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -270,7 +274,17 @@ def main():
         log(f"[bench] timed step {i + 1}/{args.steps}: rev {ev['r'][0].elapsed_time(ev['r'][1]):.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # Kernel-level timing for the roofline: the same step again with the library's HIP events
+    # around every panel-contraction launch (recorded on the stream the kernels run on).  A pass
+    # of its own, because the events between launches leave the GPU idle for a few microseconds
+    # each (about 1.8 ms per chol_rev call), which the timed steps above must not include.
+    prof_steps = max(1, min(args.steps, 2))
+    cg.profile_begin()
+    for i in range(prof_steps):
+        step(False)
+        torch.cuda.synchronize()
     prof = cg.profile_end()
+    log(f"[bench] kernel-timing pass of {prof_steps} step(s) done")
     if int(info.item()) != 0:
         raise RuntimeError(f"chol_factor reported info={int(info.item())}")
     if not bool(torch.isfinite(Ab).all()) or not bool(torch.isfinite(Ad).all()):
@@ -524,7 +538,8 @@ def main():
                 "kernel_avg_us": round(k_ms * 1e3 / max(k_launch, 1), 2),
                 "algorithmic_bytes_per_launch": round(k_bytes / max(k_launch, 1)),
                 "algorithmic_flops_per_launch": round(k_flops / max(k_launch, 1)),
-                "launches_per_step": k_launch // K}
+                "launches_per_step": k_launch // prof_steps,
+                "kernel_timing": f"library HIP events around each launch, {prof_steps} extra step(s) after the timed ones"}
 
     out = {
         "metric": METRIC, "value": round(rev_tflops, 3), "unit": "TFLOP/s", "n_gpus": 1,
