@@ -28,6 +28,14 @@ _OPS = {"factor": OP_FACTOR, "rev": OP_REV, "fwd": OP_FWD}
 _lib = None
 
 
+def _pick(table, key, what):
+    """table[key], or a ValueError naming the accepted values."""
+    try:
+        return table[key]
+    except (KeyError, TypeError):
+        raise ValueError(f"unknown {what} {key!r}; expected one of {sorted(table)}") from None
+
+
 class CholError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__(f"{fn} returned {status}: {msg}")
@@ -106,7 +114,8 @@ def _stream(device):
 
 def workspace_bytes(op, n, nb=0, precision="f64"):
     """Device workspace bytes for op in {'factor', 'rev', 'fwd'} at size n and block size nb."""
-    return int(load_library().chol_workspace_bytes(_OPS[op], _PRECS[precision], int(n), int(nb)))
+    op_code, prec = _pick(_OPS, op, "op"), _pick(_PRECS, precision, "precision")
+    return int(load_library().chol_workspace_bytes(op_code, prec, int(n), int(nb)))
 
 
 def _workspace(op, n, nb, device, workspace, precision="f64"):
@@ -124,12 +133,13 @@ def chol_factor(A, nb=0, workspace=None, info=None, precision="f64"):
     precision: 'f64', 'f64_trail_f32' (trailing updates on FP32 MFMA) or 'f64_trail_bf16x3'
     (trailing updates as split-bfloat16 products)."""
     lib = load_library()
+    prec = _pick(_PRECS, precision, "precision")
     n = _square("A", A)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
     ws = _workspace("factor", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_factor", lib.chol_factor(_PRECS[precision], n, A.data_ptr(), A.stride(0) if n else 1, nb,
+        _check("chol_factor", lib.chol_factor(prec, n, A.data_ptr(), A.stride(0) if n else 1, nb,
                                               info.data_ptr(), ws.data_ptr(), ws.numel(),
                                               _stream(A.device)))
     return A, info
@@ -139,14 +149,15 @@ def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64", diag="auto
     """In place: tril(A) = L-bar -> A = Sigma-bar in the chosen form ('sym' or 'tril').
     diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*)."""
     lib = load_library()
+    prec, fm, dv = _pick(_PRECS, precision, "precision"), _pick(_FORMS, form, "form"), _pick(_DIAGS, diag, "diag")
     n = _square("L", L)
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("rev", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_rev", lib.chol_rev_ex(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
-                                           A.data_ptr(), A.stride(0) if n else 1, _FORMS[form], nb,
-                                           _DIAGS[diag], ws.data_ptr(), ws.numel(), _stream(A.device)))
+        _check("chol_rev", lib.chol_rev_ex(prec, n, L.data_ptr(), L.stride(0) if n else 1,
+                                           A.data_ptr(), A.stride(0) if n else 1, fm, nb, dv,
+                                           ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
 
@@ -154,13 +165,14 @@ def chol_fwd(L, A, nb=0, workspace=None, precision="f64", diag="auto"):
     """In place: tril(A) = tril(Sigma-dot) -> tril(A) = L-dot, strict upper set to 0.
     diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*)."""
     lib = load_library()
+    prec, dv = _pick(_PRECS, precision, "precision"), _pick(_DIAGS, diag, "diag")
     n = _square("L", L)
     if _square("A", A) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("fwd", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_fwd", lib.chol_fwd_ex(_PRECS[precision], n, L.data_ptr(), L.stride(0) if n else 1,
-                                           A.data_ptr(), A.stride(0) if n else 1, nb, _DIAGS[diag],
+        _check("chol_fwd", lib.chol_fwd_ex(prec, n, L.data_ptr(), L.stride(0) if n else 1,
+                                           A.data_ptr(), A.stride(0) if n else 1, nb, dv,
                                            ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
@@ -169,6 +181,7 @@ def chol_factor_fwd(A, D, nb=0, workspace=None, info=None, precision="f64"):
     """In place, one sweep: tril(A) = Sigma -> L and tril(D) = tril(Sigma-dot) -> L-dot (strict
     upper triangles set to 0).  Returns (A, D, info)."""
     lib = load_library()
+    prec = _pick(_PRECS, precision, "precision")
     n = _square("A", A)
     if _square("D", D) != n or D.device != A.device:
         raise ValueError("A and D must have the same size and device")
@@ -176,7 +189,7 @@ def chol_factor_fwd(A, D, nb=0, workspace=None, info=None, precision="f64"):
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
     ws = _workspace("fwd", n, nb, A.device, workspace, precision)
     with torch.cuda.device(A.device):
-        _check("chol_factor_fwd", lib.chol_factor_fwd(_PRECS[precision], n, A.data_ptr(), A.stride(0) if n else 1,
+        _check("chol_factor_fwd", lib.chol_factor_fwd(prec, n, A.data_ptr(), A.stride(0) if n else 1,
                                                       D.data_ptr(), D.stride(0) if n else 1, nb, info.data_ptr(),
                                                       ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A, D, info
@@ -311,7 +324,7 @@ def chol_rev_batched(L, A, form="sym", workspace=None):
     with torch.cuda.device(A.device):
         _check("chol_rev_batched", lib.chol_rev_batched(
             A.prec, len(A), A.n.data_ptr(), L.ptr.data_ptr(), L.ld.data_ptr(), A.ptr.data_ptr(),
-            A.ld.data_ptr(), A.n_max, _FORMS[form], ws.data_ptr(), ws.numel(), _stream(A.device)))
+            A.ld.data_ptr(), A.n_max, _pick(_FORMS, form, "form"), ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A.mats
 
 
@@ -342,7 +355,7 @@ def chol_factor_rev_batched(A, G, form="sym", info=None, workspace=None):
     with torch.cuda.device(A.device):
         _check("chol_factor_rev_batched", lib.chol_factor_rev_batched(
             A.prec, len(A), A.n.data_ptr(), A.ptr.data_ptr(), A.ld.data_ptr(), G.ptr.data_ptr(),
-            G.ld.data_ptr(), A.n_max, _FORMS[form], info.data_ptr(), ws.data_ptr(), ws.numel(),
+            G.ld.data_ptr(), A.n_max, _pick(_FORMS, form, "form"), info.data_ptr(), ws.data_ptr(), ws.numel(),
             _stream(A.device)))
     return info
 

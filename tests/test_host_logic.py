@@ -52,3 +52,16 @@ def test_ingest_pmc_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     # a changed kernel or a changed launch schedule invalidates the record
     for key in ("kernel_source_sha256", "schedule_source_sha256"):
         assert bench.traffic_for({**bench.source_hashes(), key: "0" * 64}) is None
+
+
+def test_binding_rejects_unknown_names():
+    """Unknown precision / form / diagonal-variant / op names are a ValueError naming the choices,
+    raised on the host before any workspace is allocated."""
+    from paper_1602_07527_amd import _binding as b
+    for table, key, what in ((b._DIAGS, "recursive", "diag"), (b._FORMS, "upper", "form"),
+                             (b._PRECS, "bf16", "precision"), (b._OPS, "solve", "op")):
+        with pytest.raises(ValueError, match=what):
+            b._pick(table, key, what)
+    assert b._pick(b._DIAGS, "level2", "diag") == b.DIAG_LEVEL2 == 2
+    with pytest.raises(ValueError, match="precision"):
+        b.workspace_bytes("rev", 100, precision="f16")
