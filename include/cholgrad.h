@@ -101,6 +101,19 @@ extern "C" {
 #define CHOL_DIAG_SYMBOLIC 1
 #define CHOL_DIAG_LEVEL2 2
 
+/* Storage layout of the n x n matrices of chol_factor_ex, chol_rev_ex and chol_fwd_ex (the other
+ * entry points are row-major):
+ *   CHOL_LAYOUT_ROW_MAJOR : element (i, j) at A[i*ld + j];
+ *   CHOL_LAYOUT_COL_MAJOR : element (i, j) at A[i + j*ld], LAPACK's layout (equivalently: the
+ *                           upper-triangular factor U = L^T in row-major storage).
+ * In both layouts the lower triangle of each input is read and every output has the same meaning
+ * (L and L-dot lower triangular with a zero strict upper triangle; Sigma-bar in the chosen form).
+ * The column-major calls convert in place with element-wise kernels (a few extra passes over each
+ * n x n array); chol_rev_ex and chol_fwd_ex also copy L, transposed, into the workspace (n*n more
+ * doubles, included by chol_workspace_bytes_ex). */
+#define CHOL_LAYOUT_ROW_MAJOR 0
+#define CHOL_LAYOUT_COL_MAJOR 1
+
 /* Operation codes for chol_workspace_bytes. */
 #define CHOL_OP_FACTOR 0
 #define CHOL_OP_REV 1
@@ -109,6 +122,10 @@ extern "C" {
 /* Bytes of device workspace that a call with these parameters needs (0 for n == 0).  Returns 0
  * as well for invalid parameters; the call itself then reports the error. */
 size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb);
+
+/* The same for a storage layout (CHOL_LAYOUT_*); 0 for an unknown layout.  Row-major: equal to
+ * chol_workspace_bytes. */
+size_t chol_workspace_bytes_ex(int op, int precision, int64_t n, int nb, int layout);
 
 /*
  * chol_factor -- blocked Cholesky factorisation, Sec. 4.2 chol_blocked (left-looking DPOTRF):
@@ -124,6 +141,12 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb);
 int chol_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int *info,
                 void *workspace, size_t workspace_bytes, void *stream);
 
+/* chol_factor with the storage layout of A chosen by the caller (CHOL_LAYOUT_*, argument 6; any
+ * other value returns -6; info is argument 7, -7 when NULL).  chol_factor(...) is
+ * chol_factor_ex(..., CHOL_LAYOUT_ROW_MAJOR, ...). */
+int chol_factor_ex(int precision, int64_t n, void *A, int64_t lda, int nb, int layout, int *info,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
 /*
  * chol_rev -- reverse-mode propagation Sigma-bar(L, L-bar), Sec. 4.2 chol_blocked_rev, right to
  * left: per block C-bar <- C-bar D^-1 (panel solve), D-bar <- D-bar - tril(C-bar^T C), the
@@ -138,11 +161,14 @@ int chol_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int *inf
 int chol_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream);
 
-/* chol_rev with the diagonal-block variant chosen by the caller (CHOL_DIAG_*; argument 9, any
- * other value returns -9); the remaining arguments as chol_rev's, shifted by one from workspace
- * on.  chol_rev(...) is chol_rev_ex(..., CHOL_DIAG_AUTO, ...). */
+/* chol_rev with the diagonal-block variant (CHOL_DIAG_*, argument 9; any other value returns -9)
+ * and the storage layout of L and A (CHOL_LAYOUT_*, argument 10; any other value returns -10)
+ * chosen by the caller; the remaining arguments as chol_rev's, shifted by two from workspace on
+ * (workspace sized by chol_workspace_bytes_ex).  chol_rev(...) is
+ * chol_rev_ex(..., CHOL_DIAG_AUTO, CHOL_LAYOUT_ROW_MAJOR, ...). */
 int chol_rev_ex(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda,
-                int sbar_form, int nb, int diag, void *workspace, size_t workspace_bytes, void *stream);
+                int sbar_form, int nb, int diag, int layout, void *workspace, size_t workspace_bytes,
+                void *stream);
 
 /*
  * chol_fwd -- forward-mode propagation L-dot(L, Sigma-dot), Sec. 4.2 chol_blocked_fwd, left to
@@ -158,10 +184,11 @@ int chol_rev_ex(int precision, int64_t n, const void *L, int64_t ldl, void *A, i
 int chol_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream);
 
-/* chol_fwd with the diagonal-block variant chosen by the caller (CHOL_DIAG_*; argument 8, any
- * other value returns -8); chol_fwd(...) is chol_fwd_ex(..., CHOL_DIAG_AUTO, ...). */
+/* chol_fwd with the diagonal-block variant (CHOL_DIAG_*, argument 8; else -8) and the storage
+ * layout of L and A (CHOL_LAYOUT_*, argument 9; else -9) chosen by the caller; workspace sized by
+ * chol_workspace_bytes_ex.  chol_fwd(...) is chol_fwd_ex(..., CHOL_DIAG_AUTO, CHOL_LAYOUT_ROW_MAJOR, ...). */
 int chol_fwd_ex(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb,
-                int diag, void *workspace, size_t workspace_bytes, void *stream);
+                int diag, int layout, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * chol_factor_fwd -- chol_factor and chol_fwd in ONE left-to-right sweep (Sec. 4.2: the forward

@@ -5,7 +5,10 @@ Public calls (torch tensors as device memory, work on the current stream):
   chol_rev(L, A)     L-bar -> Sigma-bar       (Sec. 4.2 chol_blocked_rev)
   chol_fwd(L, A)     Sigma-dot -> L-dot       (Sec. 4.2 chol_blocked_fwd)
   chol_factor_fwd(A, D)  both in one sweep (Sigma -> L and Sigma-dot -> L-dot)
-and their batched forms (many matrices, n <= 512, one persistent launch), including a fused
+(single-matrix options: diag='auto' | 'symbolic' | 'level2' for the diagonal-block variant of
+chol_rev / chol_fwd, layout='row' | 'col' for row- or column-major storage, precision for the
+reduced-precision trailing modes) and their batched forms (many matrices, n <= 512, one
+persistent launch), including a fused
 factor + reverse sweep (chol_factor_rev_batched) and a fused Gaussian-process loss
 (chol_gp_nll_batched: Sigma -> L -> f -> Sigma-bar per matrix).  `autograd` wraps them as
 torch.autograd Functions; `serve` runs a continuous-batching request loop on top of them.

@@ -23,6 +23,8 @@ OP_FACTOR, OP_REV, OP_FWD = 0, 1, 2
 _FORMS = {"sym": SBAR_SYM, "tril": SBAR_TRIL}
 DIAG_AUTO, DIAG_SYMBOLIC, DIAG_LEVEL2 = 0, 1, 2
 _DIAGS = {"auto": DIAG_AUTO, "symbolic": DIAG_SYMBOLIC, "level2": DIAG_LEVEL2}
+LAYOUT_ROW_MAJOR, LAYOUT_COL_MAJOR = 0, 1
+_LAYOUTS = {"row": LAYOUT_ROW_MAJOR, "col": LAYOUT_COL_MAJOR}
 _OPS = {"factor": OP_FACTOR, "rev": OP_REV, "fwd": OP_FWD}
 
 _lib = None
@@ -54,13 +56,17 @@ def load_library():
     i64, vp, i32, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     lib.chol_workspace_bytes.argtypes = [i32, i32, i64, i32]
     lib.chol_workspace_bytes.restype = sz
+    lib.chol_workspace_bytes_ex.argtypes = [i32, i32, i64, i32, i32]
+    lib.chol_workspace_bytes_ex.restype = sz
     lib.chol_factor.argtypes = [i32, i64, vp, i64, i32, vp, vp, sz, vp]
     lib.chol_factor.restype = i32
+    lib.chol_factor_ex.argtypes = [i32, i64, vp, i64, i32, i32, vp, vp, sz, vp]
+    lib.chol_factor_ex.restype = i32
     lib.chol_rev.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, vp, sz, vp]
-    lib.chol_rev_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, i32, vp, sz, vp]
+    lib.chol_rev_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, i32, i32, vp, sz, vp]
     lib.chol_rev.restype = i32
     lib.chol_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, sz, vp]
-    lib.chol_fwd_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, vp, sz, vp]
+    lib.chol_fwd_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, i32, vp, sz, vp]
     lib.chol_fwd.restype = i32
     lib.chol_factor_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, vp, sz, vp]
     lib.chol_factor_fwd.restype = i32
@@ -95,7 +101,9 @@ def _check(fn, status):
         raise CholError(fn, status, lib.chol_status_string(status).decode())
 
 
-def _square(name, t, dtypes=(torch.float64,)):
+def _square(name, t, dtypes=(torch.float64,), layout="row"):
+    """n of a square matrix tensor in the given storage: 'row' (unit column stride) or 'col'
+    (column-major, unit row stride, e.g. `x.T.contiguous().T`)."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
     if t.dtype not in dtypes:
@@ -103,23 +111,35 @@ def _square(name, t, dtypes=(torch.float64,)):
     if t.dim() != 2 or t.shape[0] != t.shape[1]:
         raise ValueError(f"{name} must be square 2-D, got {tuple(t.shape)}")
     n = t.shape[0]
-    if n > 0 and (t.stride(1) != 1 or t.stride(0) < n):
+    if layout == "col":
+        if n > 0 and (t.stride(0) != 1 or t.stride(1) < n):
+            raise ValueError(f"{name} must be column-major with unit row stride for layout='col'")
+    elif n > 0 and (t.stride(1) != 1 or t.stride(0) < n):
         raise ValueError(f"{name} must be row-major with unit column stride")
     return n
+
+
+def _ld(t, layout="row"):
+    """Leading dimension of a matrix tensor in its storage layout (1 for an empty matrix)."""
+    if t.shape[0] == 0:
+        return 1
+    return t.stride(1) if layout == "col" else t.stride(0)
 
 
 def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def workspace_bytes(op, n, nb=0, precision="f64"):
-    """Device workspace bytes for op in {'factor', 'rev', 'fwd'} at size n and block size nb."""
+def workspace_bytes(op, n, nb=0, precision="f64", layout="row"):
+    """Device workspace bytes for op in {'factor', 'rev', 'fwd'} at size n and block size nb, for
+    matrices stored in `layout` ('row' or 'col')."""
     op_code, prec = _pick(_OPS, op, "op"), _pick(_PRECS, precision, "precision")
-    return int(load_library().chol_workspace_bytes(op_code, prec, int(n), int(nb)))
+    lay = _pick(_LAYOUTS, layout, "layout")
+    return int(load_library().chol_workspace_bytes_ex(op_code, prec, int(n), int(nb), lay))
 
 
-def _workspace(op, n, nb, device, workspace, precision="f64"):
-    need = workspace_bytes(op, n, nb, precision)
+def _workspace(op, n, nb, device, workspace, precision="f64", layout="row"):
+    need = workspace_bytes(op, n, nb, precision, layout)
     if workspace is None:
         return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
     if workspace.device != device or workspace.numel() * workspace.element_size() < need:
@@ -127,53 +147,56 @@ def _workspace(op, n, nb, device, workspace, precision="f64"):
     return workspace
 
 
-def chol_factor(A, nb=0, workspace=None, info=None, precision="f64"):
+def chol_factor(A, nb=0, workspace=None, info=None, precision="f64", layout="row"):
     """In place: tril(A) = Sigma -> tril(A) = L, strict upper set to 0.  Returns (A, info) where
     info is a device int32 tensor (0, or the 1-based column of the first non-positive pivot).
     precision: 'f64', 'f64_trail_f32' (trailing updates on FP32 MFMA) or 'f64_trail_bf16x3'
-    (trailing updates as split-bfloat16 products)."""
+    (trailing updates as split-bfloat16 products).  layout: 'row', or 'col' for column-major
+    (LAPACK) storage of A."""
     lib = load_library()
-    prec = _pick(_PRECS, precision, "precision")
-    n = _square("A", A)
+    prec, lay = _pick(_PRECS, precision, "precision"), _pick(_LAYOUTS, layout, "layout")
+    n = _square("A", A, layout=layout)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    ws = _workspace("factor", n, nb, A.device, workspace, precision)
+    ws = _workspace("factor", n, nb, A.device, workspace, precision, layout)
     with torch.cuda.device(A.device):
-        _check("chol_factor", lib.chol_factor(prec, n, A.data_ptr(), A.stride(0) if n else 1, nb,
-                                              info.data_ptr(), ws.data_ptr(), ws.numel(),
-                                              _stream(A.device)))
+        _check("chol_factor", lib.chol_factor_ex(prec, n, A.data_ptr(), _ld(A, layout), nb, lay,
+                                                 info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                 _stream(A.device)))
     return A, info
 
 
-def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64", diag="auto"):
+def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64", diag="auto", layout="row"):
     """In place: tril(A) = L-bar -> A = Sigma-bar in the chosen form ('sym' or 'tril').
-    diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*)."""
+    diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*); layout: 'row', or
+    'col' for column-major (LAPACK) storage of L and A."""
     lib = load_library()
     prec, fm, dv = _pick(_PRECS, precision, "precision"), _pick(_FORMS, form, "form"), _pick(_DIAGS, diag, "diag")
-    n = _square("L", L)
-    if _square("A", A) != n or A.device != L.device:
+    lay = _pick(_LAYOUTS, layout, "layout")
+    n = _square("L", L, layout=layout)
+    if _square("A", A, layout=layout) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
-    ws = _workspace("rev", n, nb, A.device, workspace, precision)
+    ws = _workspace("rev", n, nb, A.device, workspace, precision, layout)
     with torch.cuda.device(A.device):
-        _check("chol_rev", lib.chol_rev_ex(prec, n, L.data_ptr(), L.stride(0) if n else 1,
-                                           A.data_ptr(), A.stride(0) if n else 1, fm, nb, dv,
-                                           ws.data_ptr(), ws.numel(), _stream(A.device)))
+        _check("chol_rev", lib.chol_rev_ex(prec, n, L.data_ptr(), _ld(L, layout), A.data_ptr(), _ld(A, layout),
+                                           fm, nb, dv, lay, ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
 
-def chol_fwd(L, A, nb=0, workspace=None, precision="f64", diag="auto"):
+def chol_fwd(L, A, nb=0, workspace=None, precision="f64", diag="auto", layout="row"):
     """In place: tril(A) = tril(Sigma-dot) -> tril(A) = L-dot, strict upper set to 0.
-    diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*)."""
+    diag: diagonal-block variant, 'auto', 'symbolic' or 'level2' (CHOL_DIAG_*); layout: 'row', or
+    'col' for column-major (LAPACK) storage of L and A."""
     lib = load_library()
     prec, dv = _pick(_PRECS, precision, "precision"), _pick(_DIAGS, diag, "diag")
-    n = _square("L", L)
-    if _square("A", A) != n or A.device != L.device:
+    lay = _pick(_LAYOUTS, layout, "layout")
+    n = _square("L", L, layout=layout)
+    if _square("A", A, layout=layout) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
-    ws = _workspace("fwd", n, nb, A.device, workspace, precision)
+    ws = _workspace("fwd", n, nb, A.device, workspace, precision, layout)
     with torch.cuda.device(A.device):
-        _check("chol_fwd", lib.chol_fwd_ex(prec, n, L.data_ptr(), L.stride(0) if n else 1,
-                                           A.data_ptr(), A.stride(0) if n else 1, nb, dv,
-                                           ws.data_ptr(), ws.numel(), _stream(A.device)))
+        _check("chol_fwd", lib.chol_fwd_ex(prec, n, L.data_ptr(), _ld(L, layout), A.data_ptr(), _ld(A, layout),
+                                           nb, dv, lay, ws.data_ptr(), ws.numel(), _stream(A.device)))
     return A
 
 

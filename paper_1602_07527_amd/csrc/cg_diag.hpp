@@ -1034,6 +1034,34 @@ __global__ __launch_bounds__(256) void fwd_panel_solve_kernel(int M, int w, cons
   }
 }
 
+// Column-major (LAPACK) storage of an n x n matrix is the row-major storage of its transpose, so
+// the column-major entry points convert with these two element-wise kernels.  Each element pair
+// (r, c), (c, r) is read and written by one thread only, so both may work in place.
+// dst[r][c] = src[c][r] for r >= c: the lower triangle of dst from the upper triangle of src.
+__global__ __launch_bounds__(256) void lower_from_upper_kernel(int64_t n, const double *src, int64_t lds,
+                                                               double *dst, int64_t ldd) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n, c = e - r * n;
+    if (c <= r) dst[r * ldd + c] = src[c * lds + r];
+  }
+}
+
+// A[c][r] = A[r][c] for r > c, then A[r][c] = 0: the strict lower triangle moved to the strict
+// upper triangle (the diagonal stays).
+__global__ __launch_bounds__(256) void lower_to_upper_kernel(int64_t n, double *A, int64_t lda) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n, c = e - r * n;
+    if (c < r) {
+      A[c * lda + r] = A[r * lda + c];
+      A[r * lda + c] = 0.0;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void sym_to_tril_kernel(int64_t n, double *A, int64_t lda) {
   const int64_t total = n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;

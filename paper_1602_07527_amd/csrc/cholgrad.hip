@@ -448,8 +448,8 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
 bool diag_ok(int diag) { return diag == CHOL_DIAG_AUTO || diag == CHOL_DIAG_SYMBOLIC || diag == CHOL_DIAG_LEVEL2; }
 bool diag_symbolic(int diag) { return diag != CHOL_DIAG_LEVEL2; }
 
-int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
-                int sbar_form, int nb, int diag, void *workspace, size_t workspace_bytes, void *stream) {
+static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
+                    int sbar_form, int nb, int diag, void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   int cp = cg::CP_F64;
   if (!single_prec(precision, &cp)) return -1;
@@ -582,8 +582,8 @@ int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
 
 int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
-  return chol_rev_ex(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_AUTO, workspace,
-                     workspace_bytes, stream);
+  return rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_AUTO, workspace, workspace_bytes,
+                  stream);
 }
 
 int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *info,
@@ -670,8 +670,8 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   return CHOL_SUCCESS;
 }
 
-int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
-                int diag, void *workspace, size_t workspace_bytes, void *stream) {
+static int fwd_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
+                    int diag, void *workspace, size_t workspace_bytes, void *stream) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   int cp = cg::CP_F64;
   if (!single_prec(precision, &cp)) return -1;
@@ -987,7 +987,101 @@ int chol_rev_batched(int precision, int batch, const int64_t *n, const void *con
 
 int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream) {
-  return chol_fwd_ex(precision, n, Lv, ldl, Av, lda, nb, CHOL_DIAG_AUTO, workspace, workspace_bytes, stream);
+  return fwd_impl(precision, n, Lv, ldl, Av, lda, nb, CHOL_DIAG_AUTO, workspace, workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Entry points with a caller-chosen diagonal-block variant and storage layout.  Column-major
+// storage of a matrix is row-major storage of its transpose: the input lower triangles are
+// mirrored in place into the row-major lower triangle (and L, which the call may not modify, is
+// copied that way into the workspace), the row-major sweep runs, and each lower-triangular output
+// is moved back to the column-major lower triangle.
+
+static size_t transposed_l_bytes(int64_t n) { return align_up((size_t)n * n * sizeof(double)); }
+
+static hipError_t launch_lower_from_upper(int64_t n, const double *src, int64_t lds, double *dst, int64_t ldd,
+                                          hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
+  hipLaunchKernelGGL(cg::lower_from_upper_kernel, dim3(blocks), dim3(256), 0, s, n, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+static hipError_t launch_lower_to_upper(int64_t n, double *A, int64_t lda, hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
+  hipLaunchKernelGGL(cg::lower_to_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
+  return hipGetLastError();
+}
+
+size_t chol_workspace_bytes_ex(int op, int precision, int64_t n, int nb, int layout) {
+  if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return 0;
+  const size_t base = chol_workspace_bytes(op, precision, n, nb);
+  if (base == 0 || layout == CHOL_LAYOUT_ROW_MAJOR || op == CHOL_OP_FACTOR) return base;
+  return transposed_l_bytes(n) + base;
+}
+
+int chol_factor_ex(int precision, int64_t n, void *Av, int64_t lda, int nb, int layout, int *info,
+                   void *workspace, size_t workspace_bytes, void *stream) {
+  if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return -6;
+  if (n > 0 && !info) return -7;
+  if (layout == CHOL_LAYOUT_ROW_MAJOR || n <= 0)
+    return chol_factor(precision, n, Av, lda, nb, info, workspace, workspace_bytes, stream);
+  // A dry call (no workspace) validates every argument before anything is enqueued.
+  const int chk = chol_factor(precision, n, Av, lda, nb, info, nullptr, 0, stream);
+  if (chk != CHOL_ERR_WORKSPACE) return chk;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 ||
+      workspace_bytes < chol_workspace_bytes_ex(CHOL_OP_FACTOR, precision, n, nb, layout))
+    return CHOL_ERR_WORKSPACE;  // before anything is enqueued
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *A = static_cast<double *>(Av);
+  CG_TRY(launch_lower_from_upper(n, A, lda, A, lda, s));
+  const int rc = chol_factor(precision, n, Av, lda, nb, info, workspace, workspace_bytes, stream);
+  if (rc != CHOL_SUCCESS) return rc;
+  CG_TRY(launch_lower_to_upper(n, A, lda, s));
+  return CHOL_SUCCESS;
+}
+
+int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int sbar_form,
+                int nb, int diag, int layout, void *workspace, size_t workspace_bytes, void *stream) {
+  if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return -10;
+  if (layout == CHOL_LAYOUT_ROW_MAJOR || n <= 0)
+    return rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, diag, workspace, workspace_bytes, stream);
+  const int chk = rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, diag, nullptr, 0, stream);
+  if (chk != CHOL_ERR_WORKSPACE) return chk;
+  const size_t lt = transposed_l_bytes(n);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 ||
+      workspace_bytes < chol_workspace_bytes_ex(CHOL_OP_REV, precision, n, nb, layout))
+    return CHOL_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *Lt = static_cast<double *>(workspace), *A = static_cast<double *>(Av);
+  CG_TRY(launch_lower_from_upper(n, static_cast<const double *>(Lv), ldl, Lt, n, s));
+  CG_TRY(launch_lower_from_upper(n, A, lda, A, lda, s));
+  const int rc = rev_impl(precision, n, Lt, n, Av, lda, sbar_form, nb, diag, static_cast<char *>(workspace) + lt,
+                          workspace_bytes - lt, stream);
+  if (rc != CHOL_SUCCESS) return rc;
+  if (sbar_form == CHOL_SBAR_TRIL) CG_TRY(launch_lower_to_upper(n, A, lda, s));  // the sym form is symmetric
+  return CHOL_SUCCESS;
+}
+
+int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb, int diag,
+                int layout, void *workspace, size_t workspace_bytes, void *stream) {
+  if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return -9;
+  if (layout == CHOL_LAYOUT_ROW_MAJOR || n <= 0)
+    return fwd_impl(precision, n, Lv, ldl, Av, lda, nb, diag, workspace, workspace_bytes, stream);
+  const int chk = fwd_impl(precision, n, Lv, ldl, Av, lda, nb, diag, nullptr, 0, stream);
+  if (chk != CHOL_ERR_WORKSPACE) return chk;
+  const size_t lt = transposed_l_bytes(n);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 ||
+      workspace_bytes < chol_workspace_bytes_ex(CHOL_OP_FWD, precision, n, nb, layout))
+    return CHOL_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *Lt = static_cast<double *>(workspace), *A = static_cast<double *>(Av);
+  CG_TRY(launch_lower_from_upper(n, static_cast<const double *>(Lv), ldl, Lt, n, s));
+  CG_TRY(launch_lower_from_upper(n, A, lda, A, lda, s));
+  const int rc = fwd_impl(precision, n, Lt, n, Av, lda, nb, diag, static_cast<char *>(workspace) + lt,
+                          workspace_bytes - lt, stream);
+  if (rc != CHOL_SUCCESS) return rc;
+  CG_TRY(launch_lower_to_upper(n, A, lda, s));
+  return CHOL_SUCCESS;
 }
 
 int chol_fwd_batched(int precision, int batch, const int64_t *n, const void *const *L, const int64_t *ldl,

@@ -23,7 +23,8 @@ def declared_functions():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for want in ("chol_factor", "chol_rev", "chol_fwd", "chol_rev_ex", "chol_fwd_ex", "chol_workspace_bytes",
+    for want in ("chol_factor", "chol_rev", "chol_fwd", "chol_factor_ex", "chol_rev_ex", "chol_fwd_ex",
+                 "chol_workspace_bytes", "chol_workspace_bytes_ex",
                  "chol_status_string", "chol_version"):
         assert want in names
 
@@ -67,11 +68,28 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.chol_rev(0, 0, None, 0, None, 0, 0, 0, None, 0, None) == 0   # n == 0 is a no-op
     assert lib.chol_fwd(0, 10, fake, 10, fake, 10, 33, ws, big, None) == -7
     assert lib.chol_fwd(0, 10, fake, 10, fake, 10, 0, None, big, None) == -102
-    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 3, ws, big, None) == -9      # diag variant
-    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, -1, ws, big, None) == -9
-    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 2, ws, 16, None) == -102
-    assert lib.chol_fwd_ex(0, 10, fake, 10, fake, 10, 0, 3, ws, big, None) == -8
-    assert lib.chol_fwd_ex(0, 10, fake, 10, fake, 10, 0, 1, None, big, None) == -102
+    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 3, 0, ws, big, None) == -9      # diag variant
+    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, -1, 0, ws, big, None) == -9
+    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 2, 0, ws, 16, None) == -102
+    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 0, 2, ws, big, None) == -10     # layout
+    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 0, 1, ws, 16, None) == -102
+    assert lib.chol_rev_ex(0, 10, fake, 9, fake, 10, 0, 0, 0, 1, ws, big, None) == -4
+    assert lib.chol_fwd_ex(0, 10, fake, 10, fake, 10, 0, 3, 0, ws, big, None) == -8
+    assert lib.chol_fwd_ex(0, 10, fake, 10, fake, 10, 0, 1, 0, None, big, None) == -102
+    assert lib.chol_fwd_ex(0, 10, fake, 10, fake, 10, 0, 0, 7, ws, big, None) == -9
+    assert lib.chol_fwd_ex(0, 10, fake, 10, fake, 10, 33, 0, 1, ws, big, None) == -7
+    assert lib.chol_factor_ex(0, 10, fake, 10, 0, 2, fake, ws, big, None) == -6               # layout
+    assert lib.chol_factor_ex(0, 10, fake, 10, 0, 1, None, ws, big, None) == -7
+    assert lib.chol_factor_ex(0, 10, fake, 5, 0, 1, fake, ws, big, None) == -4
+    assert lib.chol_factor_ex(0, 10, fake, 10, 0, 1, fake, ws, 16, None) == -102
+    assert lib.chol_factor_ex(0, 0, None, 0, 0, 1, None, None, 0, None) == 0
+    # column-major rev / fwd need n*n more doubles for the transposed copy of L
+    ext = lib.chol_workspace_bytes_ex
+    assert ext(1, 0, 1000, 0, 0) == lib.chol_workspace_bytes(1, 0, 1000, 0)
+    assert ext(1, 0, 1000, 0, 1) == lib.chol_workspace_bytes(1, 0, 1000, 0) + 8 * 1000 * 1000
+    assert ext(2, 0, 1000, 0, 1) == lib.chol_workspace_bytes(2, 0, 1000, 0) + 8 * 1000 * 1000
+    assert ext(0, 0, 1000, 0, 1) == lib.chol_workspace_bytes(0, 0, 1000, 0)
+    assert ext(1, 0, 1000, 0, 5) == 0 and ext(1, 0, 0, 0, 1) == 0
     assert lib.chol_factor(0, 10, fake, 10, 0, None, ws, big, None) == -6
     assert lib.chol_factor(0, 10, fake, 5, 0, fake, ws, big, None) == -4
     assert lib.chol_factor(0, 0, None, 0, 0, None, None, 0, None) == 0

@@ -268,3 +268,39 @@ def test_repeatable_bitwise(cg, dev):
     a = cg.chol_rev(Lt, to_dev(Lb, dev)).cpu().numpy()
     b = cg.chol_rev(Lt, to_dev(Lb, dev)).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("N,nb", [(1, 32), (65, 32), (257, 64), (300, 128), (513, 128)])
+def test_col_major_layout(cg, dev, N, nb):
+    """layout='col': the same sweeps on column-major (LAPACK) storage.  The logical lower triangle
+    of each input is read (junk in the logical strict upper triangles, L's included, is ignored),
+    L is not modified, and the logical results match the oracle: L and L-dot lower triangular with
+    a zero strict upper triangle, Sigma-bar in both forms."""
+    S, L, Lb, Sd, junk = spd_case(N, 7000 + N)
+
+    def col(x):  # column-major tensor holding the logical matrix x
+        return to_dev(x, dev).T.contiguous().T
+
+    A = col(S + junk)
+    cg.chol_factor(A, nb=nb, layout="col")
+    Lg = A.cpu().numpy()
+    assert rel(Lg, O.chol(S)[0]) <= TOL
+    assert np.all(np.triu(Lg, 1) == 0)
+    Lc = col(L + junk)
+    L_before = Lc.cpu().numpy()
+    for form in ("sym", "tril"):
+        X = col(Lb + junk)
+        cg.chol_rev(Lc, X, form=form, nb=nb, layout="col")
+        assert rel(X.cpu().numpy(), O.chol_rev(L, Lb, form)) <= TOL, form
+    X = col(np.tril(Sd) + junk)
+    cg.chol_fwd(Lc, X, nb=nb, layout="col")
+    Xg = X.cpu().numpy()
+    assert rel(Xg, O.chol_fwd(L, Sd)) <= TOL
+    assert np.all(np.triu(Xg, 1) == 0)
+    assert np.array_equal(Lc.cpu().numpy(), L_before)
+
+
+def test_col_major_rejects_row_major_tensors(cg, dev):
+    A = to_dev(np.eye(8), dev)
+    with pytest.raises(ValueError, match="column-major"):
+        cg.chol_factor(A, layout="col")
