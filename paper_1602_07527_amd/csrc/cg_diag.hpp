@@ -773,15 +773,35 @@ constexpr int SYM_TILE = 16;
 // Sum over k in [k0, k1) of A(i, k) B(k, j) for the workgroup's 16 x 16 tile; the result is
 // valid in wave 0 only (tile_mma's layout).  `red` is 3 * 256 doubles of LDS.  Every thread of
 // the workgroup must call it.
+// tile_mma for K <= 32 with every operand load of the wave issued before the first MFMA (one
+// memory latency instead of two).
+template <class FA, class FB>
+__device__ __forceinline__ dbl4 tile_mma_k32(dbl4 acc, FA A, FB B, int K) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  double a[8], b[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = 4 * u + kq;
+    a[u] = (k < K) ? A(i, k) : 0.0;
+    b[u] = (k < K) ? B(k, i) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (4 * u < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  return acc;
+}
+
 template <class FA, class FB>
 __device__ __forceinline__ dbl4 wg_tile16(FA A, FB B, int k0, int k1, double *red) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int span = (((k1 - k0) + 15) / 16) * 4;  // per wave, a multiple of 4
   const int ka = k0 + wave * span, kb = min(k1, ka + span);
   dbl4 acc{0, 0, 0, 0};
-  if (kb > ka)
-    acc = tile_mma(acc, [&](int i, int k) { return A(i, ka + k); }, [&](int k, int j) { return B(ka + k, j); },
-                   kb - ka);
+  auto As = [&](int i, int k) { return A(i, ka + k); };
+  auto Bs = [&](int k, int j) { return B(ka + k, j); };
+  if (kb - ka > 32) acc = tile_mma(acc, As, Bs, kb - ka);  // only the forward panel's two-term range
+  else if (kb > ka) acc = tile_mma_k32(acc, As, Bs, kb - ka);
   double *r = as_lds(red);
   if (wave > 0) {
 #pragma unroll
