@@ -4,6 +4,10 @@ matrices chosen by hand; the expected values follow from the mathematics (no lib
   rev_closed.txt   Sec. 2/3: for f = Tr(C Sigma) = Tr(C L L^T), dF/dL = 2 C L, so the reverse-mode
                    input L-bar = tril(2 C L) must give the symmetric gradient Sigma-bar = C.
   fwd_closed.txt   Sec. 3, eqn (symfwd): Sigma-dot = M L^T + L M^T with M lower gives L-dot = M.
+  gp_int.txt       Sec. 2's x -> Sigma -> L -> f chain with the Gaussian-process loss
+                   f = sum_i log L_ii + |L^-1 y|^2 / 2: y = L L^T w0 with w0 integer makes
+                   z = L^-1 y = L^T w0 and w = L^-T z = w0 integers, so f = log(prod_i L_ii) + z.z / 2
+                   and L-bar = diag(1 / L_ii) - tril(w z^T) follow by hand.
 Run:  python tests/golden/make_golden.py
 """
 import os
@@ -14,6 +18,7 @@ L = np.array([[2, 0, 0, 0, 0], [1, 3, 0, 0, 0], [-1, 2, 1, 0, 0], [3, 0, -2, 4, 
               [0, 1, 1, -1, 2]], dtype=np.int64)
 C = np.array([[1, 2, 0, -1, 3], [2, -3, 1, 0, 0], [0, 1, 2, 1, -2], [-1, 0, 1, 0, 1],
               [3, 0, -2, 1, 4]], dtype=np.int64)
+W0 = np.array([1, -2, 0, 3, -1], dtype=np.int64)
 M = np.array([[1, 0, 0, 0, 0], [-2, 3, 0, 0, 0], [0, 1, -1, 0, 0], [2, 2, 0, 1, 0],
               [1, -1, 3, 0, -2]], dtype=np.int64)
 assert (C == C.T).all() and (np.triu(L, 1) == 0).all() and (np.triu(M, 1) == 0).all()
@@ -40,3 +45,8 @@ dump("rev_closed.txt",
 dump("fwd_closed.txt",
      ["Sec. 3 eqn (symfwd): Sigma-dot = M L^T + L M^T with M lower-triangular gives L-dot = M."],
      [("L", L), ("Sdot", M @ L.T + L @ M.T), ("Ldot", M)])
+dump("gp_int.txt",
+     ["Sec. 2 chain with f = sum log L_ii + |L^-1 y|^2 / 2; y = L L^T w0 (w0 integer), so",
+      "z = L^-1 y = L^T w0 and w = L^-T z = w0 exactly: f = log(prod L_ii) + z.z / 2,",
+      "L-bar = diag(1 / L_ii) - tril(w z^T)."],
+     [("L", L), ("y", (L @ L.T @ W0)[:, None]), ("z", (L.T @ W0)[:, None]), ("w", W0[:, None])])

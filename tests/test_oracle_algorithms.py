@@ -157,3 +157,41 @@ def test_planted_transpose_in_symbolic_rev_is_caught(monkeypatch):
         return sla.solve_triangular(L, X.T, lower=True, trans=1).T
     monkeypatch.setattr(OC, "chol_rev_S", bad_S)
     assert not _pins_pass()
+
+
+def _gp_pins_pass(fn):
+    """The two pins of the GP loss value (the integer golden and the log-det route) applied to fn."""
+    from _golden import load
+    g = load("gp_int.txt")
+    L, y, z, w = g["L"], g["y"][:, 0], g["z"][:, 0], g["w"][:, 0]
+    f, Lbar = fn(L, y)
+    ok = [abs(f - (np.log(np.prod(np.diag(L))) + 0.5 * float(z @ z))) <= 1e-12 * abs(f),
+          np.abs(Lbar - (np.diag(1.0 / np.diag(L)) - np.tril(np.outer(w, z)))).max() <= 1e-12]
+    S, L2, _, _ = case(7, 91)
+    y2 = np.random.default_rng(91).standard_normal(7)
+    f2, _ = fn(L2, y2)
+    ok.append(abs(f2 - 0.5 * (np.linalg.slogdet(S)[1] + y2 @ np.linalg.solve(S, y2))) <= 1e-12 * abs(f2))
+    return all(ok)
+
+
+def test_gp_pins_catch_planted_mistakes():
+    assert _gp_pins_pass(OC.gp_loss_and_lbar)
+
+    def no_half(L, y):               # the 1/2 on |L^-1 y|^2 dropped
+        z = sla.solve_triangular(L, y, lower=True)
+        f, Lbar = OC.gp_loss_and_lbar(L, y)
+        return f + 0.5 * float(z @ z), Lbar
+
+    def transposed_w(L, y):          # w = L^-1 z instead of L^-T z
+        z = sla.solve_triangular(L, y, lower=True)
+        w = sla.solve_triangular(L, z, lower=True)
+        f, _ = OC.gp_loss_and_lbar(L, y)
+        return f, np.diag(1.0 / np.diag(L)) - np.tril(np.outer(w, z))
+
+    def log_of_sum(L, y):            # log of the summed diagonal instead of the summed logs
+        z = sla.solve_triangular(L, y, lower=True)
+        _, Lbar = OC.gp_loss_and_lbar(L, y)
+        return float(np.log(np.sum(np.diag(L))) + 0.5 * z @ z), Lbar
+
+    for bad in (no_half, transposed_w, log_of_sum):
+        assert not _gp_pins_pass(bad), bad.__name__

@@ -177,3 +177,30 @@ def test_derivative_inputs_read_lower_only():
     junk = np.triu(rng.standard_normal((N, N)), 1)
     assert np.array_equal(O.chol_rev(L, Lb), O.chol_rev(L, Lb + junk))
     assert np.array_equal(O.chol_fwd(L, np.tril(Sd)), O.chol_fwd(L, np.tril(Sd) + junk))
+
+
+# ----------------------------------------------------------------------------- GP loss value
+
+def test_gp_loss_golden_integer():
+    # Sec. 2's chain closed by f = sum log L_ii + |L^-1 y|^2 / 2 on a hand-built case in which
+    # z = L^-1 y and w = L^-T z are integers (tests/golden/gp_int.txt): f and L-bar follow by hand.
+    g = load("gp_int.txt")
+    L, y, z, w = g["L"], g["y"][:, 0], g["z"][:, 0], g["w"][:, 0]
+    f, Lbar = O.gp_loss_and_lbar(L, y)
+    want_f = np.log(np.prod(np.diag(L))) + 0.5 * float(z @ z)
+    assert f == pytest.approx(want_f, rel=4 * U)
+    want_Lbar = np.diag(1.0 / np.diag(L)) - np.tril(np.outer(w, z))
+    assert np.abs(Lbar - want_Lbar).max() <= 8 * U * np.abs(want_Lbar).max()
+
+
+@pytest.mark.parametrize("N", [1, 5, 40])
+def test_gp_loss_value_is_half_logdet_plus_quadratic(N):
+    # f = log det L + |L^-1 y|^2 / 2 = (1/2) log det Sigma + (1/2) y^T Sigma^-1 y, with the right
+    # side from host LAPACK routes that share nothing with the oracle's triangular solves.
+    S, rng = spd(N, 900 + N)
+    y = rng.standard_normal(N)
+    f, _ = O.gp_loss_and_lbar(sla.cholesky(S, lower=True), y)
+    sign, logdet = np.linalg.slogdet(S)
+    assert sign > 0
+    want = 0.5 * logdet + 0.5 * float(y @ np.linalg.solve(S, y))
+    assert f == pytest.approx(want, rel=1e-13, abs=1e-13)
