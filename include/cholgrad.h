@@ -67,12 +67,18 @@ extern "C" {
  *                   panel solves, split-K sums and every stored value stay FP64.  An
  *                   approximation of the FP64 result: on the N = 16384 squared-exponential
  *                   workload (condition number ~1e5) the stated relative Frobenius errors are
- *                   <= 3e-4 for L and <= 3e-3 for Sigma-bar and L-dot.
+ *                   <= 3e-4 for L, <= 1e-4 for Sigma-bar and <= 3e-5 for L-dot (chol_rev and
+ *                   chol_fwd given the exact L; measured on MI355X 7.6e-5, 7.1e-6, 2.6e-6).
+ *                   Factor and chol_rev both in this mode, each on its own L, on squared-
+ *                   exponential kernels in 2-D with n <= 4096 and condition numbers up to ~2e6:
+ *                   <= 6e-4 for L and <= 2e-2 for Sigma-bar per problem (measured max 2.7e-4
+ *                   and 9.2e-3; the error grows with the condition number).
  *   CHOL_PREC_F64_TRAIL_BF16X3 : as CHOL_PREC_F64_TRAIL_F32, but the trailing contractions split
  *                   each operand into bfloat16 hi + lo parts (hi = bf16(fp32(x)),
  *                   lo = bf16(fp32(x) - hi)) and take hi*hi + hi*lo + lo*hi on bfloat16 MFMA
  *                   with FP32 accumulation (~16 significant bits per operand).  Stated relative
- *                   errors on the same workload: <= 1e-3 for L, <= 1e-2 for Sigma-bar and L-dot. */
+ *                   errors on the same N = 16384 workload: <= 1e-3 for L, <= 3e-4 for Sigma-bar
+ *                   and L-dot (measured 3.0e-4, 2.3e-5, 2.1e-5). */
 #define CHOL_PREC_F64 0
 #define CHOL_PREC_F32 1
 #define CHOL_PREC_F64_TRAIL_F32 2
@@ -215,8 +221,9 @@ int chol_factor_fwd(int precision, int64_t n, void *A, int64_t lda, void *D, int
  * dimension is smaller than its size is skipped (its info entry, where there is one, becomes -1).
  * Problems are processed largest first; each problem's result does not depend on the batch it is
  * in.  Workspace: chol_batched_workspace_bytes(precision, batch, n_max) bytes, 256-byte aligned
- * (about 300 MB; CHOL_PREC_F32 adds 16 * n_max^2 bytes of FP64 staging per workgroup, for at
- * most 256 workgroups: 1.07 GB at n_max = 512).
+ * (about 1.2 MB of scratch per workgroup, one workgroup per problem up to 256: about 300 MB for
+ * 256 or more problems; CHOL_PREC_F32 adds 16 * n_max^2 bytes of FP64 staging per workgroup,
+ * 1.07 GB for 256 workgroups at n_max = 512).
  * Semantics per problem are those of the single-matrix calls above.
  */
 size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max);

@@ -339,7 +339,7 @@ size_t carve_batch(int batch, int64_t n_max, bool f32, void *base, BatchWs *w) {
   Carver c(base);
   w->order = reinterpret_cast<int *>(c.take((size_t)cdiv(batch, 2)));
   w->counter = reinterpret_cast<int *>(c.take(1));
-  w->slots = c.take((size_t)BATCH_WGS * cg::SLOT_DOUBLES);
+  w->slots = c.take((size_t)std::min(batch, BATCH_WGS) * cg::SLOT_DOUBLES);  // one per workgroup
   w->stage = f32 ? c.take((size_t)std::min(batch, BATCH_WGS) * cg::stage_doubles(n_max)) : nullptr;
   return c.off;
 }

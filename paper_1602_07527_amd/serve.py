@@ -10,7 +10,8 @@ Scheduling, one `step()` at a time on the host:
     complete (latency = completion seen - arrival);
   * admit: pending requests are admitted strictly in arrival order while the HBM footprint of
     everything admitted and not yet completed stays within `hbm_budget` bytes (a request's
-    footprint: its two n x n FP64 buffers plus its share of workspace);
+    footprint: its two n x n FP64 buffers plus its workspace; a group of small requests is
+    charged the workspace of its one batched launch);
   * launch: the admitted requests with n <= small_max (512) form ONE batched launch per step
     (chol_factor_rev_batched: one persistent kernel for the whole group) on the small-request
     stream; larger ones are launched one by one (chol_factor + chol_rev), each on whichever of
@@ -26,7 +27,10 @@ written (a request may carry an event that the launch waits for).  Each library 
 whole sequence under the library's lock and waits only on events it recorded itself, so streams
 that share a hardware queue cannot deadlock each other; sharing only costs overlap.  Precision
 'f64' runs everything in FP64; 'f64_trail_f32' runs the large requests with FP32-MFMA trailing
-contractions (the batched small requests stay FP64).
+contractions (the batched small requests stay FP64).  Stated per-request accuracy of the mixed
+mode on the serving workload (2-D squared-exponential kernels, n <= 4096, condition numbers up to
+~2e6; each request on its own L): relative Frobenius error <= 2e-2 in Sigma-bar and <= 6e-4 in L
+against the FP64 result (measured on MI355X: Sigma-bar p95 8.9e-3, max 9.2e-3).
 """
 import time
 from collections import deque
@@ -76,22 +80,32 @@ class Request:
         return None if self.t_done is None else self.t_done - self.t_arrive
 
 
-def admit(pending, in_use, budget, small_max, max_group):
+def admit(pending, in_use, budget, small_max, max_group, group_ws=None):
     """The admission policy, without side effects: walk the pending requests in arrival order and
-    take each while the footprint fits (in_use + footprint <= budget) and the small group has room
+    take each while the footprint fits (in_use + cost <= budget) and the small group has room
     (at most max_group requests with n <= small_max); stop at the first that does not fit, so no
-    request is overtaken.  Returns (small, large, new_in_use)."""
+    request is overtaken.  A large request costs its footprint.  A small request costs its own
+    footprint plus what it adds to the workspace of the one batched launch the small group makes:
+    group_ws(count, n_max) is that launch's workspace in bytes (None: no workspace), so the group
+    is charged exactly group_ws(len(small), max n).  Returns (small, large, new_in_use)."""
     small, large = [], []
+    ws_now, n_max = 0, 0
     for r in pending:
-        if in_use + r.footprint > budget:
-            break
+        cost = r.footprint
         if r.n <= small_max:
             if len(small) >= max_group:
                 break
+            nm = max(n_max, r.n)
+            ws_next = group_ws(len(small) + 1, nm) if group_ws is not None else 0
+            cost += ws_next - ws_now
+        if in_use + cost > budget:
+            break
+        if r.n <= small_max:
             small.append(r)
+            ws_now, n_max = ws_next, nm
         else:
             large.append(r)
-        in_use += r.footprint
+        in_use += cost
     return small, large, in_use
 
 
@@ -132,16 +146,20 @@ class Server:
         self.peak_in_use = 0
         self.completed = 0
         self.launches = {"small": 0, "large": 0}
-        self._slot_share = B.batched_workspace_bytes(256, small_max) // 256
+
+    @staticmethod
+    def group_workspace(count, n_max):
+        """Workspace bytes of one batched launch of `count` small requests of size <= n_max."""
+        return B.batched_workspace_bytes(count, n_max)
 
     def footprint(self, n):
-        """Device bytes a request of size n holds while admitted: its two FP64 buffers plus its
-        workspace (a whole single-matrix workspace for a large request; for a small one, one
-        workgroup slot's share of a batched workspace)."""
+        """Device bytes a request of size n holds by itself while admitted: its two FP64 buffers,
+        plus, for a large request, its single-matrix workspace.  A small request's share of its
+        group's batched workspace is charged at admission (see admit)."""
         own = 2 * 8 * n * n
         if n > self.small_max:
             return own + max(B.workspace_bytes(op, n, self.nb, self.precision) for op in ("factor", "rev"))
-        return own + self._slot_share
+        return own
 
     def submit(self, req):
         if req.n == 0:
@@ -150,8 +168,9 @@ class Server:
             raise ValueError("request on another device")
         req.route = "small" if req.n <= self.small_max else "large"
         req.footprint = self.footprint(req.n)
-        if req.footprint > self.hbm_budget:
-            raise ValueError(f"request {req.rid} needs {req.footprint} bytes, above the budget")
+        alone = req.footprint + (self.group_workspace(1, req.n) if req.route == "small" else 0)
+        if alone > self.hbm_budget:
+            raise ValueError(f"request {req.rid} needs {alone} bytes, above the budget")
         self.pending.append(req)
         return req
 
@@ -163,7 +182,7 @@ class Server:
         completed in this step."""
         done = self._retire()
         small, large, in_use = admit(self.pending, self.in_use, self.hbm_budget, self.small_max,
-                                     self.max_group)
+                                     self.max_group, self.group_workspace)
         taken = len(small) + len(large)
         if taken:
             now = time.perf_counter()
@@ -233,7 +252,7 @@ class Server:
             r.Sigma.record_stream(s)
             r.Lbar.record_stream(s)
         ln.requests = reqs
-        ln.footprint = sum(r.footprint for r in reqs)
+        ln.footprint = sum(r.footprint for r in reqs) + ln.workspace.numel()   # as admit charged it
         self.launches["small"] += 1
         self.running.append(ln)
 

@@ -7,13 +7,15 @@ result against the FP64 oracle (rev and fwd on the oracle's own L, so only the m
 measured), on the squared-exponential workloads (N = 4096 and the full N = 16384, condition
 numbers ~3e4 and ~1e5):
 
-    f64_trail_f32     relL <= 3e-4, rel Sigma-bar <= 3e-3, rel L-dot <= 3e-3
-    f64_trail_bf16x3  relL <= 1e-3, rel Sigma-bar <= 1e-2, rel L-dot <= 1e-2
+    f64_trail_f32     relL <= 3e-4, rel Sigma-bar <= 1e-4, rel L-dot <= 3e-5
+    f64_trail_bf16x3  relL <= 1e-3, rel Sigma-bar <= 3e-4, rel L-dot <= 3e-4
 
-(a CPU emulation of the same roundings measured relL / rel Sigma-bar 3.5e-5 / 3.4e-4 (FP32) at
-N = 4096 and 7.6e-5 / 8.2e-4 at N = 16384; for the factor in split-bf16, relL 1.6e-4 at N = 4096).  Every result must also differ from
-the oracle by more than 1e-9 (the FP64 path is ~1e-13 away), which shows the reduced-precision
-kernels really ran.
+The Sigma-bar and L-dot bounds are about 10x the largest error measured on MI355X (N = 16384:
+FP32 trailing relL 7.6e-5, rel Sigma-bar 7.1e-6, rel L-dot 2.6e-6; split-bf16 relL 3.0e-4,
+rel Sigma-bar 2.3e-5, rel L-dot 2.1e-5), so a 10x loss of accuracy fails them; the relL bounds
+keep a 3-4x margin over the factor's measured error, which grows with N.  Every result must also
+differ from the oracle by more than 1e-9 (the FP64 path is ~1e-13 away), which shows the
+reduced-precision kernels really ran.
 """
 import numpy as np
 import pytest
@@ -22,7 +24,7 @@ import oracle as O
 import workloads as W
 
 pytestmark = pytest.mark.gpu
-TOLS = {"f64_trail_f32": (3e-4, 3e-3, 3e-3), "f64_trail_bf16x3": (1e-3, 1e-2, 1e-2)}
+TOLS = {"f64_trail_f32": (3e-4, 1e-4, 3e-5), "f64_trail_bf16x3": (1e-3, 3e-4, 3e-4)}
 MODES = list(TOLS)
 FLOOR = 1e-9
 
@@ -107,12 +109,14 @@ def full16384():
     return {"inp": inp, "L": L, "rev": rev, "fwd": fwd}
 
 
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", ["f64"] + MODES)
 def test_mixed_full_size_n16384(cg, full16384, mode):
-    """The benchmark's N = 16384 workload: factor, rev and fwd in the reduced-precision modes
-    against the oracle on the same device-built inputs."""
+    """The benchmark's N = 16384 workload: factor, rev and fwd in FP64 (1e-10 element-wise against
+    the oracle: rev and fwd on the oracle's L) and in the reduced-precision modes, against the
+    oracle on the same device-built inputs."""
     inp, L = full16384["inp"], full16384["L"]
-    tol_l, tol_s, tol_d = TOLS[mode]
+    tol_l, tol_s, tol_d = TOLS.get(mode, (1e-10, 1e-10, 1e-10))
+    floor = FLOOR if mode in TOLS else 0.0
     A, info = cg.chol_factor(inp["Sigma"].clone(), nb=128, precision=mode)
     assert int(info.item()) == 0
     eL = rel(A.cpu().numpy(), L)
@@ -121,6 +125,6 @@ def test_mixed_full_size_n16384(cg, full16384, mode):
     eS = rel(cg.chol_rev(Lt, inp["Lbar"].clone(), nb=128, precision=mode).cpu().numpy(), full16384["rev"])
     eD = rel(cg.chol_fwd(Lt, inp["Sdot"].clone(), nb=128, precision=mode).cpu().numpy(), full16384["fwd"])
     print(f"{mode} N=16384 nb=128: relL {eL:.2e}  rel Sigma-bar {eS:.2e}  rel L-dot {eD:.2e}")
-    assert FLOOR < eL <= tol_l
-    assert FLOOR < eS <= tol_s
-    assert FLOOR < eD <= tol_d
+    assert floor <= eL <= tol_l
+    assert floor <= eS <= tol_s
+    assert floor <= eD <= tol_d

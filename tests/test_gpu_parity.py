@@ -80,10 +80,10 @@ def test_rev_diagonal_variants_agree(cg, dev, N, nb):
     sym = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=nb, diag="symbolic").cpu().numpy()
     lev2 = cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=nb, diag="level2").cpu().numpy()
     kappa = np.linalg.cond(c["Sigma"])
-    tol = max(TOL, 100 * kappa * np.finfo(np.float64).eps)
     print(f"N={N} kappa={kappa:.1e}: symbolic {rel(sym, want):.2e}  Level-2 {rel(lev2, want):.2e}  "
           f"between {rel(sym, lev2):.2e}")
-    assert rel(sym, want) <= tol and rel(lev2, want) <= tol and rel(sym, lev2) <= tol
+    # both sides use the same L, so the FP64 gate holds whatever the conditioning of Sigma
+    assert rel(sym, want) <= TOL and rel(lev2, want) <= TOL and rel(sym, lev2) <= TOL
     assert np.array_equal(sym, sym.T) and np.array_equal(lev2, lev2.T)
 
 
@@ -116,10 +116,10 @@ def test_fwd_diagonal_variants_agree(cg, dev, N, nb):
     sym = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=nb, diag="symbolic").cpu().numpy()
     lev2 = cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=nb, diag="level2").cpu().numpy()
     kappa = np.linalg.cond(c["Sigma"])
-    tol = max(TOL, 100 * kappa * np.finfo(np.float64).eps)
     print(f"N={N} kappa={kappa:.1e}: symbolic {rel(sym, want):.2e}  Level-2 {rel(lev2, want):.2e}  "
           f"between {rel(sym, lev2):.2e}")
-    assert rel(sym, want) <= tol and rel(lev2, want) <= tol and rel(sym, lev2) <= tol
+    # both sides use the same L, so the FP64 gate holds whatever the conditioning of Sigma
+    assert rel(sym, want) <= TOL and rel(lev2, want) <= TOL and rel(sym, lev2) <= TOL
     assert np.all(np.triu(sym, 1) == 0) and np.all(np.triu(lev2, 1) == 0)
 
 

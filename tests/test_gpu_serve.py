@@ -138,7 +138,8 @@ def test_serve_under_a_tight_budget(cg):
     from paper_1602_07527_amd import serve
     tr = _trace(0.5, seed=78)
     srv = serve.Server("cuda:0", hbm_budget=1)
-    budget = max(srv.footprint(int(n)) for n in tr["n"]) + srv.footprint(64)
+    alone = lambda n: srv.footprint(n) + (srv.group_workspace(1, n) if n <= serve.SMALL_MAX else 0)
+    budget = max(alone(int(n)) for n in tr["n"]) + alone(64)
     srv = serve.Server("cuda:0", hbm_budget=budget)
     order = []
     done, wall = serve.replay(srv, tr["t"], _make_inputs(tr), on_done=lambda r: order.append(r.t_admit))
@@ -149,7 +150,19 @@ def test_serve_under_a_tight_budget(cg):
     assert admits == sorted(admits)                     # nobody overtook an earlier request
 
 
+# Stated per-request accuracy of mixed-precision serving ('f64_trail_f32': factor and reverse sweep
+# of every request above the batched size limit with FP32-MFMA trailing contractions, each request
+# on its own L) on the serving workload (n log-uniform in [64, 4096], 2-D squared-exponential
+# kernels with lengthscale U[0.1, 0.5] + 1e-3 I, condition numbers up to ~2e6).  Measured on
+# MI355X over 420 requests of the 60 s stream (400 drawn at random plus the 20 with the largest
+# n * lengthscale): rel Sigma-bar p50 2.7e-3, p95 8.9e-3, max 9.2e-3; relL max 2.7e-4.
+SERVE_MIXED_REL_SBAR = 2e-2
+SERVE_MIXED_REL_L = 6e-4
+
+
 def test_serve_mixed_precision_within_stated_tolerance(cg):
+    """Mixed-precision served results against the oracle (each side factors for itself), for
+    requests of moderate size, at the stated per-request bounds."""
     from paper_1602_07527_amd import serve
     tr = _trace(1.0, seed=79)
     big = [i for i in range(len(tr["t"])) if 600 <= tr["n"][i] <= 1100][:3]
@@ -164,9 +177,45 @@ def test_serve_mixed_precision_within_stated_tolerance(cg):
     for i, r in zip(big, reqs):
         Sigma, Lbar = make(i)
         S, Lb = Sigma.cpu().numpy(), np.tril(Lbar.cpu().numpy())
-        L = O.chol(S)[0]
+        L = O.chol_host(S)
         eL = rel(r.L.cpu().numpy(), L)
         eS = rel(r.Sbar.cpu().numpy(), O.chol_rev(L, Lb))
-        kappa = np.linalg.cond(S)
-        print(f"mixed serving n={tr['n'][i]} kappa={kappa:.1e}: relL {eL:.2e} rel Sigma-bar {eS:.2e}")
-        assert eL <= max(3e-4, 100 * kappa * 6e-8) and eS <= max(3e-3, 1e3 * kappa * 6e-8)
+        print(f"mixed serving n={tr['n'][i]}: relL {eL:.2e} rel Sigma-bar {eS:.2e}")
+        assert 1e-9 < eS <= SERVE_MIXED_REL_SBAR and eL <= SERVE_MIXED_REL_L
+
+
+def test_serve_mixed_precision_worst_requests(cg):
+    """The worst-conditioned requests of the 60 s serving stream (largest n * lengthscale, n near
+    4096 and lengthscale near 0.5): the mixed-precision served Sigma-bar against the oracle for the
+    two worst, and against the FP64 served result (itself within max(1e-10, 100 kappa u) of the
+    oracle) for the next six, all at the stated per-request bounds."""
+    import torch
+    from paper_1602_07527_amd import serve
+    tr = W.serve_trace(rate=200.0, seconds=60.0)
+    worst = [int(i) for i in np.argsort(tr["n"] * tr["lengthscale"])[::-1][:8]]
+    make = _make_inputs(tr)
+    for rank, i in enumerate(worst):
+        out = {}
+        for mode in ("f64", "f64_trail_f32"):
+            srv = serve.Server("cuda:0", hbm_budget=8 << 30, precision=mode)
+            Sigma, Lbar = make(i)
+            r = srv.submit(serve.Request(i, Sigma, Lbar))
+            srv.drain()
+            assert int(r.info.item()) == 0
+            out[mode] = r
+        mixed, f64 = out["f64_trail_f32"], out["f64"]
+        if rank < 2:
+            Sigma, Lbar = make(i)
+            S, Lb = Sigma.cpu().numpy(), np.tril(Lbar.cpu().numpy())
+            L = O.chol_host(S)
+            eL = rel(mixed.L.cpu().numpy(), L)
+            eS = rel(mixed.Sbar.cpu().numpy(), O.chol_rev(L, Lb))
+            ref = "oracle"
+        else:
+            nrm = lambda x: float(torch.linalg.norm(x))
+            eL = nrm(mixed.L - f64.L) / nrm(f64.L)
+            eS = nrm(mixed.Sbar - f64.Sbar) / nrm(f64.Sbar)
+            ref = "FP64 served"
+        print(f"mixed serving n={tr['n'][i]} lengthscale={tr['lengthscale'][i]:.3f}: relL {eL:.2e} "
+              f"rel Sigma-bar {eS:.2e} (vs {ref})")
+        assert 1e-9 < eS <= SERVE_MIXED_REL_SBAR and eL <= SERVE_MIXED_REL_L
