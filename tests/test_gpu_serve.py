@@ -70,6 +70,15 @@ def _make_inputs(tr):
     return lambda i: W.se_request_device(tr["n"][i], tr["lengthscale"][i], tr["seed"][i], dev)
 
 
+def _request(serve, rid, Sigma, Lbar):
+    """A request whose launch waits for its inputs, written on the current stream (the server
+    launches on streams of its own)."""
+    import torch
+    ev = torch.cuda.Event()
+    ev.record()
+    return serve.Request(rid, Sigma, Lbar, ready=ev)
+
+
 @pytest.fixture(scope="module")
 def served(cg):
     """One 3-second stream through an FP64 server; results of every request copied to the host."""
@@ -110,7 +119,7 @@ def test_serve_alone_equals_mix_bitwise(cg, served):
     for i in pick:
         srv = serve.Server("cuda:0", hbm_budget=8 << 30)
         Sigma, Lbar = make(i)
-        r = srv.submit(serve.Request(int(i), Sigma, Lbar))
+        r = srv.submit(_request(serve, int(i), Sigma, Lbar))
         srv.drain()
         assert int(r.info.item()) == 0
         assert np.array_equal(r.L.cpu().numpy(), res[i][1]), f"L of request {i} (n={tr['n'][i]})"
@@ -172,7 +181,7 @@ def test_serve_mixed_precision_within_stated_tolerance(cg):
     reqs = []
     for i in big:
         Sigma, Lbar = make(i)
-        reqs.append(srv.submit(serve.Request(int(i), Sigma, Lbar)))
+        reqs.append(srv.submit(_request(serve, int(i), Sigma, Lbar)))
     srv.drain()
     for i, r in zip(big, reqs):
         Sigma, Lbar = make(i)
@@ -199,7 +208,7 @@ def test_serve_mixed_precision_worst_requests(cg):
         for mode in ("f64", "f64_trail_f32"):
             srv = serve.Server("cuda:0", hbm_budget=8 << 30, precision=mode)
             Sigma, Lbar = make(i)
-            r = srv.submit(serve.Request(i, Sigma, Lbar))
+            r = srv.submit(_request(serve, i, Sigma, Lbar))
             srv.drain()
             assert int(r.info.item()) == 0
             out[mode] = r
