@@ -51,6 +51,7 @@ extern "C" {
 #define CHOL_ERR_HIP (-101)          /* a HIP runtime call or kernel launch failed           */
 #define CHOL_ERR_WORKSPACE (-102)    /* workspace NULL, too small, or not 256-byte aligned    */
 #define CHOL_ERR_UNSUPPORTED (-103)  /* precision / form / size combination not implemented */
+#define CHOL_ERR_TOO_LARGE (-104)    /* beyond the static scratch of chol_rev_noalloc        */
 
 /* Precision of the call.
  *   CHOL_PREC_F64 : double storage; every step in FP64 (FP64 MFMA for the contractions).
@@ -175,6 +176,24 @@ int chol_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int6
 int chol_rev_ex(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda,
                 int sbar_form, int nb, int diag, int layout, void *workspace, size_t workspace_bytes,
                 void *stream);
+
+/*
+ * chol_rev_noalloc -- chol_rev for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same sweep, with the
+ * symbolic diagonal-block variant, but its workspace is a static device array of the library
+ * (45 MiB, held on each device the call runs on until the process ends) instead of a caller's
+ * buffer.  The call allocates nothing, frees nothing and creates no stream or event; the device
+ * address of the array is looked up once per device, on the first call with that device current.
+ *   n  <= 4096 (CHOL_ERR_TOO_LARGE above), nb <= 128 (0 selects 128; -8 otherwise).
+ *   Every call on a device shares that device's array: calls that overlap in time on one device
+ *   (on different streams, or from different host threads) race and give wrong results; calls
+ *   ordered on one stream are safe.  The array keeps the last call's contents; nothing in it needs
+ *   to start at zero.
+ *   Other arguments, results and errors as chol_rev (row-major storage).
+ *   Arguments: 1 precision, 2 n, 3 L, 4 ldl, 5 A, 6 lda, 7 sbar_form, 8 nb, 9 stream.
+ */
+int chol_rev_noalloc(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda,
+                     int sbar_form, int nb, void *stream);
 
 /*
  * chol_fwd -- forward-mode propagation L-dot(L, Sigma-dot), Sec. 4.2 chol_blocked_fwd, left to

@@ -65,6 +65,8 @@ def load_library():
     lib.chol_rev.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, vp, sz, vp]
     lib.chol_rev_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, i32, i32, vp, sz, vp]
     lib.chol_rev.restype = i32
+    lib.chol_rev_noalloc.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, vp]
+    lib.chol_rev_noalloc.restype = i32
     lib.chol_fwd.argtypes = [i32, i64, vp, i64, vp, i64, i32, vp, sz, vp]
     lib.chol_fwd_ex.argtypes = [i32, i64, vp, i64, vp, i64, i32, i32, i32, vp, sz, vp]
     lib.chol_fwd.restype = i32
@@ -180,6 +182,20 @@ def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64", diag="auto
     with torch.cuda.device(A.device):
         _check("chol_rev", lib.chol_rev_ex(prec, n, L.data_ptr(), _ld(L, layout), A.data_ptr(), _ld(A, layout),
                                            fm, nb, dv, lay, ws.data_ptr(), ws.numel(), _stream(A.device)))
+    return A
+
+
+def chol_rev_noalloc(L, A, form="sym", nb=0, precision="f64"):
+    """chol_rev without a workspace: the library's static device scratch (n <= 4096, nb <= 128;
+    symbolic diagonal blocks; row-major).  Calls overlapping on one device race (see the header)."""
+    lib = load_library()
+    prec, fm = _pick(_PRECS, precision, "precision"), _pick(_FORMS, form, "form")
+    n = _square("L", L)
+    if _square("A", A) != n or A.device != L.device:
+        raise ValueError("L and A must have the same size and device")
+    with torch.cuda.device(A.device):
+        _check("chol_rev_noalloc", lib.chol_rev_noalloc(prec, n, L.data_ptr(), _ld(L), A.data_ptr(), _ld(A), fm,
+                                                        nb, _stream(A.device)))
     return A
 
 

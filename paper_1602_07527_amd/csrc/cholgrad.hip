@@ -10,6 +10,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <mutex>
 #include <vector>
 
@@ -33,7 +34,17 @@ constexpr int SK_WGS = 480;
 constexpr int SK_WGS_SHORT = 448;
 constexpr int64_t SK_SHORT_KTILES = 48;
 constexpr int64_t PART_SLOTS = 2 * TARGET_WGS;  // 128 x 128 partial tiles per buffer
-constexpr int64_t PART_ELEMS = PART_SLOTS * cg::GEMM_BM * cg::GEMM_BN;
+constexpr int64_t TILE_ELEMS = (int64_t)cg::GEMM_BM * cg::GEMM_BN;
+
+// A buffer of 128 x 128 partial tiles for split-K and stream-K products: base and capacity in
+// tiles.  A null buffer forbids splitting.
+struct PartBuf {
+  double *p = nullptr;
+  int64_t slots = 0;
+  PartBuf() = default;
+  PartBuf(std::nullptr_t) {}
+  PartBuf(double *base, int64_t n) : p(base), slots(base ? n : 0) {}
+};
 
 // Benchmark instrumentation: event pairs around the panel contractions, per sweep (see
 // chol_profile_begin).  Process-global and not thread-safe; off unless a benchmark enables it.
@@ -67,19 +78,22 @@ struct SweepWs {
   double *dinv = nullptr;   // inverses of the diagonal blocks of L: nblk x nb x nb
   double *panel = nullptr;  // one block column: n x nb
   double *dblk = nullptr;   // one diagonal block: nb x nb
-  double *part = nullptr;   // split-K partial tiles of the main stream: PART_ELEMS
-  double *part2 = nullptr;  // split-K partial tiles of the side stream: PART_ELEMS
+  PartBuf part;             // split-K partial tiles of the main stream
+  PartBuf part2;            // split-K partial tiles of the side stream
   double *tmp = nullptr;    // two nb x nb blocks for the symbolic diagonal-block variants
 };
 
-size_t carve(int64_t n, int nb, void *base, SweepWs *w) {
+// part_slots / part2_slots: capacity of the two partial-tile buffers (PART_SLOTS by default; the
+// allocation-free entry point carves a smaller main buffer and no side buffer).
+size_t carve(int64_t n, int nb, void *base, SweepWs *w, int64_t part_slots = PART_SLOTS,
+             int64_t part2_slots = PART_SLOTS) {
   Carver c(base);
   const int64_t nblk = cdiv(n, nb);
   w->dinv = c.take((size_t)nblk * nb * nb);
   w->panel = c.take((size_t)n * nb);
   w->dblk = c.take((size_t)nb * nb);
-  w->part = c.take((size_t)PART_ELEMS);
-  w->part2 = c.take((size_t)PART_ELEMS);
+  w->part = PartBuf(c.take((size_t)(part_slots * TILE_ELEMS)), part_slots);
+  w->part2 = PartBuf(c.take((size_t)(part2_slots * TILE_ELEMS)), part2_slots);
   w->tmp = c.take((size_t)2 * nb * nb);
   return c.off;
 }
@@ -209,7 +223,7 @@ bool dma_ld_ok(int64_t ld) { return ld % 2 == 0 && ld < ((int64_t)1 << 21); }
 hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t lda,
                 const double *B, int64_t ldb, double alpha, const double *Cin, int64_t ldcin,
                 double beta, double *C, int64_t ldc, double *Cm, int64_t ldcm, int lower_only,
-                double *part, int min_kchunk, hipStream_t s, int tag = 0, int cp = cg::CP_F64,
+                PartBuf part, int min_kchunk, hipStream_t s, int tag = 0, int cp = cg::CP_F64,
                 Pair2 q = Pair2()) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, cg::GEMM_BN);
@@ -229,19 +243,19 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   // (>= min_kchunk) to be worth a partial tile; the pieces are then summed per tile in workgroup
   // order.
   int64_t skw = 0;
-  if (part && fast && !lower_only && Kt > 0 && tiles >= 2) {
+  if (part.p && fast && !lower_only && Kt > 0 && tiles >= 2) {
     const int64_t units = (int64_t)tiles * (Kt / cg::DMA_BK);
     skw = units < SK_SHORT_KTILES * SK_WGS ? SK_WGS_SHORT : SK_WGS;
     skw = std::min<int64_t>(skw, units * cg::DMA_BK / std::max(min_kchunk, cg::DMA_BK));
-    skw = std::min<int64_t>(skw, PART_SLOTS - tiles + 1);
+    skw = std::min<int64_t>(skw, part.slots - tiles + 1);
     if (skw <= tiles) skw = 0;
   }
   int S = 1;
   int kchunk = (int)(cdiv(Kt > 0 ? Kt : 1, kstep) * kstep);
-  if (part && Kt > 0 && !skw) {
+  if (part.p && Kt > 0 && !skw) {
     int64_t s_want = TARGET_WGS / tiles;
     s_want = std::min<int64_t>(s_want, cdiv(Kt, min_kchunk));
-    s_want = std::min<int64_t>(s_want, PART_ELEMS / ((int64_t)M * N));
+    s_want = std::min<int64_t>(s_want, part.slots * TILE_ELEMS / ((int64_t)M * N));
     if (s_want > 1) {
       kchunk = (int)(cdiv(cdiv(Kt, s_want), kstep) * kstep);
       S = (int)cdiv(Kt, kchunk);
@@ -255,14 +269,14 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   p.lower_only = lower_only;
   const dim3 grid = skw ? dim3((unsigned)skw, 1, 1) : dim3(tm, tn, S);
   if (skw) {
-    p.C = part; p.ldc = cg::GEMM_BN; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
+    p.C = part.p; p.ldc = cg::GEMM_BN; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
     p.Cm = nullptr; p.ldcm = 0; p.split_stride = (int64_t)cg::GEMM_BM * cg::GEMM_BN;
     p.sk_wgs = (int)skw; p.sk_kt = Kt / cg::DMA_BK; p.sk_tm = tm; p.sk_tiles = tiles;
   } else if (S == 1) {
     p.C = C; p.ldc = ldc; p.Cin = Cin; p.ldcin = ldcin; p.alpha = alpha; p.beta = beta;
     p.Cm = Cm; p.ldcm = ldcm; p.split_stride = 0;
   } else {
-    p.C = part; p.ldc = N; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
+    p.C = part.p; p.ldc = N; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
     p.Cm = nullptr; p.ldcm = 0; p.split_stride = (int64_t)M * N;
   }
   const bool timed = g_prof.on && tag > 0 && g_prof.used < g_prof.cap;
@@ -285,7 +299,7 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   const int64_t total = (int64_t)M * N;
   if (e == hipSuccess && skw) {
     const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 4096);
-    hipLaunchKernelGGL(cg::reduce_streamk_kernel, dim3(blocks), dim3(256), 0, s, M, N, part,
+    hipLaunchKernelGGL(cg::reduce_streamk_kernel, dim3(blocks), dim3(256), 0, s, M, N, (const double *)part.p,
                        (int64_t)cg::GEMM_BM * cg::GEMM_BN, skw, (int64_t)(Kt / cg::DMA_BK), tm, alpha,
                        Cin, ldcin, beta, C, ldc, Cm, ldcm);
     return hipGetLastError();
@@ -293,13 +307,13 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   if (e != hipSuccess || S == 1) return e;
   if (S >= 4 * cg::RG_GROUPS && total <= (int64_t)64 * 1024) {  // many splits of a small output
     const int blocks = (int)std::min<int64_t>(cdiv(total, cg::RG_ELEMS), 4096);
-    hipLaunchKernelGGL(cg::reduce_splits_grouped_kernel, dim3(blocks), dim3(256), 0, s, M, N, part,
+    hipLaunchKernelGGL(cg::reduce_splits_grouped_kernel, dim3(blocks), dim3(256), 0, s, M, N, (const double *)part.p,
                        (int64_t)N, (int64_t)M * N, S, alpha, Cin, ldcin, beta, C, ldc, Cm, ldcm,
                        lower_only);
     return hipGetLastError();
   }
   const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 4096);
-  hipLaunchKernelGGL(cg::reduce_splits_kernel, dim3(blocks), dim3(256), 0, s, M, N, part, (int64_t)N,
+  hipLaunchKernelGGL(cg::reduce_splits_kernel, dim3(blocks), dim3(256), 0, s, M, N, (const double *)part.p, (int64_t)N,
                      (int64_t)M * N, S, alpha, Cin, ldcin, beta, C, ldc, Cm, ldcm, lower_only);
   return hipGetLastError();
 }
@@ -424,6 +438,7 @@ const char *chol_status_string(int status) {
     case CHOL_ERR_HIP: return "a HIP runtime call or kernel launch failed";
     case CHOL_ERR_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
     case CHOL_ERR_UNSUPPORTED: return "unsupported precision, form or size";
+    case CHOL_ERR_TOO_LARGE: return "problem larger than the allocation-free entry point's static scratch allows";
     default: break;
   }
   if (status < 0 && status > -32) return "invalid argument (status -i names argument i)";
@@ -449,7 +464,8 @@ bool diag_ok(int diag) { return diag == CHOL_DIAG_AUTO || diag == CHOL_DIAG_SYMB
 bool diag_symbolic(int diag) { return diag != CHOL_DIAG_LEVEL2; }
 
 static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
-                    int sbar_form, int nb, int diag, void *workspace, size_t workspace_bytes, void *stream) {
+                    int sbar_form, int nb, int diag, void *workspace, size_t workspace_bytes, void *stream,
+                    int64_t part_slots = PART_SLOTS, int64_t part2_slots = PART_SLOTS) {
   if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
   int cp = cg::CP_F64;
   if (!single_prec(precision, &cp)) return -1;
@@ -464,10 +480,10 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
   if (!diag_ok(diag)) return -9;
   if (nb == 0) nb = DEFAULT_NB;
   SweepWs ws;
-  const size_t need = carve(n, nb, nullptr, &ws);
+  const size_t need = carve(n, nb, nullptr, &ws, part_slots, part2_slots);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
     return CHOL_ERR_WORKSPACE;
-  carve(n, nb, workspace, &ws);
+  carve(n, nb, workspace, &ws, part_slots, part2_slots);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double *L = static_cast<const double *>(Lv);
   double *A = static_cast<double *>(Av);
@@ -584,6 +600,64 @@ int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, in
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
   return rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_AUTO, workspace, workspace_bytes,
                   stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// chol_rev_noalloc: chol_rev with its workspace in a file-scope device array instead of the
+// caller's buffer.  The array's name is a host-side stand-in in host code; the device address
+// comes from hipGetSymbolAddress, once per device (each device holds its own copy), with that
+// device current.  Layout of the array: carve(n, nb) with a partial-tile buffer of
+// NOALLOC_PART_SLOTS tiles and no side-stream buffer; at n = 4096, nb = 128 that is 4 MiB of block
+// inverses + 4 MiB of panel + 0.4 MiB of small blocks + 36 MiB of partial tiles = 44.4 MiB.
+namespace {
+constexpr int64_t NOALLOC_N_MAX = 4096;
+constexpr int NOALLOC_NB_MAX = 128;
+constexpr int64_t NOALLOC_PART_SLOTS = 288;  // stream-K over up to ~258 workgroups at n = 4096
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)45 << 20;
+
+__device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the first call per device).
+hipError_t scratch_ptr(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int chol_rev_noalloc(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
+                     int sbar_form, int nb, void *stream) {
+  // Arguments first (a dry call without workspace), before the device is touched.
+  const int chk = rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_SYMBOLIC, nullptr, 0, stream,
+                           NOALLOC_PART_SLOTS, 0);
+  if (chk != CHOL_ERR_WORKSPACE) return chk;  // CHOL_SUCCESS for n == 0, or an argument error
+  if (n > NOALLOC_N_MAX) return CHOL_ERR_TOO_LARGE;
+  if (nb > NOALLOC_NB_MAX) return -8;
+  SweepWs w;
+  if (carve(n, nb ? nb : DEFAULT_NB, nullptr, &w, NOALLOC_PART_SLOTS, 0) > NOALLOC_SCRATCH_BYTES)
+    return CHOL_ERR_TOO_LARGE;
+  void *ws = nullptr;
+  CG_TRY(scratch_ptr(&ws));
+  return rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_SYMBOLIC, ws, NOALLOC_SCRATCH_BYTES,
+                  stream, NOALLOC_PART_SLOTS, 0);
 }
 
 int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *info,

@@ -115,3 +115,22 @@ def test_precision_modes_on_host():
     assert lib.chol_factor_batched(3, 1, None, None, None, 4, None, None, 0, None) == -103
     assert lib.chol_batched_workspace_bytes(3, 1, 4) == 0
     assert lib.chol_factor_batched(7, 1, None, None, None, 4, None, None, 0, None) == -1
+
+
+def test_noalloc_entry_rejects_on_host():
+    """chol_rev_noalloc validates every argument, then its size limits (n <= 4096, nb <= 128),
+    before it touches a device."""
+    lib = _lib()
+    fake = ctypes.c_void_p(4096)
+    f = lib.chol_rev_noalloc
+    assert f(7, 10, fake, 10, fake, 10, 0, 0, None) == -1
+    assert f(0, -1, fake, 10, fake, 10, 0, 0, None) == -2
+    assert f(0, 10, None, 10, fake, 10, 0, 0, None) == -3
+    assert f(0, 10, fake, 9, fake, 10, 0, 0, None) == -4
+    assert f(0, 10, fake, 10, fake, 3, 0, 0, None) == -6
+    assert f(0, 10, fake, 10, fake, 10, 2, 0, None) == -7
+    assert f(0, 10, fake, 10, fake, 10, 0, 48, None) == -8
+    assert f(0, 4097, fake, 4097, fake, 4097, 0, 0, None) == -104
+    assert f(1, 10, fake, 10, fake, 10, 0, 0, None) == -103
+    assert f(0, 0, None, 0, None, 0, 0, 0, None) == 0
+    assert lib.chol_status_string(-104).startswith(b"problem larger")
