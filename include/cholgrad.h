@@ -31,8 +31,11 @@
  *     Numerical breakdown of chol_factor is reported asynchronously through `info`.
  *   - n == 0 is a no-op that returns CHOL_SUCCESS.
  *   - nb is the block size of the Level-3 sweep (Sec. 4.2, N_b): 0 selects the default (128);
- *     otherwise 32 <= nb <= 128 and nb % 32 == 0.  The result does not depend on nb beyond
- *     rounding (the column partition is arbitrary, Sec. 4.2).
+ *     otherwise 16 <= nb <= 256 and nb % 16 == 0.  The result does not depend on nb beyond
+ *     rounding (the column partition is arbitrary, Sec. 4.2).  Blocks wider than 128 factor and
+ *     invert their diagonal block as two halves (Sec. 4.2's remark that the unblocked routine may
+ *     be replaced by a recursive one for large blocks); the Level-2 diagonal-block variant
+ *     (CHOL_DIAG_LEVEL2) is limited to nb <= 128 and returns CHOL_ERR_UNSUPPORTED above.
  */
 #ifndef CHOLGRAD_H
 #define CHOLGRAD_H

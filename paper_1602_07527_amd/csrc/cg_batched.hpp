@@ -65,7 +65,7 @@ __host__ __device__ constexpr int64_t stage_doubles(int64_t n_max) {
 // matrix kernels inline them).
 __device__ __noinline__ void nl_trinv_block(int w, const double *Ld, int64_t ldl, double *Dinv, int nb,
                                             double *Dp, double *Xp) {
-  trinv_block(w, Ld, ldl, Dinv, nb, as_lds(Dp), as_lds(Xp));
+  trinv_block(w, Ld, ldl, Dinv, nb, nb, 0, as_lds(Dp), as_lds(Xp));
 }
 __device__ __noinline__ void nl_diag_rev_block(int w, const double *Ld, int64_t ldl, const double *Dbar,
                                                int64_t ldd, const double *Dinv, int nb, double *Aout,
@@ -78,7 +78,7 @@ __device__ __noinline__ void nl_diag_fwd_block(int w, const double *Ld, int64_t 
 }
 __device__ __noinline__ void nl_potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int nb, int *info,
                                             int64_t col0, double *Dp, double *Xp, int &bad) {
-  potf2_block(w, Ad, lda, Dinv, nb, info, col0, as_lds(Dp), as_lds(Xp), bad);
+  potf2_block(w, Ad, lda, Dinv, nb, nb, 0, info, col0, as_lds(Dp), as_lds(Xp), bad);
 }
 
 // C = alpha op(A) op(B) + beta Cin over all 128 x 128 output tiles, by the whole workgroup.

@@ -417,31 +417,52 @@ __device__ void block_inverse(const double *Dp, double *Xp, int w) {
   }
 }
 
-// Write the packed lower triangle of a w x w block to a row-major nb x nb buffer, zero elsewhere.
-__device__ __forceinline__ void store_lower_square(double *dst, int nb, const double *Xp, int w) {
-  store_block(dst, nb, nb, nb, [&](int r, int c) { return (r < w && c <= r) ? Xp[pidx(r, c)] : 0.0; });
+// Write the packed lower triangle of a w x w block into the ext x ext region at dst (row-major,
+// leading dimension ld, ext <= 128), zero elsewhere in the region, and zero `right` (<= 128) more
+// columns to the right of the region in its rows (the part of a wider block's inverse above the
+// next diagonal half).
+__device__ __forceinline__ void store_lower_region(double *dst, int64_t ld, int ext, const double *Xp, int w,
+                                                   int right) {
+  store_block(dst, ld, ext, ext, [&](int r, int c) { return (r < w && c <= r) ? Xp[pidx(r, c)] : 0.0; });
+  if (right > 0) store_block(dst + ext, ld, ext, right, [&](int, int) { return 0.0; });
 }
 
 // ---------------------------------------------------------------------------------------------
-// Inverse of each lower-triangular diagonal block: block b covers rows/cols [b*nb, min(n,(b+1)nb)).
-// Output Dinv + b*nb*nb, row-major with leading dimension nb, zero above the diagonal and outside
-// the w x w block.
-__device__ __forceinline__ void trinv_block(int w, const double *Ld, int64_t ldl, double *Dinv, int nb, double *Dp,
-                            double *Xp) {
+// Inverse of one lower-triangular w x w block (w <= 128) of L (ldl) into the ext x ext region at
+// Dinv (leading dimension ld; see store_lower_region).
+__device__ __forceinline__ void trinv_block(int w, const double *Ld, int64_t ldl, double *Dinv, int64_t ld,
+                                            int ext, int right, double *Dp, double *Xp) {
   load_packed2(Dp, Ld, ldl, nullptr, nullptr, 0, w);
   __syncthreads();
   block_inverse(Dp, Xp, w);
-  store_lower_square(Dinv, nb, Xp, w);
+  store_lower_region(Dinv, ld, ext, Xp, w, right);
   __syncthreads();
 }
 
+// Inverse of each lower-triangular diagonal block: block b covers rows/cols [b*nb, min(n,(b+1)nb)).
+// Output Dinv + b*nb*nb, row-major with leading dimension nb, zero above the diagonal.
+//   nb <= 128: workgroup b inverts block b whole (zero outside its w x w part as well).
+//   128 < nb <= 256: workgroups 2b and 2b+1 invert the two halves of block b (widths 128 and
+//   w - 128) into their diagonal positions; the first also zeroes the part above the second
+//   half.  The part below the first half, -X11 L10 X00, comes from inv_offdiag_kernel.
 __global__ __launch_bounds__(DIAG_THREADS) void trinv_kernel(int64_t n, int nb, const double *L,
                                                              int64_t ldl, double *Dinv) {
   __shared__ double Dp[DIAG_PACKED];
   __shared__ double Xp[DIAG_PACKED];
-  const int64_t j = (int64_t)blockIdx.x * nb;
-  const int w = (int)min<int64_t>(nb, n - j);
-  trinv_block(w, L + j * ldl + j, ldl, Dinv + (int64_t)blockIdx.x * nb * nb, nb, Dp, Xp);
+  if (nb <= DIAG_MAX) {
+    const int64_t j = (int64_t)blockIdx.x * nb;
+    const int w = (int)min<int64_t>(nb, n - j);
+    trinv_block(w, L + j * ldl + j, ldl, Dinv + (int64_t)blockIdx.x * nb * nb, nb, nb, 0, Dp, Xp);
+    return;
+  }
+  const int64_t b = blockIdx.x >> 1;
+  const int h = blockIdx.x & 1;
+  const int wb = (int)min<int64_t>(nb, n - b * nb);   // width of block b
+  const int w = min(DIAG_MAX, wb - h * DIAG_MAX);      // width of this half
+  if (w <= 0) return;                                   // workgroup-uniform
+  const int64_t j = b * nb + h * DIAG_MAX;
+  double *dst = Dinv + b * nb * nb + (int64_t)h * DIAG_MAX * nb + h * DIAG_MAX;
+  trinv_block(w, L + j * ldl + j, ldl, dst, nb, w, h == 0 ? wb - w : 0, Dp, Xp);
 }
 
 // Stage the 32 x 32 diagonal sub-block [a, a+32)^2 of a block inverse (row-major, ld nb) in LDS.
@@ -689,8 +710,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const dou
 // with NaN so that every kernel still exits normally.
 // In/out: A + (j, j) (lower triangle in, factor out, strict upper set to 0).  Out: Dinv (w x w
 // inverse, ld nb, zero above the diagonal).
-__device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int nb, int *info,
-                            int64_t col0, double *Dp, double *Xp, int &bad) {
+__device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int64_t ld, int ext,
+                                            int right, int *info, int64_t col0, double *Dp, double *Xp, int &bad) {
   const int tid = threadIdx.x, wave = tid >> 6;
   load_packed2(Dp, Ad, lda, nullptr, nullptr, 0, w);
   if (tid == 0) bad = -1;
@@ -733,17 +754,19 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
   if (tid == 0 && bad >= 0 && *info == 0) *info = (int)(col0 + bad + 1);
   block_inverse(Dp, Xp, w);
   store_block(Ad, lda, w, w, [&](int r, int c) { return (c <= r) ? Dp[pidx(r, c)] : 0.0; });
-  store_lower_square(Dinv, nb, Xp, w);
+  store_lower_region(Dinv, ld, ext, Xp, w, right);
   __syncthreads();
 }
 
-__global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, int64_t lda,
-                                                             double *Dinv, int nb, int *info,
+// POTF2 of one w x w block (w <= 128) with its inverse written to the ext x ext region at Dinv
+// (leading dimension ld) and `right` zero columns beside it (see store_lower_region).
+__global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, int64_t lda, double *Dinv,
+                                                             int64_t ld, int ext, int right, int *info,
                                                              int64_t col0) {
   __shared__ double Dp[DIAG_PACKED];
   __shared__ double Xp[DIAG_PACKED];
   __shared__ int bad;
-  potf2_block(w, Ad, lda, Dinv, nb, info, col0, Dp, Xp, bad);
+  potf2_block(w, Ad, lda, Dinv, ld, ext, right, info, col0, Dp, Xp, bad);
 }
 
 // Zero the strict upper triangle of an n x n matrix.
@@ -958,14 +981,19 @@ __global__ __launch_bounds__(256) void sym_fwd_n_kernel(int w, const double *P, 
 
 // Forward, product 3:  L-dot_D = tril(D) Phi(Q) = -(tril(D) N), lower tiles, lower entries written
 // to Ad (lda); D: the factor's diagonal block (ldd).  tril(D)[r][k] needs k <= r and N[k][c]
-// needs k >= c.  The strict upper triangle of Ad is left as it is.
+// needs k >= c.  The strict upper triangle of the block in Ad is set to 0 (products that read
+// the block as a dense operand rely on it).
 __global__ __launch_bounds__(256) void sym_fwd_l_kernel(int w, const double *D, int64_t ldd,
                                                         const double *N, int64_t ldn, double *Ad,
                                                         int64_t lda) {
   __shared__ double red[3 * 256];
   const int nt = (w + SYM_TILE - 1) / SYM_TILE;
   const int r0 = (blockIdx.x / nt) * SYM_TILE, c0 = (blockIdx.x % nt) * SYM_TILE;
-  if (c0 > r0) return;
+  if (c0 > r0) {  // strictly upper tile: zeros, no product (workgroup-uniform)
+    const int r = r0 + (int)threadIdx.x / SYM_TILE, c = c0 + (int)threadIdx.x % SYM_TILE;
+    if (r < w && c < w) Ad[(int64_t)r * lda + c] = 0.0;
+    return;
+  }
   auto Am = [&](int i, int k) {
     const int r = r0 + i;
     return (r < w && k <= r) ? D[(int64_t)r * ldd + k] : 0.0;
@@ -979,7 +1007,7 @@ __global__ __launch_bounds__(256) void sym_fwd_l_kernel(int w, const double *D, 
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int r = r0 + tile_row(e), c = c0 + tile_col();
-    if (r < w && c <= r) Ad[(int64_t)r * lda + c] = -acc[e];
+    if (r < w && c < w) Ad[(int64_t)r * lda + c] = c <= r ? -acc[e] : 0.0;
   }
 }
 
@@ -1051,6 +1079,54 @@ __global__ __launch_bounds__(256) void fwd_panel_solve_kernel(int M, int w, cons
   for (int e = 0; e < 4; ++e) {
     const int r = r0 + tile_row(e), c = c0 + tile_col();
     if (r < M && c < w) Out[(int64_t)r * ldo + c] = acc[e];
+  }
+}
+
+// Lower-left part of the inverse of a block of width 128 < w <= 256 whose two diagonal halves
+// X00 = D00^-1 (128 wide) and X11 = D11^-1 (w - 128 wide) are already in place in Dinv (leading
+// dimension nb):  X10 = -X11 (D10 X00), the block form of the triangular inverse.  Two launches
+// over every such block of L (block b at (b nb, b nb); n bounds the last one):
+//   phase 0: T_b = D10 X00 into T + b * 128 * 128 (ld 128);   phase 1: X10 = -X11 T_b.
+// grid = nblocks * 64, one 16 x 16 tile of a 128 x 128 output per workgroup.
+__global__ __launch_bounds__(256) void inv_offdiag_kernel(int phase, int64_t n, int nb, const double *L,
+                                                          int64_t ldl, double *Dinv, double *T) {
+  __shared__ double red[3 * 256];
+  const int64_t b = blockIdx.x / 64;
+  const int t = blockIdx.x % 64;
+  const int wb = (int)min<int64_t>(nb, n - b * nb);
+  const int h2 = wb - DIAG_MAX;
+  const int r0 = (t / 8) * SYM_TILE, c0 = (t % 8) * SYM_TILE;
+  if (h2 <= 0 || r0 >= h2) return;  // workgroup-uniform
+  double *Xb = Dinv + b * nb * nb;
+  double *Tb = T + b * DIAG_MAX * DIAG_MAX;
+  const double *L10 = L + (b * nb + DIAG_MAX) * ldl + b * nb;
+  dbl4 acc;
+  if (phase == 0) {  // T[r][c] = sum_{k >= c} D10[r][k] X00[k][c]
+    auto A = [&](int i, int k) {
+      const int r = r0 + i;
+      return (r < h2 && k < DIAG_MAX) ? L10[(int64_t)r * ldl + k] : 0.0;
+    };
+    auto B = [&](int k, int j) {
+      const int c = c0 + j;
+      return (k < DIAG_MAX && k >= c) ? Xb[(int64_t)k * nb + c] : 0.0;
+    };
+    acc = wg_tile16(A, B, c0, DIAG_MAX, red);
+  } else {           // X10[r][c] = -sum_{k <= r} X11[r][k] T[k][c]
+    auto A = [&](int i, int k) {
+      const int r = r0 + i;
+      return (r < h2 && k <= r) ? Xb[(int64_t)(DIAG_MAX + r) * nb + DIAG_MAX + k] : 0.0;
+    };
+    auto B = [&](int k, int j) { return (k < h2) ? Tb[(int64_t)k * DIAG_MAX + c0 + j] : 0.0; };
+    acc = wg_tile16(A, B, 0, min(h2, r0 + SYM_TILE), red);
+  }
+  if (threadIdx.x >= 64) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + tile_row(e), c = c0 + tile_col();
+    if (r < h2) {
+      if (phase == 0) Tb[(int64_t)r * DIAG_MAX + c] = acc[e];
+      else Xb[(int64_t)(DIAG_MAX + r) * nb + c] = -acc[e];
+    }
   }
 }
 

@@ -160,7 +160,10 @@ bool single_prec(int precision, int *cp) {
   return false;
 }
 
-bool nb_ok(int nb) { return nb == 0 || (nb >= 32 && nb <= cg::DIAG_MAX && nb % 32 == 0); }
+// Block widths: multiples of 16 up to 256.  Blocks wider than 128 (the widest diagonal block the
+// LDS routines hold) factor and invert their diagonal block as two halves (potf2_any, trinv).
+constexpr int NB_MAX = 2 * cg::DIAG_MAX;
+bool nb_ok(int nb) { return nb == 0 || (nb >= 16 && nb <= NB_MAX && nb % 16 == 0); }
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 template <int TAG, int CP>
@@ -330,6 +333,74 @@ hipError_t copy_scaled(int M, int N, const double *src, int64_t lds, double beta
 }
 
 
+// Inverses of all diagonal blocks of L into dinv (nblk blocks of nb x nb, ld nb), on stream s.  For
+// nb > 128 each block's two halves are inverted separately and the lower-left part follows from
+// them (inv_offdiag_kernel), with T (>= ceil(n / nb) * 128 * 128 doubles) as scratch.
+hipError_t block_inverses(int64_t n, int nb, const double *L, int64_t ldl, double *dinv, double *T,
+                          hipStream_t s) {
+  const int64_t nblk = cdiv(n, nb);
+  const bool halves = nb > cg::DIAG_MAX;
+  hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)(halves ? 2 * nblk : nblk)), dim3(cg::DIAG_THREADS), 0, s, n,
+                     nb, L, ldl, dinv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !halves) return e;
+  for (int phase = 0; phase < 2; ++phase) {
+    hipLaunchKernelGGL(cg::inv_offdiag_kernel, dim3((unsigned)(nblk * 64)), dim3(256), 0, s, phase, n, nb, L, ldl,
+                       dinv, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// D <- chol_unblocked(D) (POTF2) for the w x w diagonal block at Ad, in place, and D^-1 into dinv
+// (ld nb), on stream s.  w <= 128: one potf2_kernel.  128 < w <= 256: the block factored as two
+// halves, as Sec. 4.2's blocked algorithm with a smaller block (the paper suggests a recursive
+// routine in place of the unblocked one for large blocks): POTF2 of the first half, the panel
+// solve D10 <- D10 X00^T and the update D11 <- D11 - D10 D10^T as MFMA products, POTF2 of the
+// second half, then the lower-left part of the inverse (T: 128 * 128 doubles of scratch).
+hipError_t potf2_any(int w, double *Ad, int64_t lda, double *dinv, int nb, int *info, int64_t col0, double *T,
+                     PartBuf part, hipStream_t s) {
+  const int h1 = std::min(w, cg::DIAG_MAX);
+  hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, h1, Ad, lda, dinv, (int64_t)nb,
+                     std::min(nb, cg::DIAG_MAX), w - h1, info, col0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || w <= cg::DIAG_MAX) return e;
+  const int h2 = w - h1;
+  double *A10 = Ad + (int64_t)h1 * lda, *A11 = A10 + h1;
+  // D10 <- D10 X00^T (in place: the output is one 128-wide tile column)
+  if ((e = gemm(false, true, h2, h1, h1, A10, lda, dinv, nb, 1.0, nullptr, 0, 0.0, A10, lda, nullptr, 0, 0, part,
+                32, s)) != hipSuccess)
+    return e;
+  // D11 <- D11 - D10 D10^T
+  if ((e = gemm(false, true, h2, h2, h1, A10, lda, A10, lda, -1.0, A11, lda, 1.0, A11, lda, nullptr, 0, 0, part, 32,
+                s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, h2, A11, lda,
+                     dinv + (int64_t)h1 * nb + h1, (int64_t)nb, h2, 0, info, col0 + h1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int phase = 0; phase < 2; ++phase) {
+    hipLaunchKernelGGL(cg::inv_offdiag_kernel, dim3(64), dim3(256), 0, s, phase, (int64_t)w, nb,
+                       (const double *)Ad, lda, dinv, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// C <- C D^-T for the M x w panel C (ldc) with D^-1 in dinv (ld nb): in place when w <= 128 (each
+// output tile spans every column, so its workgroup reads its rows before writing them), through
+// the buffer `tmp` (M x w, ld nb) otherwise.
+hipError_t panel_solve_t(int M, int w, double *C, int64_t ldc, const double *dinv, int nb, double *tmp,
+                         PartBuf part, int min_kchunk, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  if (w <= cg::GEMM_BN)
+    return gemm(false, true, M, w, w, C, ldc, dinv, nb, 1.0, nullptr, 0, 0.0, C, ldc, nullptr, 0, 0, part,
+                min_kchunk, s);
+  hipError_t e = gemm(false, true, M, w, w, C, ldc, dinv, nb, 1.0, nullptr, 0, 0.0, tmp, nb, nullptr, 0, 0, part,
+                      min_kchunk, s);
+  if (e != hipSuccess) return e;
+  return copy_scaled(M, w, tmp, nb, 1.0, C, ldc, 0, s);
+}
+
 #define CG_TRY(expr)                          \
   do {                                        \
     hipError_t _e = (expr);                   \
@@ -479,6 +550,7 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
   if (!nb_ok(nb)) return -8;
   if (!diag_ok(diag)) return -9;
   if (nb == 0) nb = DEFAULT_NB;
+  if (!diag_symbolic(diag) && nb > cg::DIAG_MAX) return CHOL_ERR_UNSUPPORTED;  // Level-2 cores hold <= 128
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws, part_slots, part2_slots);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
@@ -503,9 +575,7 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
     s2 = side->s;
   }
 
-  hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
-                     ldl, ws.dinv);
-  CG_TRY(hipGetLastError());
+  CG_TRY(block_inverses(n, nb, L, ldl, ws.dinv, ws.panel, s));  // the panel is free until the sweep
   if (any_level2) {
     CG_TRY(hipEventRecord(side->start, s));
     CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
@@ -720,20 +790,16 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
       }
     }
     // D <- chol_unblocked(D); D^-1 for the panel solve
-    hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, A + j * lda + j, lda,
-                       ws.dblk, nb, info, j);
-    CG_TRY(hipGetLastError());
-    // C <- C tril(D)^-T, the next block's rows first (every output tile spans all w <= 128
-    // columns, so in place is safe)
+    CG_TRY(potf2_any(w, A + j * lda + j, lda, ws.dblk, nb, info, j, ws.tmp, ws.part2, s2));
+    // C <- C tril(D)^-T, the next block's rows first
     if (m > 0) {
       const int m1 = std::min(m, nb);
       if (b > 0) CG_TRY(hipStreamWaitEvent(s2, side->low, 0));
-      CG_TRY(gemm(false, true, m1, w, w, A + k * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
-                  A + k * lda + j, lda, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(panel_solve_t(m1, w, A + k * lda + j, lda, ws.dblk, nb, ws.panel, ws.part2, 32, s2));
       CG_TRY(hipEventRecord(side->top, s2));
       if (m > m1)
-        CG_TRY(gemm(false, true, m - m1, w, w, A + (k + m1) * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
-                    A + (k + m1) * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+        CG_TRY(panel_solve_t(m - m1, w, A + (k + m1) * lda + j, lda, ws.dblk, nb, ws.panel + (int64_t)m1 * nb,
+                             nullptr, 128, s2));
     }
     CG_TRY(hipEventRecord(side->panel, s2));
   }
@@ -758,6 +824,7 @@ static int fwd_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
   if (!nb_ok(nb)) return -7;
   if (!diag_ok(diag)) return -8;
   if (nb == 0) nb = DEFAULT_NB;
+  if (!diag_symbolic(diag) && nb > cg::DIAG_MAX) return CHOL_ERR_UNSUPPORTED;  // Level-2 cores hold <= 128
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
@@ -777,9 +844,7 @@ static int fwd_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
     CG_TRY(side_for(s, &side));
     s2 = side->s;
   }
-  hipLaunchKernelGGL(cg::trinv_kernel, dim3((unsigned)nblk), dim3(cg::DIAG_THREADS), 0, s, n, nb, L,
-                     ldl, ws.dinv);
-  CG_TRY(hipGetLastError());
+  CG_TRY(block_inverses(n, nb, L, ldl, ws.dinv, ws.panel, s));  // the panel is free until the sweep
   if (b0 > 0) {
     CG_TRY(hipEventRecord(side->start, s));
     CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
@@ -856,7 +921,7 @@ static int fwd_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
     // (ld nb) and writes L-dot_C to A, so the update puts the block column [D-dot; C-dot] there.
     // For nb = 128 the paired product on 128 x 128 tiles is faster (it reuses each operand strip
     // across all columns): the update and the solve then work in place in A.
-    const bool tiled = nb < 128;
+    const bool tiled = nb != cg::GEMM_BN;
     double *const col = tiled ? ws.panel : A + j * lda + j;
     const int64_t ldcol = tiled ? (int64_t)nb : lda;
     if (j > 0) {
@@ -973,19 +1038,32 @@ int chol_factor_fwd(int precision, int64_t n, void *Av, int64_t lda, void *Dv, i
         CG_TRY(hipEventRecord(side->low, s));
       }
     }
-    // L_bb = chol_unblocked(D_bb) and its inverse; then L-dot_bb = chol_unblocked_fwd(L_bb, D-dot_bb)
-    hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, A + j * lda + j, lda,
-                       ws.dblk, nb, info, j);
-    CG_TRY(hipGetLastError());
-    hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w, (const double *)(A + j * lda + j),
-                       lda, (const double *)ws.dblk, nb, D + j * ldd + j, ldd);
-    CG_TRY(hipGetLastError());
+    // L_bb = chol_unblocked(D_bb) and its inverse; then L-dot_bb from D-dot_bb: the Level-2
+    // chol_unblocked_fwd for blocks up to 128 wide, the block's symbolic form
+    // L-dot_bb = L_bb Phi(L_bb^-1 D-dot_bb L_bb^-T) (three tiled products) for wider ones
+    CG_TRY(potf2_any(w, A + j * lda + j, lda, ws.dblk, nb, info, j, ws.tmp, ws.part2, s2));
+    if (w <= cg::DIAG_MAX) {
+      hipLaunchKernelGGL(cg::diag_fwd_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s2, w,
+                         (const double *)(A + j * lda + j), lda, (const double *)ws.dblk, nb, D + j * ldd + j, ldd);
+      CG_TRY(hipGetLastError());
+    } else {
+      double *tN = ws.tmp, *tP = ws.tmp + (int64_t)nb * nb;
+      const unsigned tiles = (unsigned)(cdiv(w, cg::SYM_TILE) * cdiv(w, cg::SYM_TILE));
+      hipLaunchKernelGGL(cg::sym_fwd_p_kernel, dim3(tiles), dim3(256), 0, s2, w, (const double *)(D + j * ldd + j),
+                         ldd, (const double *)ws.dblk, (int64_t)nb, tP, (int64_t)nb);
+      CG_TRY(hipGetLastError());
+      hipLaunchKernelGGL(cg::sym_fwd_n_kernel, dim3(tiles), dim3(256), 0, s2, w, (const double *)tP, (int64_t)nb,
+                         (const double *)ws.dblk, (int64_t)nb, tN, (int64_t)nb);
+      CG_TRY(hipGetLastError());
+      hipLaunchKernelGGL(cg::sym_fwd_l_kernel, dim3(tiles), dim3(256), 0, s2, w, (const double *)(A + j * lda + j),
+                         lda, (const double *)tN, (int64_t)nb, D + j * ldd + j, ldd);
+      CG_TRY(hipGetLastError());
+    }
     if (m > 0) {
       // C <- C tril(L_bb)^-T;  C-dot <- (C-dot - C L-dot_bb^T) L_bb^-T   -- the next block's rows first
       const int m1 = std::min(m, nb);
       if (b > 0) CG_TRY(hipStreamWaitEvent(s2, side->low, 0));
-      CG_TRY(gemm(false, true, m1, w, w, A + k * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
-                  A + k * lda + j, lda, nullptr, 0, 0, ws.part2, 32, s2));
+      CG_TRY(panel_solve_t(m1, w, A + k * lda + j, lda, ws.dblk, nb, ws.panel, ws.part2, 32, s2));
       CG_TRY(gemm(false, true, m1, w, w, A + k * lda + j, lda, D + j * ldd + j, ldd, -1.0,
                   D + k * ldd + j, ldd, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part2, 32, s2));
       CG_TRY(gemm(false, true, m1, w, w, ws.panel, nb, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
@@ -993,8 +1071,8 @@ int chol_factor_fwd(int precision, int64_t n, void *Av, int64_t lda, void *Dv, i
       CG_TRY(hipEventRecord(side->top, s2));
       if (m > m1) {
         const int64_t kl = k + m1;
-        CG_TRY(gemm(false, true, m - m1, w, w, A + kl * lda + j, lda, ws.dblk, nb, 1.0, nullptr, 0, 0.0,
-                    A + kl * lda + j, lda, nullptr, 0, 0, nullptr, 128, s2));
+        CG_TRY(panel_solve_t(m - m1, w, A + kl * lda + j, lda, ws.dblk, nb, ws.panel + (int64_t)m1 * nb, nullptr,
+                             128, s2));
         CG_TRY(gemm(false, true, m - m1, w, w, A + kl * lda + j, lda, D + j * ldd + j, ldd, -1.0,
                     D + kl * ldd + j, ldd, 1.0, ws.panel + (int64_t)m1 * nb, nb, nullptr, 0, 0, nullptr, 128, s2));
         CG_TRY(gemm(false, true, m - m1, w, w, ws.panel + (int64_t)m1 * nb, nb, ws.dblk, nb, 1.0, nullptr, 0,

@@ -46,7 +46,10 @@ def test_host_only_queries():
     assert lib.chol_status_string(0) == b"success"
     assert lib.chol_workspace_bytes(1, 0, 0, 0) == 0
     assert lib.chol_workspace_bytes(1, 0, 1000, 0) > 0
-    assert lib.chol_workspace_bytes(1, 0, 1000, 48) == 0     # nb not a multiple of 32
+    assert lib.chol_workspace_bytes(1, 0, 1000, 40) == 0     # nb not a multiple of 16
+    assert lib.chol_workspace_bytes(1, 0, 1000, 272) == 0    # nb above 256
+    assert lib.chol_workspace_bytes(1, 0, 1000, 48) > 0
+    assert lib.chol_workspace_bytes(1, 0, 1000, 256) > lib.chol_workspace_bytes(1, 0, 1000, 128)
     assert lib.chol_workspace_bytes(1, 9, 1000, 0) == 0      # unknown precision
 
 
@@ -71,6 +74,8 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 3, 0, ws, big, None) == -9      # diag variant
     assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, -1, 0, ws, big, None) == -9
     assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 2, 0, ws, 16, None) == -102
+    assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 256, 2, 0, ws, big, None) == -103  # Level-2, nb > 128
+    assert lib.chol_fwd_ex(0, 10, fake, 10, fake, 10, 160, 2, 0, ws, big, None) == -103
     assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 0, 2, ws, big, None) == -10     # layout
     assert lib.chol_rev_ex(0, 10, fake, 10, fake, 10, 0, 0, 0, 1, ws, 16, None) == -102
     assert lib.chol_rev_ex(0, 10, fake, 9, fake, 10, 0, 0, 0, 1, ws, big, None) == -4
@@ -129,7 +134,8 @@ def test_noalloc_entry_rejects_on_host():
     assert f(0, 10, fake, 9, fake, 10, 0, 0, None) == -4
     assert f(0, 10, fake, 10, fake, 3, 0, 0, None) == -6
     assert f(0, 10, fake, 10, fake, 10, 2, 0, None) == -7
-    assert f(0, 10, fake, 10, fake, 10, 0, 48, None) == -8
+    assert f(0, 10, fake, 10, fake, 10, 0, 40, None) == -8
+    assert f(0, 10, fake, 10, fake, 10, 0, 144, None) == -8      # valid for chol_rev, above 128 here
     assert f(0, 4097, fake, 4097, fake, 4097, 0, 0, None) == -104
     assert f(1, 10, fake, 10, fake, 10, 0, 0, None) == -103
     assert f(0, 0, None, 0, None, 0, 0, 0, None) == 0

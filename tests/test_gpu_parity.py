@@ -304,3 +304,65 @@ def test_col_major_rejects_row_major_tensors(cg, dev):
     A = to_dev(np.eye(8), dev)
     with pytest.raises(ValueError, match="column-major"):
         cg.chol_factor(A, layout="col")
+
+
+WIDE_NBS = [16, 48, 80, 144, 192, 256]
+WIDE_SIZES = [1, 17, 129, 255, 256, 257, 300, 513, 700]
+
+
+@pytest.mark.parametrize("nb", WIDE_NBS)
+@pytest.mark.parametrize("N", WIDE_SIZES)
+def test_block_widths(cg, dev, N, nb):
+    """Block widths beyond {32, 64, 128}: multiples of 16 below 128 (ragged inner blocks of the
+    diagonal routines) and 144..256, whose diagonal blocks are factored and inverted as two halves.
+    Factor, rev (both forms), fwd and the one-sweep factor + fwd against the oracle at 1e-10."""
+    S, L, Lb, Sd, junk = spd_case(N, 8000 + N + nb)
+    A, info = cg.chol_factor(to_dev(S + junk, dev), nb=nb)
+    assert int(info.item()) == 0
+    Lg = A.cpu().numpy()
+    assert rel(Lg, O.chol(S)[0]) <= TOL and np.all(np.triu(Lg, 1) == 0)
+    Lt = to_dev(L, dev)
+    for form in ("sym", "tril"):
+        X = cg.chol_rev(Lt, to_dev(Lb + junk, dev), form=form, nb=nb).cpu().numpy()
+        assert rel(X, O.chol_rev(L, Lb, form)) <= TOL, form
+    D = cg.chol_fwd(Lt, to_dev(np.tril(Sd) + junk, dev), nb=nb).cpu().numpy()
+    assert rel(D, O.chol_fwd(L, Sd)) <= TOL and np.all(np.triu(D, 1) == 0)
+    A2, D2, info = cg.chol_factor_fwd(to_dev(S + junk, dev), to_dev(np.tril(Sd) + junk, dev), nb=nb)
+    assert int(info.item()) == 0
+    assert rel(A2.cpu().numpy(), O.chol(S)[0]) <= TOL and rel(D2.cpu().numpy(), O.chol_fwd(L, Sd)) <= TOL
+
+
+@pytest.mark.parametrize("N,bad,nb", [(300, 100, 256), (300, 200, 256), (300, 299, 256), (600, 400, 192)])
+def test_wide_block_reports_first_bad_pivot(cg, dev, N, bad, nb):
+    """A non-positive pivot in either half of a wide diagonal block is reported 1-based, as LAPACK."""
+    S, *_ = spd_case(N, 5100 + bad)
+    S[bad, bad] = -1.0
+    _, info_o = O.chol(S)
+    A, info = cg.chol_factor(to_dev(S, dev), nb=nb)
+    assert info_o == bad + 1 and int(info.item()) == info_o
+
+
+def test_level2_wide_block_unsupported(cg, dev):
+    S, L, Lb, Sd, junk = spd_case(300, 8100)
+    with pytest.raises(cg.CholError, match="-103"):
+        cg.chol_rev(to_dev(L, dev), to_dev(Lb, dev), nb=256, diag="level2")
+    with pytest.raises(cg.CholError, match="-103"):
+        cg.chol_fwd(to_dev(L, dev), to_dev(np.tril(Sd), dev), nb=192, diag="level2")
+
+
+def test_medium_case_nb256(cg, dev, medium):
+    """The N = 4096 workload (kappa ~ 8e6) at nb = 256: factor at 1e-10 against the oracle's L,
+    rev and fwd on the oracle's L at 1e-10, and the one-sweep factor + fwd (its own L, end-to-end
+    gate max(1e-10, 100 kappa u))."""
+    A, info = cg.chol_factor(to_dev(medium["Sigma"], dev), nb=256)
+    assert int(info.item()) == 0
+    assert rel(A.cpu().numpy(), medium["L"]) <= TOL
+    Lt = to_dev(medium["L"], dev)
+    Sb = cg.chol_rev(Lt, to_dev(medium["Lbar"], dev), nb=256).cpu().numpy()
+    assert rel(Sb, medium["rev"]) <= TOL
+    Ld = cg.chol_fwd(Lt, to_dev(np.tril(medium["Sdot"]), dev), nb=256).cpu().numpy()
+    assert rel(Ld, medium["fwd"]) <= TOL
+    A2, D2, info = cg.chol_factor_fwd(to_dev(medium["Sigma"], dev), to_dev(np.tril(medium["Sdot"]), dev), nb=256)
+    assert int(info.item()) == 0
+    assert rel(A2.cpu().numpy(), medium["L"]) <= TOL
+    assert rel(D2.cpu().numpy(), medium["fwd"]) <= 1e-7
