@@ -1,0 +1,942 @@
+// Batched sweeps in step-synchronous form (FP64 storage, n <= 512).  Every problem of the batch
+// runs the same sequence of block steps of Sec. 4.2's algorithms with 64-wide blocks, and each step
+// is ONE grouped launch over all problems that have it:
+//   factor   (chol_blocked, left-looking as Sec. 4.2 writes it):  for s = 0, 1, ...:
+//              U   [D_s; C] -= [R; B] R^T over the columns left of block s   (64-row tiles)
+//              F1  D_s <- chol_unblocked(D_s) and D_s^-1          (one wave per problem)
+//              F2  C <- C D_s^-T                                   (64-row tiles)
+//   GP loss  z = L^-1 y, w = L^-T z, f, L-bar = diag(1/L_ii) - tril(w z^T)   (one workgroup each)
+//   reverse  (chol_blocked_rev in the left-looking order of the single-matrix sweep), problem p
+//            at step t takes its block b = nblk_p - 1 - t, so every problem starts with its last
+//            block:
+//              R0  X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k]        (64-row tiles, in place)
+//              R1  C-bar / 2 = X D^-1 / 2 with its mirrored store          (64-row tiles)
+//              R2  D-bar = tril(L-bar_D) - tril(C-bar^T C)                  (one workgroup per problem)
+//              R3  chol_unblocked_rev(D, D-bar) with the Phi halving        (one wave per problem)
+// so the block products of the large problems spread over the whole GPU, and the diagonal-block
+// routines (the single-wave Level-2 cores of cg_diag.hpp on 64-wide blocks) run four per compute
+// unit with every wave busy.  Problems are ordered largest first; a plan (order, per-step tile counts
+// and their prefix sums) is built on the device once per call, so the host needs only n_max.
+// Every output element is computed by the same operations in the same order whatever the batch,
+// so results are bitwise independent of the other problems.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cg_batched.hpp"
+#include "cg_diag.hpp"
+
+namespace cg {
+
+constexpr int B2_NB = 64;                              // block width
+constexpr int B2_MAXBLK = BATCH_NMAX / B2_NB;          // 8 blocks at n = 512
+constexpr int B2_PACKED = B2_NB * (B2_NB + 1) / 2;     // 2080 doubles: a packed 64-block
+constexpr int B2_BLK = B2_NB * B2_NB;                  // 4096 doubles: a square 64-block
+// Prefix arrays of the plan: F2 tiles per step s, U tiles per step s, reverse-step tiles per
+// step t, diagonal blocks per problem.
+constexpr int B2_Q_F2 = 0, B2_Q_UP = B2_MAXBLK, B2_Q_RV = 2 * B2_MAXBLK, B2_Q_BLK = 3 * B2_MAXBLK;
+constexpr int B2_NPREF = 3 * B2_MAXBLK + 1;
+
+struct B2Args {
+  int op;                   // BatchOp: FACTOR, REV, GP or FACTOR_REV
+  int batch;
+  int sbar_form;
+  int n_max;
+  const int64_t *n;
+  double *const *A;         // factor ops: Sigma -> L;  REV: L-bar -> Sigma-bar
+  const int64_t *lda;
+  const double *const *L;   // REV: the factors
+  const int64_t *ldl;
+  const double *const *y;   // GP: right-hand sides
+  double *const *G;         // GP: Sigma-bar out;  FACTOR_REV: L-bar -> Sigma-bar
+  const int64_t *ldg;
+  double *f;                // GP: losses
+  int *info;                // factor ops
+  // plan and scratch (workspace)
+  int *order;               // ordered position -> problem index
+  int *nv;                  // ordered position -> size (0 for a skipped problem)
+  int *pref;                // B2_NPREF arrays of batch + 1 ints
+  int *count;               // B2_MAXBLK: positions with more than s blocks
+  double *dinv;             // per position: ceil(n_max / 64) inverses of 64-blocks
+  double *vec;              // per position: z and w (2 n_max)
+  int64_t dinv_stride, vec_stride;  // doubles per position
+};
+
+__device__ __forceinline__ int b2_nblk(int n) { return (n + B2_NB - 1) / B2_NB; }
+__device__ __forceinline__ int b2_below(int n, int b) { return max(0, n - min(n, (b + 1) * B2_NB)); }
+__device__ __forceinline__ int b2_cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Tiles of prefix array q for a problem of size n.
+__device__ __forceinline__ int b2_tiles(int q, int n) {
+  const int nb = b2_nblk(n);
+  if (q < B2_Q_UP) {
+    const int s = q - B2_Q_F2;
+    return nb > s ? b2_cdiv(b2_below(n, s), B2_NB) : 0;
+  }
+  if (q < B2_Q_RV) {
+    const int s = q - B2_Q_UP;
+    return (s > 0 && nb > s) ? b2_cdiv(n - s * B2_NB, B2_NB) : 0;
+  }
+  if (q < B2_Q_BLK) {
+    const int t = q - B2_Q_RV;
+    return nb > t ? b2_cdiv(b2_below(n, nb - 1 - t), B2_NB) : 0;
+  }
+  return nb;
+}
+
+__device__ __forceinline__ bool b2_factor_op(int op) {
+  return op == BATCH_FACTOR || op == BATCH_GP || op == BATCH_FACTOR_REV;
+}
+
+// The factor of problem i (the factor ops overwrite A with it; REV reads L) and the array the
+// reverse sweep works in (REV: A; GP and FACTOR_REV: G).
+__device__ __forceinline__ const double *b2_L(const B2Args &a, int i, int64_t &ld) {
+  if (a.op == BATCH_REV) { ld = a.ldl[i]; return a.L[i]; }
+  ld = a.lda[i];
+  return a.A[i];
+}
+__device__ __forceinline__ double *b2_G(const B2Args &a, int i, int64_t &ld) {
+  if (a.op == BATCH_REV) { ld = a.lda[i]; return a.A[i]; }
+  ld = a.ldg[i];
+  return a.G[i];
+}
+
+// Plan, part 1 (one workgroup of 1024 threads): validate each problem (size in [0, n_max],
+// leading dimensions >= size; otherwise it is skipped: size 0 in the plan, info -1), order the
+// problems by decreasing size (counting sort), count the positions with more than s blocks, and
+// initialise info (0) and, for n == 0, the loss (0).
+__global__ __launch_bounds__(1024) void b2_order_kernel(B2Args a) {
+  __shared__ int cnt[BATCH_NMAX + 2];
+  __shared__ int blk[B2_MAXBLK];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < BATCH_NMAX + 2; i += blockDim.x) cnt[i] = 0;
+  if (tid < B2_MAXBLK) blk[tid] = 0;
+  __syncthreads();
+  auto key_of = [&](int i) -> int {
+    const int64_t v = a.n[i];
+    bool ok = v >= 0 && v <= a.n_max && a.lda[i] >= v;
+    if (a.op == BATCH_REV) ok = ok && a.ldl[i] >= v;
+    if (a.op == BATCH_GP || a.op == BATCH_FACTOR_REV) ok = ok && a.ldg[i] >= v;
+    return ok ? (int)v : -1;
+  };
+  for (int i = tid; i < a.batch; i += blockDim.x) {
+    const int key = max(0, key_of(i));
+    atomicAdd(&cnt[BATCH_NMAX - key], 1);  // bin 0 holds the largest size
+    const int nb = b2_nblk(key);
+    for (int s = 0; s < nb; ++s) atomicAdd(&blk[s], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < BATCH_NMAX + 1; ++i) {
+      const int c = cnt[i];
+      cnt[i] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < a.batch; i += blockDim.x) {
+    const int key = key_of(i);
+    const int pos = atomicAdd(&cnt[BATCH_NMAX - max(0, key)], 1);
+    a.order[pos] = i;
+    a.nv[pos] = max(0, key);
+    if (b2_factor_op(a.op)) a.info[i] = key < 0 ? -1 : 0;
+    if (a.op == BATCH_GP && key == 0) a.f[i] = 0.0;
+  }
+  if (tid < B2_MAXBLK) a.count[tid] = blk[tid];
+}
+
+// Plan, part 2 (B2_NPREF workgroups of 1024 threads, one per prefix array): exclusive prefix sum
+// over the ordered positions of the tiles each problem has in that launch; entry batch holds the
+// total.
+__global__ __launch_bounds__(1024) void b2_prefix_kernel(B2Args a) {
+  __shared__ int sc[1024];
+  __shared__ int carry;
+  const int q = blockIdx.x, tid = threadIdx.x;
+  int *pr = a.pref + (int64_t)q * (a.batch + 1);
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < a.batch; base += 1024) {
+    const int p = base + tid;
+    const int v = p < a.batch ? b2_tiles(q, a.nv[p]) : 0;
+    sc[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan
+      const int add = tid >= o ? sc[tid - o] : 0;
+      __syncthreads();
+      sc[tid] += add;
+      __syncthreads();
+    }
+    if (p < a.batch) pr[p] = carry + sc[tid] - v;
+    __syncthreads();
+    if (tid == 1023) carry += sc[1023];
+    __syncthreads();
+  }
+  if (tid == 0) pr[a.batch] = carry;
+}
+
+// Position p of item `it` in prefix array pr (last p with pr[p] <= it; items of empty problems
+// never match).
+__device__ __forceinline__ int b2_find(const int *pr, int batch, int it) {
+  int lo = 0, hi = batch;  // pr[lo] <= it < pr[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pr[mid] <= it) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------------------------
+// 64 x 64 MFMA tile product by one 256-thread workgroup: four waves in a 2 x 2 arrangement, each
+// owning a 32 x 32 quadrant as 2 x 2 v_mfma_f64_16x16x4_f64 accumulators; K staged through LDS 16
+// deep, double-buffered from registers (one barrier per K-step), so ragged operands just return 0
+// from their accessors.  acc[a][b][e] holds (row 32 wm + 16 a + 4 e + lane/16, column
+// 32 wn + 16 b + lane % 16).  AK / BK: the operand is contiguous along k in memory (the load
+// mapping follows it so that loads coalesce).
+constexpr int T64_LD = B2_NB + 4;
+constexpr int T64_LDS = 4 * 16 * T64_LD;  // doubles: two stages of A and B
+
+__device__ __forceinline__ int t64_row(int a, int e) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  return 32 * (wave >> 1) + 16 * a + 4 * e + (lane >> 4);
+}
+__device__ __forceinline__ int t64_col(int b) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  return 32 * (wave & 1) + 16 * b + (lane & 15);
+}
+
+template <bool AK, bool BK, class FA, class FB>
+__device__ __forceinline__ void t64_mma(dbl4 (&acc)[2][2], FA A, FB B, int K, double *lds) {
+  double *const lb = (double *)(__attribute__((address_space(3))) double *)lds;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  auto As = [&](int st) { return lb + st * 16 * T64_LD; };
+  auto Bs = [&](int st) { return lb + (2 + st) * 16 * T64_LD; };
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0, 0, 0, 0};
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = u * 256 + tid;
+      const int i = AK ? (e >> 4) : (e & 63), k = AK ? (e & 15) : (e >> 6);
+      ra[u] = (k0 + k < K) ? A(i, k0 + k) : 0.0;
+      const int j = BK ? (e >> 4) : (e & 63), kb = BK ? (e & 15) : (e >> 6);
+      rb[u] = (k0 + kb < K) ? B(k0 + kb, j) : 0.0;
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = u * 256 + tid;
+      const int i = AK ? (e >> 4) : (e & 63), k = AK ? (e & 15) : (e >> 6);
+      As(st)[k * T64_LD + i] = ra[u];
+      const int j = BK ? (e >> 4) : (e & 63), kb = BK ? (e & 15) : (e >> 6);
+      Bs(st)[kb * T64_LD + j] = rb[u];
+    }
+  };
+  const int nkt = (K + 15) / 16;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  const int fk = lane >> 4, fi = lane & 15;
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int st = kt & 1;
+    if (kt + 1 < nkt) load((kt + 1) * 16);
+    const double *as = As(st), *bs = Bs(st);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) af[t] = as[(kk + fk) * T64_LD + 32 * wm + 16 * t + fi];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) bf[t] = bs[(kk + fk) * T64_LD + 32 * wn + 16 * t + fi];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+    }
+    if (kt + 1 < nkt) store(st ^ 1);
+    __syncthreads();
+  }
+}
+
+// Elementwise epilogue over the tile: out(r, c, v) for every accumulator element.
+template <class F>
+__device__ __forceinline__ void t64_each(const dbl4 (&acc)[2][2], F out) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out(t64_row(x, e), t64_col(y), acc[x][y][e]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Diagonal blocks (w <= 64) one WAVE each: the Level-2 cores of cg_diag.hpp are single-wave
+// already, so a wave can run a whole 64-block -- its two 32-column inner blocks, the products
+// between them as 16 x 16 MFMA tiles, the inverse -- with only wave-level ordering of its LDS
+// accesses, and the four waves of a workgroup take four different problems.  Each wave holds two
+// packed 64-blocks (33 KB), so a compute unit runs four blocks at once with every wave busy.
+constexpr int B2W_WAVES = 4;
+constexpr int B2W_LDS = 2 * B2_PACKED;  // doubles per wave
+
+// Orders this wave's LDS writes before its later LDS reads (a wave's LDS accesses are processed in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Packed lower triangle of a w x w block (w <= 64, row-major source) into Dp, by one wave, sixteen
+// rows of loads in flight.
+__device__ __forceinline__ void wave_load_lower(double *Dp, const double *src, int64_t ld, int w) {
+  const int lane = threadIdx.x & 63;
+  for (int r0 = 0; r0 < w; r0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = r0 + u;
+      v[u] = (r < w && lane <= r) ? src[(int64_t)r * ld + lane] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = r0 + u;
+      if (r < w && lane <= r) Dp[pidx(r, lane)] = v[u];
+    }
+  }
+}
+
+// D <- chol_unblocked(D) and Xp = D^-1 for the w x w block (w <= 64) packed in Dp, by one wave:
+// inner block 0 (Level-2 core), the rows below it solved lane by lane, the update of inner block 1
+// (three 16 x 16 MFMA tiles), inner block 1, then X00, X11 and X10 = -X11 (D10 X00).  Returns the
+// first column with a non-positive or NaN pivot, or -1.
+__device__ int wave_potf2_64(double *Dp, double *Xp, int w) {
+  const int lane = threadIdx.x & 63;
+  const int ib0 = min(INNER, w), ib1 = w - ib0;
+  int bad = level2_potf2_wave(Dp, 0, ib0);
+  wave_sync();
+  if (ib1 > 0) {
+    if (lane < ib1) panel_solve_row(Dp, 0, INNER, INNER + lane);
+    wave_sync();
+    // D11 <- D11 - D10 D10^T, lower 16 x 16 tiles, K = 32
+    dbl4 acc[3];
+    const int nt = (ib1 + 15) / 16;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int ti = (u == 0) ? 0 : 1, tj = (u == 2) ? 1 : 0;
+      acc[u] = dbl4{0, 0, 0, 0};
+      if (ti < nt) {
+        auto A = [&](int i, int k) { const int r = 16 * ti + i; return r < ib1 ? Dp[pidx(INNER + r, k)] : 0.0; };
+        auto B = [&](int k, int j) { const int c = 16 * tj + j; return c < ib1 ? Dp[pidx(INNER + c, k)] : 0.0; };
+        acc[u] = tile_mma(acc[u], A, B, INNER);
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int ti = (u == 0) ? 0 : 1, tj = (u == 2) ? 1 : 0;
+      if (ti >= nt) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 16 * ti + tile_row(e), c = 16 * tj + tile_col();
+        if (r < ib1 && c <= r) Dp[pidx(INNER + r, INNER + c)] -= acc[u][e];
+      }
+    }
+    wave_sync();
+    const int f = level2_potf2_wave(Dp, INNER, ib1);
+    if (bad < 0 && f >= 0) bad = INNER + f;
+    wave_sync();
+  }
+  wave_trinv32(Dp, Xp, 0, ib0);
+  if (ib1 > 0) {
+    wave_trinv32(Dp, Xp, INNER, ib1);
+    wave_sync();
+    // Y = D10 X00 (ib1 x 32), then X10 = -X11 Y, each as up to 2 x 2 tiles held in registers
+    const int nt = (ib1 + 15) / 16;
+    dbl4 y[2][2], x[2][2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        y[ti][tj] = dbl4{0, 0, 0, 0};
+        if (ti >= nt) continue;
+        auto A = [&](int i, int k) { const int r = 16 * ti + i; return r < ib1 ? Dp[pidx(INNER + r, k)] : 0.0; };
+        auto B = [&](int k, int j) { const int c = 16 * tj + j; return k >= c ? Xp[pidx(k, c)] : 0.0; };
+        y[ti][tj] = tile_mma(y[ti][tj], A, B, INNER);
+      }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        if (ti >= nt) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 16 * ti + tile_row(e), c = 16 * tj + tile_col();
+          if (r < ib1) Xp[pidx(INNER + r, c)] = y[ti][tj][e];
+        }
+      }
+    wave_sync();
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        x[ti][tj] = dbl4{0, 0, 0, 0};
+        if (ti >= nt) continue;
+        auto A = [&](int i, int k) {
+          const int r = 16 * ti + i;
+          return (r < ib1 && k <= r) ? Xp[pidx(INNER + r, INNER + k)] : 0.0;
+        };
+        auto B = [&](int k, int j) { return k < ib1 ? Xp[pidx(INNER + k, 16 * tj + j)] : 0.0; };
+        x[ti][tj] = tile_mma(x[ti][tj], A, B, min(ib1, 16 * ti + 16));
+      }
+    wave_sync();
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        if (ti >= nt) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 16 * ti + tile_row(e), c = 16 * tj + tile_col();
+          if (r < ib1) Xp[pidx(INNER + r, c)] = -x[ti][tj][e];
+        }
+      }
+  }
+  wave_sync();
+  return bad;
+}
+
+// D-bar <- chol_unblocked_rev(D, D-bar) for a w x w block (w <= 64), D packed in Dp, D-bar in Bp,
+// by one wave: the blocked reverse sweep over its two inner blocks from the bottom-right, as
+// diag_rev_core, with D_0^-1 read from Dinv (ld 64).
+__device__ void wave_diag_rev_64(double *Dp, double *Bp, const double *Dinv, int w) {
+  const int ib0 = min(INNER, w), ib1 = w - ib0;
+  if (ib1 > 0) {
+    level2_rev_wave(Dp, Bp, INNER, ib1);
+    wave_sync();
+    // R-bar -= (D-bar_1 + D-bar_1^T) R   (rows [32, w) x cols [0, 32), K = ib1)
+    const int nt = (ib1 + 15) / 16;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        acc[ti][tj] = dbl4{0, 0, 0, 0};
+        if (ti >= nt) continue;
+        auto A = [&](int i, int k) {
+          const int m = 16 * ti + i;
+          if (m >= ib1 || k >= ib1) return 0.0;
+          return (k < m) ? Bp[pidx(INNER + m, INNER + k)]
+                         : (k > m) ? Bp[pidx(INNER + k, INNER + m)] : 2.0 * Bp[pidx(INNER + m, INNER + m)];
+        };
+        auto B = [&](int k, int j) { return k < ib1 ? Dp[pidx(INNER + k, 16 * tj + j)] : 0.0; };
+        acc[ti][tj] = tile_mma(acc[ti][tj], A, B, ib1);
+      }
+    wave_sync();
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        if (ti >= nt) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int m = 16 * ti + tile_row(e);
+          if (m < ib1) Bp[pidx(INNER + m, 16 * tj + tile_col())] -= acc[ti][tj][e];
+        }
+      }
+    wave_sync();
+    // C-bar <- C-bar D_0^-1   (rows [32, w) x cols [0, 32), K = 32)
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        acc[ti][tj] = dbl4{0, 0, 0, 0};
+        if (ti >= nt) continue;
+        auto A = [&](int i, int k) { const int r = 16 * ti + i; return r < ib1 ? Bp[pidx(INNER + r, k)] : 0.0; };
+        auto B = [&](int k, int j) { return Dinv[k * B2_NB + 16 * tj + j]; };
+        acc[ti][tj] = tile_mma(acc[ti][tj], A, B, INNER);
+      }
+    wave_sync();
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        if (ti >= nt) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 16 * ti + tile_row(e);
+          if (r < ib1) Bp[pidx(INNER + r, 16 * tj + tile_col())] = acc[ti][tj][e];
+        }
+      }
+    wave_sync();
+    // D-bar_0 -= tril(C-bar^T C)   (three lower 16 x 16 tiles, K = ib1)
+    dbl4 d[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int r0 = (u == 0) ? 0 : 16, c0 = (u == 2) ? 16 : 0;
+      auto A = [&](int i, int k) { return k < ib1 ? Bp[pidx(INNER + k, r0 + i)] : 0.0; };
+      auto B = [&](int k, int j) { return k < ib1 ? Dp[pidx(INNER + k, c0 + j)] : 0.0; };
+      d[u] = tile_mma(dbl4{0, 0, 0, 0}, A, B, ib1);
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int r0 = (u == 0) ? 0 : 16, c0 = (u == 2) ? 16 : 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + tile_row(e), cc = c0 + tile_col();
+        if (cc <= r) Bp[pidx(r, cc)] -= d[u][e];
+      }
+    }
+    wave_sync();
+  }
+  level2_rev_wave(Dp, Bp, 0, ib0);
+  wave_sync();
+}
+
+// F1: POTF2 of block s of every problem with more than s blocks, and its inverse, one wave per
+// problem.
+__global__ __launch_bounds__(256) void b2_potf2_kernel(B2Args a, int s) {
+  __shared__ double lds[B2W_WAVES * B2W_LDS];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *Dp = as_lds(lds + wave * B2W_LDS), *Xp = Dp + B2_PACKED;
+  const int cnt = a.count[s];
+  for (int p = blockIdx.x * B2W_WAVES + wave; p < cnt; p += gridDim.x * B2W_WAVES) {
+    const int i = a.order[p], n = a.nv[p];
+    const int j = s * B2_NB, w = min(B2_NB, n - j);
+    double *Ad = a.A[i] + (int64_t)j * a.lda[i] + j;
+    const int64_t lda = a.lda[i];
+    wave_load_lower(Dp, Ad, lda, w);
+    wave_sync();
+    const int bad = wave_potf2_64(Dp, Xp, w);
+    if (lane == 0 && bad >= 0 && a.info[i] == 0) a.info[i] = j + bad + 1;
+    for (int r = 0; r < w; ++r)
+      if (lane < w) Ad[(int64_t)r * lda + lane] = lane <= r ? Dp[pidx(r, lane)] : 0.0;
+    double *X = a.dinv + p * a.dinv_stride + s * B2_BLK;
+    for (int r = 0; r < B2_NB; ++r) X[r * B2_NB + lane] = (r < w && lane <= r) ? Xp[pidx(r, lane)] : 0.0;
+    wave_sync();
+  }
+}
+
+// Inverses of every diagonal block of L (REV, which is given L), one wave per block.
+__global__ __launch_bounds__(256) void b2_trinv_kernel(B2Args a) {
+  __shared__ double lds[B2W_WAVES * B2W_LDS];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *Dp = as_lds(lds + wave * B2W_LDS), *Xp = Dp + B2_PACKED;
+  const int *pr = a.pref + (int64_t)B2_Q_BLK * (a.batch + 1);
+  const int total = pr[a.batch];
+  for (int it = blockIdx.x * B2W_WAVES + wave; it < total; it += gridDim.x * B2W_WAVES) {
+    const int p = b2_find(pr, a.batch, it), b = it - pr[p];
+    const int i = a.order[p], n = a.nv[p];
+    const int j = b * B2_NB, w = min(B2_NB, n - j);
+    int64_t ldl;
+    const double *Li = b2_L(a, i, ldl);
+    wave_load_lower(Dp, Li + (int64_t)j * ldl + j, ldl, w);
+    wave_sync();
+    const int ib0 = min(INNER, w), ib1 = w - ib0;
+    wave_trinv32(Dp, Xp, 0, ib0);
+    if (ib1 > 0) {
+      wave_trinv32(Dp, Xp, INNER, ib1);
+      wave_sync();
+      const int nt = (ib1 + 15) / 16;
+      dbl4 y[2][2];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          y[ti][tj] = dbl4{0, 0, 0, 0};
+          if (ti >= nt) continue;
+          auto A = [&](int ii, int k) { const int r = 16 * ti + ii; return r < ib1 ? Dp[pidx(INNER + r, k)] : 0.0; };
+          auto B = [&](int k, int jj) { const int c = 16 * tj + jj; return k >= c ? Xp[pidx(k, c)] : 0.0; };
+          y[ti][tj] = tile_mma(y[ti][tj], A, B, INNER);
+        }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          if (ti >= nt) continue;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = 16 * ti + tile_row(e), c = 16 * tj + tile_col();
+            if (r < ib1) Xp[pidx(INNER + r, c)] = y[ti][tj][e];
+          }
+        }
+      wave_sync();
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          y[ti][tj] = dbl4{0, 0, 0, 0};
+          if (ti >= nt) continue;
+          auto A = [&](int ii, int k) {
+            const int r = 16 * ti + ii;
+            return (r < ib1 && k <= r) ? Xp[pidx(INNER + r, INNER + k)] : 0.0;
+          };
+          auto B = [&](int k, int jj) { return k < ib1 ? Xp[pidx(INNER + k, 16 * tj + jj)] : 0.0; };
+          y[ti][tj] = tile_mma(y[ti][tj], A, B, min(ib1, 16 * ti + 16));
+        }
+      wave_sync();
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          if (ti >= nt) continue;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = 16 * ti + tile_row(e), c = 16 * tj + tile_col();
+            if (r < ib1) Xp[pidx(INNER + r, c)] = -y[ti][tj][e];
+          }
+        }
+    }
+    wave_sync();
+    double *X = a.dinv + p * a.dinv_stride + b * B2_BLK;
+    for (int r = 0; r < B2_NB; ++r) X[r * B2_NB + lane] = (r < w && lane <= r) ? Xp[pidx(r, lane)] : 0.0;
+    wave_sync();
+  }
+}
+
+
+// F2: rows below block s, C <- C D_s^-T, one 64-row tile per item (the tile spans all of the
+// block's columns, so it is read before it is written); the mirrored positions above the
+// diagonal are set to 0 (the factor's strict upper triangle).
+__global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
+  __shared__ double lds[T64_LDS];
+  const int *pr = a.pref + (int64_t)(B2_Q_F2 + s) * (a.batch + 1);
+  const int total = pr[a.batch];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = b2_find(pr, a.batch, it), ti = it - pr[p];
+    const int i = a.order[p], n = a.nv[p];
+    const int j = s * B2_NB, w = min(B2_NB, n - j), k = j + w;
+    const int r0 = k + ti * B2_NB, R = min(B2_NB, n - r0);
+    double *Ai = a.A[i];
+    const int64_t lda = a.lda[i];
+    const double *Di = a.dinv + p * a.dinv_stride + s * B2_BLK;
+    dbl4 acc[2][2];
+    t64_mma<true, true>(
+        acc, [&](int r, int kk) { return (r < R && kk < w) ? Ai[(int64_t)(r0 + r) * lda + j + kk] : 0.0; },
+        [&](int kk, int c) { return (c < w && kk <= c) ? Di[c * B2_NB + kk] : 0.0; }, w, lds);
+    t64_each(acc, [&](int r, int c, double v) {
+      if (r < R && c < w) {
+        Ai[(int64_t)(r0 + r) * lda + j + c] = v;
+        Ai[(int64_t)(j + c) * lda + r0 + r] = 0.0;
+      }
+    });
+    __syncthreads();
+  }
+}
+
+// U: left-looking update of block column s, [D_s; C] -= [R; B] R^T over columns [0, 64 s), one
+// 64-row tile of rows [64 s, n) per item (in place: it reads only columns left of the block).  The
+// diagonal block's strict upper part is not needed (POTF2 reads the lower triangle).
+__global__ __launch_bounds__(256) void b2_up_kernel(B2Args a, int s) {
+  __shared__ double lds[T64_LDS];
+  const int *pr = a.pref + (int64_t)(B2_Q_UP + s) * (a.batch + 1);
+  const int total = pr[a.batch];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = b2_find(pr, a.batch, it), ti = it - pr[p];
+    const int i = a.order[p], n = a.nv[p];
+    const int j = s * B2_NB, w = min(B2_NB, n - j);
+    const int r0 = j + ti * B2_NB, R = min(B2_NB, n - r0);
+    double *Ai = a.A[i];
+    const int64_t lda = a.lda[i];
+    dbl4 acc[2][2];
+    t64_mma<true, true>(
+        acc, [&](int r, int kk) { return (r < R) ? Ai[(int64_t)(r0 + r) * lda + kk] : 0.0; },
+        [&](int kk, int c) { return (c < w) ? Ai[(int64_t)(j + c) * lda + kk] : 0.0; }, j, lds);
+    t64_each(acc, [&](int r, int c, double v) {
+      if (r < R && c < w && (ti > 0 || c <= r)) {
+        double *d = Ai + (int64_t)(r0 + r) * lda + j + c;
+        *d = *d - v;
+      }
+    });
+    __syncthreads();
+  }
+}
+
+// GP loss per problem (after the factor): z = L^-1 y and w = L^-T z by block substitution with
+// the block inverses, f = sum_i log L_ii + |z|^2 / 2, L-bar = diag(1 / L_ii) - tril(w z^T) into G
+// (strict upper triangle 0).  A problem whose factorisation failed gets f = NaN, G untouched.
+__global__ __launch_bounds__(256) void b2_loss_kernel(B2Args a) {
+  __shared__ double t[B2_NB];
+  __shared__ double zl[BATCH_NMAX];
+  __shared__ double wl[BATCH_NMAX];
+  __shared__ double pt[4 * B2_NB];
+  __shared__ double red[256];
+  __shared__ double dg[BATCH_NMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = 4;
+  const int cnt = a.count[0];
+  for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
+    const int i = a.order[p], n = a.nv[p];
+    if (a.info[i] != 0) {
+      if (threadIdx.x == 0) a.f[i] = __builtin_nan("");
+      continue;  // workgroup-uniform
+    }
+    const double *L = a.A[i];
+    const int64_t ldl = a.lda[i];
+    const double *y = a.y[i];
+    double *G = a.G[i];
+    const int64_t ldg = a.ldg[i];
+    const double *dinv = a.dinv + p * a.dinv_stride;
+    double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
+    const int nblk = b2_nblk(n);
+    // forward: z_b = D_b^-1 (y_b - L[b, :j] z[:j]).  Wave h takes rows h, h + 4, ... of the block
+    // with its lanes along the columns (coalesced, sixteen loads in flight per lane), and reduces
+    // each row with a fixed xor tree.
+    for (int b = 0; b < nblk; ++b) {
+      const int j = b * B2_NB, w = min(B2_NB, n - j);
+      double acc[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+      for (int q0 = 0; q0 < j; q0 += B2_NB) {
+        const double zv = zl[q0 + lane];
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int r = wave + 4 * u;
+          v[u] = r < w ? L[(int64_t)(j + r) * ldl + q0 + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc[u] = fma(v[u], zv, acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int r = wave + 4 * u;
+        const double tot = wave_sum(acc[u]);
+        if (lane == 0 && r < w) t[r] = y[j + r] - tot;
+      }
+      __syncthreads();
+      const double *Di = dinv + b * B2_BLK;
+      const double tv = lane < w ? t[lane] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int r = wave + 4 * u;
+        acc[u] = (r < w && lane <= r) ? Di[r * B2_NB + lane] * tv : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int r = wave + 4 * u;
+        const double tot = wave_sum(acc[u]);
+        if (lane == 0 && r < w) {
+          zg[j + r] = tot;
+          zl[j + r] = tot;
+        }
+      }
+      __syncthreads();
+    }
+    // backward: w_b = D_b^-T (z_b - L[k:, b]^T w[k:]); thread (h, r) = (wave, lane) walks rows
+    // k + h, k + h + 4, ... of column j + r (loads coalesced over r, sixteen in flight), the four
+    // partial sums added in a fixed order
+    for (int b = nblk - 1; b >= 0; --b) {
+      const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j;
+      double sv = 0.0;
+      if (lane < w) {
+        int ii = k + wave;
+        for (; ii + 60 < n; ii += 64) {
+          double lv[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) lv[u] = L[(int64_t)(ii + 4 * u) * ldl + j + lane];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) sv = fma(lv[u], wl[ii + 4 * u], sv);
+        }
+        for (; ii < n; ii += 4) sv = fma(L[(int64_t)ii * ldl + j + lane], wl[ii], sv);
+      }
+      pt[wave * B2_NB + lane] = sv;
+      __syncthreads();
+      if (wave == 0 && lane < w)
+        t[lane] = zl[j + lane] - (((pt[lane] + pt[B2_NB + lane]) + pt[2 * B2_NB + lane]) + pt[3 * B2_NB + lane]);
+      __syncthreads();
+      const double *Di = dinv + b * B2_BLK;
+      double dv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = lane + wave + 4 * u;
+        dv[u] = (lane < w && q < w) ? Di[q * B2_NB + lane] : 0.0;
+      }
+      sv = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = lane + wave + 4 * u;
+        if (lane < w && q < w) sv = fma(dv[u], t[q], sv);
+      }
+      pt[wave * B2_NB + lane] = sv;
+      __syncthreads();
+      if (wave == 0 && lane < w) {
+        const double v = ((pt[lane] + pt[B2_NB + lane]) + pt[2 * B2_NB + lane]) + pt[3 * B2_NB + lane];
+        wg[j + lane] = v;
+        wl[j + lane] = v;
+      }
+      __syncthreads();
+    }
+    // f: per-thread partial sums over a fixed stride, then a fixed-order tree; 1 / L_ii kept in
+    // LDS (t is free again) for L-bar
+    double part = 0.0;
+    for (int ii = threadIdx.x; ii < n; ii += blockDim.x) {
+      const double d = L[(int64_t)ii * ldl + ii];
+      part += log(d) + 0.5 * zl[ii] * zl[ii];
+      dg[ii] = 1.0 / d;
+    }
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int hh = blockDim.x / 2; hh > 0; hh >>= 1) {
+      if ((int)threadIdx.x < hh) red[threadIdx.x] += red[threadIdx.x + hh];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.f[i] = red[0];
+    // L-bar = diag(1 / L_ii) - tril(w z^T), one wave per row (LDS operands only)
+    for (int rr = wave; rr < n; rr += NW) {
+      const double wr = wl[rr], dr = dg[rr];
+      for (int c = lane; c < n; c += 64)
+        G[(int64_t)rr * ldg + c] = c < rr ? -wr * zl[c] : (c == rr ? dr - wr * zl[c] : 0.0);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool b2_rev_skip(const B2Args &a, int i) {
+  return (a.op == BATCH_GP || a.op == BATCH_FACTOR_REV) && a.info[i] != 0;
+}
+
+// R0: X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k] for the rows below block b = nblk - 1 - t, in place
+// in the block column of G (one 64-row tile per item; it reads only columns >= k of G).
+__global__ __launch_bounds__(256) void b2_r0_kernel(B2Args a, int t) {
+  __shared__ double lds[T64_LDS];
+  const int *pr = a.pref + (int64_t)(B2_Q_RV + t) * (a.batch + 1);
+  const int total = pr[a.batch];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = b2_find(pr, a.batch, it), ti = it - pr[p];
+    const int i = a.order[p], n = a.nv[p];
+    if (b2_rev_skip(a, i)) continue;
+    const int b = b2_nblk(n) - 1 - t;
+    const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j, m = n - k;
+    const int r0 = k + ti * B2_NB, R = min(B2_NB, n - r0);
+    int64_t ldl, ldg;
+    const double *Li = b2_L(a, i, ldl);
+    double *Gi = b2_G(a, i, ldg);
+    dbl4 acc[2][2];
+    t64_mma<true, false>(
+        acc, [&](int r, int kk) { return (r < R && kk < m) ? Gi[(int64_t)(r0 + r) * ldg + k + kk] : 0.0; },
+        [&](int kk, int c) { return (c < w && kk < m) ? Li[(int64_t)(k + kk) * ldl + j + c] : 0.0; }, m, lds);
+    t64_each(acc, [&](int r, int c, double v) {
+      if (r < R && c < w) {
+        double *d = Gi + (int64_t)(r0 + r) * ldg + j + c;
+        *d = *d - 2.0 * v;
+      }
+    });
+    __syncthreads();
+  }
+}
+
+// R1: C-bar / 2 = X D_b^-1 / 2 for one 64-row tile (in place: the tile spans all of the block's
+// columns, so it is read before it is written), mirrored to the upper triangle.
+__global__ __launch_bounds__(256) void b2_r1_kernel(B2Args a, int t) {
+  __shared__ double lds[T64_LDS];
+  const int *pr = a.pref + (int64_t)(B2_Q_RV + t) * (a.batch + 1);
+  const int total = pr[a.batch];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = b2_find(pr, a.batch, it), ti = it - pr[p];
+    const int i = a.order[p], n = a.nv[p];
+    if (b2_rev_skip(a, i)) continue;
+    const int b = b2_nblk(n) - 1 - t;
+    const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j;
+    const int r0 = k + ti * B2_NB, R = min(B2_NB, n - r0);
+    int64_t ldg;
+    double *Gi = b2_G(a, i, ldg);
+    const double *Di = a.dinv + p * a.dinv_stride + b * B2_BLK;
+    dbl4 acc[2][2];
+    t64_mma<true, false>(
+        acc, [&](int r, int kk) { return (r < R && kk < w) ? Gi[(int64_t)(r0 + r) * ldg + j + kk] : 0.0; },
+        [&](int kk, int c) { return (c < w && kk < w && kk >= c) ? Di[kk * B2_NB + c] : 0.0; }, w, lds);
+    t64_each(acc, [&](int r, int c, double v) {
+      if (r < R && c < w) {
+        const double h = 0.5 * v;
+        Gi[(int64_t)(r0 + r) * ldg + j + c] = h;
+        Gi[(int64_t)(j + c) * ldg + r0 + r] = h;
+      }
+    });
+    __syncthreads();
+  }
+}
+
+// R2: D-bar = tril(L-bar_D) - tril(C-bar^T C) for block b = nblk - 1 - t, C-bar = 2 G[k:, j:k]
+// (after R1) and C = L[k:, j:k], K = m; one workgroup per problem, written in place into the
+// lower triangle of G's diagonal block.
+__global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
+  __shared__ double lds[T64_LDS];
+  const int cnt = a.count[t];
+  for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
+    const int i = a.order[p], n = a.nv[p];
+    if (b2_rev_skip(a, i)) continue;
+    const int b = b2_nblk(n) - 1 - t;
+    const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j, m = n - k;
+    int64_t ldl, ldg;
+    const double *Li = b2_L(a, i, ldl);
+    double *Gi = b2_G(a, i, ldg);
+    dbl4 acc[2][2];
+    t64_mma<false, false>(
+        acc, [&](int x, int kk) { return (x < w) ? Gi[(int64_t)(k + kk) * ldg + j + x] : 0.0; },
+        [&](int kk, int y) { return (y < w) ? Li[(int64_t)(k + kk) * ldl + j + y] : 0.0; }, m, lds);
+    t64_each(acc, [&](int x, int y, double v) {
+      if (x < w && y <= x) {
+        double *d = Gi + (int64_t)(j + x) * ldg + j + y;
+        *d = *d - 2.0 * v;
+      }
+    });
+    __syncthreads();
+  }
+}
+
+// R3: chol_unblocked_rev (Sec. 4.1, Phi halving) on the diagonal block b = nblk - 1 - t of every
+// problem that has it, one wave per problem, from D = L's block and D-bar in the lower triangle of
+// G's block; the symmetric gradient's block goes to both triangles of G.
+__global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
+  __shared__ double lds[B2W_WAVES * B2W_LDS];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double *Dp = as_lds(lds + wave * B2W_LDS), *Bp = Dp + B2_PACKED;
+  const int cnt = a.count[t];
+  for (int p = blockIdx.x * B2W_WAVES + wave; p < cnt; p += gridDim.x * B2W_WAVES) {
+    const int i = a.order[p], n = a.nv[p];
+    if (b2_rev_skip(a, i)) continue;
+    const int b = b2_nblk(n) - 1 - t;
+    const int j = b * B2_NB, w = min(B2_NB, n - j);
+    int64_t ldl, ldg;
+    const double *Ld = b2_L(a, i, ldl) + (int64_t)j * ldl + j;
+    double *Gd = b2_G(a, i, ldg) + (int64_t)j * ldg + j;
+    wave_load_lower(Dp, Ld, ldl, w);
+    wave_load_lower(Bp, Gd, ldg, w);
+    wave_sync();
+    wave_diag_rev_64(Dp, Bp, a.dinv + p * a.dinv_stride + b * B2_BLK, w);
+    for (int r = 0; r < w; ++r)
+      if (lane < w)
+        Gd[(int64_t)r * ldg + lane] = lane < r ? 0.5 * Bp[pidx(r, lane)]
+                                               : (lane == r ? Bp[pidx(r, r)] : 0.5 * Bp[pidx(lane, r)]);
+    wave_sync();
+  }
+}
+
+// Paper's lower-triangular form T = Phi(S + S^T) from the symmetric gradient (strict lower doubled,
+// strict upper 0), per problem.
+__global__ __launch_bounds__(256) void b2_form_kernel(B2Args a) {
+  const int cnt = a.count[0];
+  for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
+    const int i = a.order[p], n = a.nv[p];
+    if (b2_rev_skip(a, i)) continue;
+    int64_t ldg;
+    double *Gi = b2_G(a, i, ldg);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int r = e / n, c = e - r * n;
+      double *d = Gi + (int64_t)r * ldg + c;
+      if (c > r) *d = 0.0;
+      else if (c < r) *d = 2.0 * *d;
+    }
+  }
+}
+
+}  // namespace cg

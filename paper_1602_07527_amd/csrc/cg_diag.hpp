@@ -482,12 +482,10 @@ __device__ __forceinline__ void stage_inverse32(double *Xi, const double *Dinv, 
 // Dinv: this block's inverse (ld nb).
 // Out: the block of the symmetric gradient, written to both triangles of A + (j, j):
 //   A[r][c] = A[c][r] = T[r][c] / 2 (r > c),  A[r][r] = T[r][r],   T = final D-bar.
-__device__ __forceinline__ void diag_rev_block(int w, const double *Ld, int64_t ldl, const double *Dbar, int64_t ldd,
-                               const double *Dinv, int nb, double *Aout, int64_t lda, double *Dp,
-                               double *Bp, double *Xi) {
+// The sweep itself, on D (packed in Dp) and D-bar (packed in Bp) already in LDS.
+__device__ __forceinline__ void diag_rev_core(int w, const double *Dinv, int nb, double *Aout, int64_t lda,
+                                              double *Dp, double *Bp, double *Xi) {
   const int tid = threadIdx.x, wave = tid >> 6;
-  load_packed2(Dp, Ld, ldl, Bp, Dbar, ldd, w);
-  __syncthreads();
 
   for (int a = ((w - 1) / INNER) * INNER; a >= 0; a -= INNER) {
     const int b = min(w, a + INNER);
@@ -586,6 +584,14 @@ __device__ __forceinline__ void diag_rev_block(int w, const double *Ld, int64_t 
     return (r > cc) ? 0.5 * Bp[pidx(r, cc)] : (r == cc ? Bp[pidx(r, r)] : 0.5 * Bp[pidx(cc, r)]);
   });
   __syncthreads();
+}
+
+__device__ __forceinline__ void diag_rev_block(int w, const double *Ld, int64_t ldl, const double *Dbar, int64_t ldd,
+                               const double *Dinv, int nb, double *Aout, int64_t lda, double *Dp,
+                               double *Bp, double *Xi) {
+  load_packed2(Dp, Ld, ldl, Bp, Dbar, ldd, w);
+  __syncthreads();
+  diag_rev_core(w, Dinv, nb, Aout, lda, Dp, Bp, Xi);
 }
 
 __global__ __launch_bounds__(DIAG_THREADS) void diag_rev_kernel(int w, const double *Ld, int64_t ldl,

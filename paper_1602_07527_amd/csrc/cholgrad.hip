@@ -16,6 +16,7 @@
 
 #include "cholgrad.h"
 #include "cg_batched.hpp"
+#include "cg_batched2.hpp"
 #include "cg_diag.hpp"
 #include "cg_gemm.hpp"
 
@@ -429,11 +430,116 @@ size_t carve_batch(int batch, int64_t n_max, bool f32, void *base, BatchWs *w) {
   return c.off;
 }
 
+// Workspace of the step-synchronous batched path (FP64 storage; cg_batched2.hpp): the plan
+// (order, sizes, B2_NPREF prefix arrays, step counts) and per problem ceil(n_max / 64) block
+// inverses and the two GP vectors.
+struct Batch2Ws {
+  int *order = nullptr, *nv = nullptr, *pref = nullptr, *count = nullptr;
+  double *dinv = nullptr, *vec = nullptr;
+  int64_t dinv_stride = 0, vec_stride = 0;
+};
+
+size_t carve_batch2(int batch, int64_t n_max, void *base, Batch2Ws *w) {
+  Carver c(base);
+  const int64_t nblk = std::max<int64_t>(1, cdiv(n_max, cg::B2_NB));
+  w->dinv_stride = nblk * cg::B2_BLK;
+  w->vec_stride = 2 * std::max<int64_t>(1, n_max);
+  w->order = reinterpret_cast<int *>(c.take((size_t)cdiv(batch, 2)));
+  w->nv = reinterpret_cast<int *>(c.take((size_t)cdiv(batch, 2)));
+  w->pref = reinterpret_cast<int *>(c.take((size_t)cdiv((int64_t)cg::B2_NPREF * (batch + 1), 2)));
+  w->count = reinterpret_cast<int *>(c.take((size_t)cg::B2_MAXBLK));
+  w->dinv = c.take((size_t)(batch * w->dinv_stride));
+  w->vec = c.take((size_t)(batch * w->vec_stride));
+  return c.off;
+}
+
+// Workspace of a batched call: enough for either path (FP64 storage: the step-synchronous path
+// of the factor, reverse, GP and factor + reverse calls or the persistent kernel of the forward
+// call; FP32 storage: the persistent kernel).
+size_t batched_ws_bytes(int batch, int64_t n_max, bool f32) {
+  BatchWs w;
+  const size_t v1 = carve_batch(batch, n_max, f32, nullptr, &w);
+  if (f32) return v1;
+  Batch2Ws w2;
+  return std::max(v1, carve_batch2(batch, n_max, nullptr, &w2));
+}
+
+// FP64 factor, reverse, GP and factor + reverse batches take the step-synchronous path: a plan,
+// then per 64-wide block step one grouped launch of each kind over every problem that has the
+// step (cg_batched2.hpp), all on stream s.
+constexpr int B2_GRID_DIAG = 256;    // diagonal blocks, one per wave: 133 KB of LDS, one per compute unit
+constexpr int B2_GRID_TILE = 1024;   // 64 x 64 tile products: 35 KB of LDS, four per compute unit
+
+bool batch2_op(const cg::BatchArgs &a) {
+  return !a.f32 && (a.op == cg::BATCH_FACTOR || a.op == cg::BATCH_REV || a.op == cg::BATCH_GP ||
+                    a.op == cg::BATCH_FACTOR_REV);
+}
+
+int run_batched2(const cg::BatchArgs &a, int64_t n_max, void *workspace, hipStream_t s) {
+  Batch2Ws ws;
+  carve_batch2(a.batch, n_max, workspace, &ws);
+  cg::B2Args b{};
+  b.op = a.op; b.batch = a.batch; b.sbar_form = a.sbar_form; b.n_max = (int)n_max;
+  b.n = a.n; b.A = a.A; b.lda = a.lda; b.L = a.L; b.ldl = a.ldl; b.y = a.y; b.G = a.G; b.ldg = a.ldg;
+  b.f = a.f; b.info = a.info;
+  b.order = ws.order; b.nv = ws.nv; b.pref = ws.pref; b.count = ws.count;
+  b.dinv = ws.dinv; b.vec = ws.vec;
+  b.dinv_stride = ws.dinv_stride; b.vec_stride = ws.vec_stride;
+  const int nsteps = (int)cdiv(std::max<int64_t>(n_max, 1), cg::B2_NB);
+  hipLaunchKernelGGL(cg::b2_order_kernel, dim3(1), dim3(1024), 0, s, b);
+  CG_TRY(hipGetLastError());
+  hipLaunchKernelGGL(cg::b2_prefix_kernel, dim3(cg::B2_NPREF), dim3(1024), 0, s, b);
+  CG_TRY(hipGetLastError());
+  const bool factor = a.op != cg::BATCH_REV;
+  const unsigned gd = (unsigned)std::min<int64_t>(cdiv(a.batch, cg::B2W_WAVES), B2_GRID_DIAG);
+  const unsigned gl = (unsigned)std::min(a.batch, 1024);  // GP loss: one workgroup per problem
+  if (factor) {
+    for (int st = 0; st < nsteps; ++st) {
+      if (st > 0) {
+        hipLaunchKernelGGL(cg::b2_up_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, st);
+        CG_TRY(hipGetLastError());
+      }
+      hipLaunchKernelGGL(cg::b2_potf2_kernel, dim3(gd), dim3(256), 0, s, b, st);
+      CG_TRY(hipGetLastError());
+      if (st + 1 < nsteps) {
+        hipLaunchKernelGGL(cg::b2_f2_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, st);
+        CG_TRY(hipGetLastError());
+      }
+    }
+  } else {
+    hipLaunchKernelGGL(cg::b2_trinv_kernel, dim3(B2_GRID_DIAG), dim3(256), 0, s, b);
+    CG_TRY(hipGetLastError());
+  }
+  if (a.op == cg::BATCH_FACTOR) return CHOL_SUCCESS;
+  if (a.op == cg::BATCH_GP) {
+    hipLaunchKernelGGL(cg::b2_loss_kernel, dim3(gl), dim3(256), 0, s, b);
+    CG_TRY(hipGetLastError());
+  }
+  for (int t = 0; t < nsteps; ++t) {
+    if (t > 0) {
+      hipLaunchKernelGGL(cg::b2_r0_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, t);
+      CG_TRY(hipGetLastError());
+      hipLaunchKernelGGL(cg::b2_r1_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, t);
+      CG_TRY(hipGetLastError());
+      hipLaunchKernelGGL(cg::b2_r2_kernel, dim3(gl), dim3(256), 0, s, b, t);
+      CG_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(cg::b2_r3_kernel, dim3(gd), dim3(256), 0, s, b, t);
+    CG_TRY(hipGetLastError());
+  }
+  if (a.sbar_form == CHOL_SBAR_TRIL) {
+    hipLaunchKernelGGL(cg::b2_form_kernel, dim3(gl), dim3(256), 0, s, b);
+    CG_TRY(hipGetLastError());
+  }
+  return CHOL_SUCCESS;
+}
+
 int run_batched(cg::BatchArgs a, int64_t n_max, void *workspace, size_t workspace_bytes, hipStream_t s) {
   BatchWs ws;
-  const size_t need = carve_batch(a.batch, n_max, a.f32 != 0, nullptr, &ws);
+  const size_t need = batched_ws_bytes(a.batch, n_max, a.f32 != 0);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
     return CHOL_ERR_WORKSPACE;
+  if (batch2_op(a)) return run_batched2(a, n_max, workspace, s);
   carve_batch(a.batch, n_max, a.f32 != 0, workspace, &ws);
   a.order = ws.order;
   a.counter = ws.counter;
@@ -611,8 +717,15 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
       CG_TRY(gemm(false, false, m - mb, w, m, A + k * lda + k, lda, L + k * ldl + j, ldl, -2.0,
                   A + k * lda + j, lda, 1.0, ws.panel, nb, nullptr, 0, 0, ws.part, 64, s, 1, cp));
       // C-bar = X D^-1 (Sec. 4.2: C-bar <- C-bar D^-1); store C-bar/2 = S_sym entries in both
-      // triangles.
-      {
+      // triangles.  Blocks wider than 128 below at least 8192 rows: one unsplit MFMA product on
+      // 128 x 128 tiles with the mirrored store (each X row strip is read once per 128 output
+      // columns instead of once per 16; measured at n = 16384, nb = 256: 46 us against the tiled
+      // kernel's 95 us at m = 16128, but a fixed ~45 us of K-tile latency at small m, where the
+      // tiled kernel takes 6 to 40 us); otherwise the tiled kernel.
+      if (w > cg::GEMM_BN && m >= 8192) {
+        CG_TRY(gemm(false, false, m, w, w, ws.panel, nb, ws.dinv + b * nb * nb, nb, 0.5, nullptr, 0, 0.0,
+                    A + k * lda + j, lda, A + j * lda + k, lda, 0, nullptr, 64, s));
+      } else {
         const int64_t nct = cdiv(w, cg::SYM_TILE);
         const unsigned grid = (unsigned)(cdiv(cdiv(m, cg::SYM_TILE), 8) * 8 * nct);
         hipLaunchKernelGGL(cg::rev_panel_solve_kernel, dim3(grid), dim3(256), 0, s, m, w, (const double *)ws.panel,
@@ -1092,8 +1205,7 @@ int chol_factor_fwd(int precision, int64_t n, void *Av, int64_t lda, void *Dv, i
 
 size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max) {
   if (!batched_prec_ok(precision) || batch <= 0 || n_max < 0 || n_max > cg::BATCH_NMAX) return 0;
-  BatchWs w;
-  return carve_batch(batch, n_max, precision == CHOL_PREC_F32, nullptr, &w);
+  return batched_ws_bytes(batch, n_max, precision == CHOL_PREC_F32);
 }
 
 static int batched_common_checks(int precision, int batch, int64_t n_max) {
