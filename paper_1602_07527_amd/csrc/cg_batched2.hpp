@@ -660,18 +660,16 @@ __global__ __launch_bounds__(256) void b2_up_kernel(B2Args a, int s) {
   }
 }
 
-// GP loss per problem (after the factor): z = L^-1 y and w = L^-T z by block substitution with
-// the block inverses, f = sum_i log L_ii + |z|^2 / 2, L-bar = diag(1 / L_ii) - tril(w z^T) into G
-// (strict upper triangle 0).  A problem whose factorisation failed gets f = NaN, G untouched.
+// GP loss per problem (after the factor): z = L^-1 y by block substitution with the block inverses
+// (kept in the workspace) and f = sum_i log L_ii + |z|^2 / 2.  The reverse-mode input
+// L-bar = diag(1 / L_ii) - tril(w z^T), w = L^-T z, is never stored: the reverse steps compute w
+// block by block (b2_gp_w) and form the entries of L-bar where they read them.  A problem whose
+// factorisation failed gets f = NaN and G untouched.
 __global__ __launch_bounds__(256) void b2_loss_kernel(B2Args a) {
   __shared__ double t[B2_NB];
   __shared__ double zl[BATCH_NMAX];
-  __shared__ double wl[BATCH_NMAX];
-  __shared__ double pt[4 * B2_NB];
   __shared__ double red[256];
-  __shared__ double dg[BATCH_NMAX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int NW = 4;
   const int cnt = a.count[0];
   for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
     const int i = a.order[p], n = a.nv[p];
@@ -682,10 +680,8 @@ __global__ __launch_bounds__(256) void b2_loss_kernel(B2Args a) {
     const double *L = a.A[i];
     const int64_t ldl = a.lda[i];
     const double *y = a.y[i];
-    double *G = a.G[i];
-    const int64_t ldg = a.ldg[i];
     const double *dinv = a.dinv + p * a.dinv_stride;
-    double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
+    double *zg = a.vec + p * a.vec_stride;
     const int nblk = b2_nblk(n);
     // forward: z_b = D_b^-1 (y_b - L[b, :j] z[:j]).  Wave h takes rows h, h + 4, ... of the block
     // with its lanes along the columns (coalesced, sixteen loads in flight per lane), and reduces
@@ -731,58 +727,9 @@ __global__ __launch_bounds__(256) void b2_loss_kernel(B2Args a) {
       }
       __syncthreads();
     }
-    // backward: w_b = D_b^-T (z_b - L[k:, b]^T w[k:]); thread (h, r) = (wave, lane) walks rows
-    // k + h, k + h + 4, ... of column j + r (loads coalesced over r, sixteen in flight), the four
-    // partial sums added in a fixed order
-    for (int b = nblk - 1; b >= 0; --b) {
-      const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j;
-      double sv = 0.0;
-      if (lane < w) {
-        int ii = k + wave;
-        for (; ii + 60 < n; ii += 64) {
-          double lv[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) lv[u] = L[(int64_t)(ii + 4 * u) * ldl + j + lane];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) sv = fma(lv[u], wl[ii + 4 * u], sv);
-        }
-        for (; ii < n; ii += 4) sv = fma(L[(int64_t)ii * ldl + j + lane], wl[ii], sv);
-      }
-      pt[wave * B2_NB + lane] = sv;
-      __syncthreads();
-      if (wave == 0 && lane < w)
-        t[lane] = zl[j + lane] - (((pt[lane] + pt[B2_NB + lane]) + pt[2 * B2_NB + lane]) + pt[3 * B2_NB + lane]);
-      __syncthreads();
-      const double *Di = dinv + b * B2_BLK;
-      double dv[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int q = lane + wave + 4 * u;
-        dv[u] = (lane < w && q < w) ? Di[q * B2_NB + lane] : 0.0;
-      }
-      sv = 0.0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int q = lane + wave + 4 * u;
-        if (lane < w && q < w) sv = fma(dv[u], t[q], sv);
-      }
-      pt[wave * B2_NB + lane] = sv;
-      __syncthreads();
-      if (wave == 0 && lane < w) {
-        const double v = ((pt[lane] + pt[B2_NB + lane]) + pt[2 * B2_NB + lane]) + pt[3 * B2_NB + lane];
-        wg[j + lane] = v;
-        wl[j + lane] = v;
-      }
-      __syncthreads();
-    }
-    // f: per-thread partial sums over a fixed stride, then a fixed-order tree; 1 / L_ii kept in
-    // LDS (t is free again) for L-bar
+    // f: per-thread partial sums over a fixed stride, then a fixed-order tree
     double part = 0.0;
-    for (int ii = threadIdx.x; ii < n; ii += blockDim.x) {
-      const double d = L[(int64_t)ii * ldl + ii];
-      part += log(d) + 0.5 * zl[ii] * zl[ii];
-      dg[ii] = 1.0 / d;
-    }
+    for (int ii = threadIdx.x; ii < n; ii += blockDim.x) part += log(L[(int64_t)ii * ldl + ii]) + 0.5 * zl[ii] * zl[ii];
     red[threadIdx.x] = part;
     __syncthreads();
     for (int hh = blockDim.x / 2; hh > 0; hh >>= 1) {
@@ -790,18 +737,68 @@ __global__ __launch_bounds__(256) void b2_loss_kernel(B2Args a) {
       __syncthreads();
     }
     if (threadIdx.x == 0) a.f[i] = red[0];
-    // L-bar = diag(1 / L_ii) - tril(w z^T), one wave per row (LDS operands only)
-    for (int rr = wave; rr < n; rr += NW) {
-      const double wr = wl[rr], dr = dg[rr];
-      for (int c = lane; c < n; c += 64)
-        G[(int64_t)rr * ldg + c] = c < rr ? -wr * zl[c] : (c == rr ? dr - wr * zl[c] : 0.0);
-    }
     __syncthreads();
   }
 }
 
 __device__ __forceinline__ bool b2_rev_skip(const B2Args &a, int i) {
   return (a.op == BATCH_GP || a.op == BATCH_FACTOR_REV) && a.info[i] != 0;
+}
+
+// GP mode: w_b = D_b^-T (z_b - L[k:, j:k]^T w[k:]) for block b = [j, k) by a whole workgroup
+// (called by all its threads), once w[k:] is known -- the backward substitution of w = L^-T z, one
+// block per reverse step.  Thread (h, r) = (wave, lane) walks rows k + h, k + h + 4, ... of column
+// j + r (coalesced, sixteen loads in flight) and the four partial sums are added in a fixed order.
+// tb and pt: B2_NB and 4 * B2_NB doubles of LDS.
+__device__ void b2_gp_w(const B2Args &a, int p, int n, int b, double *tb, double *pt) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = a.order[p];
+  const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j;
+  const double *L = a.A[i];
+  const int64_t ldl = a.lda[i];
+  const double *zg = a.vec + p * a.vec_stride;
+  double *wg = (double *)zg + a.n_max;
+  double sv = 0.0;
+  if (lane < w) {
+    int ii = k + wave;
+    for (; ii + 60 < n; ii += 64) {
+      double lv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) lv[u] = L[(int64_t)(ii + 4 * u) * ldl + j + lane];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) sv = fma(lv[u], wg[ii + 4 * u], sv);
+    }
+    for (; ii < n; ii += 4) sv = fma(L[(int64_t)ii * ldl + j + lane], wg[ii], sv);
+  }
+  pt[wave * B2_NB + lane] = sv;
+  __syncthreads();
+  if (wave == 0 && lane < w)
+    tb[lane] = zg[j + lane] - (((pt[lane] + pt[B2_NB + lane]) + pt[2 * B2_NB + lane]) + pt[3 * B2_NB + lane]);
+  __syncthreads();
+  const double *Di = a.dinv + p * a.dinv_stride + b * B2_BLK;
+  double dv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = lane + wave + 4 * u;
+    dv[u] = (lane < w && q < w) ? Di[q * B2_NB + lane] : 0.0;
+  }
+  sv = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = lane + wave + 4 * u;
+    if (lane < w && q < w) sv = fma(dv[u], tb[q], sv);
+  }
+  pt[wave * B2_NB + lane] = sv;
+  __syncthreads();
+  if (wave == 0 && lane < w) wg[j + lane] = ((pt[lane] + pt[B2_NB + lane]) + pt[2 * B2_NB + lane]) + pt[3 * B2_NB + lane];
+  __syncthreads();
+}
+
+// GP mode: entry (r, c), r >= c, of L-bar = diag(1 / L_ii) - tril(w z^T).
+__device__ __forceinline__ double b2_gp_lbar(const double *zg, const double *wg, const double *L, int64_t ldl,
+                                             int r, int c) {
+  const double v = -wg[r] * zg[c];
+  return r == c ? 1.0 / L[(int64_t)r * ldl + r] + v : v;
 }
 
 // R0: X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k] for the rows below block b = nblk - 1 - t, in place
@@ -824,10 +821,13 @@ __global__ __launch_bounds__(256) void b2_r0_kernel(B2Args a, int t) {
     t64_mma<true, false>(
         acc, [&](int r, int kk) { return (r < R && kk < m) ? Gi[(int64_t)(r0 + r) * ldg + k + kk] : 0.0; },
         [&](int kk, int c) { return (c < w && kk < m) ? Li[(int64_t)(k + kk) * ldl + j + c] : 0.0; }, m, lds);
+    const bool gp = a.op == BATCH_GP;
+    const double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w) {
         double *d = Gi + (int64_t)(r0 + r) * ldg + j + c;
-        *d = *d - 2.0 * v;
+        const double lbar = gp ? -wg[r0 + r] * zg[j + c] : *d;
+        *d = lbar - 2.0 * v;
       }
     });
     __syncthreads();
@@ -870,7 +870,10 @@ __global__ __launch_bounds__(256) void b2_r1_kernel(B2Args a, int t) {
 // lower triangle of G's diagonal block.
 __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
   __shared__ double lds[T64_LDS];
+  __shared__ double tb[B2_NB];
+  __shared__ double pt[4 * B2_NB];
   const int cnt = a.count[t];
+  const bool gp = a.op == BATCH_GP;
   for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
     const int i = a.order[p], n = a.nv[p];
     if (b2_rev_skip(a, i)) continue;
@@ -879,6 +882,8 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
     int64_t ldl, ldg;
     const double *Li = b2_L(a, i, ldl);
     double *Gi = b2_G(a, i, ldg);
+    if (gp) b2_gp_w(a, p, n, b, as_lds(tb), as_lds(pt));
+    const double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
     dbl4 acc[2][2];
     t64_mma<false, false>(
         acc, [&](int x, int kk) { return (x < w) ? Gi[(int64_t)(k + kk) * ldg + j + x] : 0.0; },
@@ -886,7 +891,8 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
     t64_each(acc, [&](int x, int y, double v) {
       if (x < w && y <= x) {
         double *d = Gi + (int64_t)(j + x) * ldg + j + y;
-        *d = *d - 2.0 * v;
+        const double lbar = gp ? b2_gp_lbar(zg, wg, Li, ldl, j + x, j + y) : *d;
+        *d = lbar - 2.0 * v;
       }
     });
     __syncthreads();
@@ -898,9 +904,11 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
 // G's block; the symmetric gradient's block goes to both triangles of G.
 __global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
   __shared__ double lds[B2W_WAVES * B2W_LDS];
+  __shared__ double wv[B2W_WAVES * B2_NB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double *Dp = as_lds(lds + wave * B2W_LDS), *Bp = Dp + B2_PACKED;
+  double *Dp = as_lds(lds + wave * B2W_LDS), *Bp = Dp + B2_PACKED, *wl = as_lds(wv + wave * B2_NB);
   const int cnt = a.count[t];
+  const bool gp0 = a.op == BATCH_GP && t == 0;
   for (int p = blockIdx.x * B2W_WAVES + wave; p < cnt; p += gridDim.x * B2W_WAVES) {
     const int i = a.order[p], n = a.nv[p];
     if (b2_rev_skip(a, i)) continue;
@@ -909,10 +917,39 @@ __global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
     int64_t ldl, ldg;
     const double *Ld = b2_L(a, i, ldl) + (int64_t)j * ldl + j;
     double *Gd = b2_G(a, i, ldg) + (int64_t)j * ldg + j;
+    const double *Di = a.dinv + p * a.dinv_stride + b * B2_BLK;
     wave_load_lower(Dp, Ld, ldl, w);
-    wave_load_lower(Bp, Gd, ldg, w);
+    if (gp0) {
+      // GP, last block: w_b = D_b^-T z_b (nothing below it), then D-bar = L-bar_D from w and z
+      const double *zg = a.vec + p * a.vec_stride;
+      double *wg = (double *)zg + a.n_max;
+      double sv = 0.0;
+      for (int q0 = 0; q0 < w; q0 += 16) {
+        double dv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int q = q0 + u;
+          dv[u] = (lane < w && q < w && q >= lane) ? Di[q * B2_NB + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (q0 + u < w) sv = fma(dv[u], zg[j + q0 + u], sv);
+      }
+      if (lane < w) {
+        wl[lane] = sv;
+        wg[j + lane] = sv;
+      }
+      wave_sync();
+      for (int r = 0; r < w; ++r)
+        if (lane <= r) {
+          const double v = -wl[r] * zg[j + lane];
+          Bp[pidx(r, lane)] = lane == r ? 1.0 / Ld[(int64_t)r * ldl + r] + v : v;
+        }
+    } else {
+      wave_load_lower(Bp, Gd, ldg, w);
+    }
     wave_sync();
-    wave_diag_rev_64(Dp, Bp, a.dinv + p * a.dinv_stride + b * B2_BLK, w);
+    wave_diag_rev_64(Dp, Bp, Di, w);
     for (int r = 0; r < w; ++r)
       if (lane < w)
         Gd[(int64_t)r * ldg + lane] = lane < r ? 0.5 * Bp[pidx(r, lane)]
