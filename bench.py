@@ -13,11 +13,12 @@ percentiles are reported under "batched", and those of the same matrices in FP32
 "batched_f32".  The three sweeps in the reduced-precision modes (trailing contractions on FP32
 MFMA, or as split-bfloat16 MFMA products) are timed alone under "f64_trail_f32" and
 "f64_trail_bf16x3"; the headline value stays the FP64 path's.  The three sweeps on the
-N = 4096 workload (lengthscale 0.3, nugget 1e-4) are timed for nb = 32, 64 and 128 under
+N = 4096 workload (lengthscale 0.3, nugget 1e-4) are timed for nb = 64, 128 and 256 under
 "n4096_by_nb", and one call of each on the N = 256 dense case under "n256_latency".  Under
-"serving", a Poisson stream of factor + chol_rev requests of uneven size runs through the
-continuous-batching loop (paper_1602_07527_amd.serve) in both precision modes: p50/p99 latency and
-solves/s.
+"serving", a 60 s Poisson stream of factor + chol_rev requests of uneven size runs through the
+continuous-batching loop (paper_1602_07527_amd.serve) in both precision modes (p50/p99 latency and
+solves/s), then compressed in time to find where each mode saturates, with the per-request error of
+the mixed mode against the FP64 one.
 
 Roofline: the dominant kernel (chol_rev's panel contraction) is timed per launch by HIP events the
 library records around each launch on the call's stream, in a kernel-timing pass of one or two
@@ -186,12 +187,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
-    ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--nb", type=int, default=0,
+                    help="block width of all three sweeps (0: the measured per-sweep choice, "
+                         "chol_rev and chol_factor 256, chol_fwd 128)")
     ap.add_argument("--batch-launches", type=int, default=50,
                     help="timed launches of the batched path for its latency percentiles")
     ap.add_argument("--cpu-sample", type=int, default=10240,
                     help="leading-block size for the CPU oracle baseline (0 skips it)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served request stream (0 skips it)")
     ap.add_argument("--n4096-steps", type=int, default=5,
                     help="timed passes of the N=4096 sweeps for each nb (0 skips them)")
@@ -218,7 +221,12 @@ def main():
 
     cg.load_library()
     dev = torch.device("cuda:0")
-    n, nb = args.n, args.nb
+    n = args.n
+    # Block widths per sweep (measured on MI355X at N = 16384: chol_rev 54.1 ms at nb = 256 against
+    # 55.9 ms at 128, chol_factor 35.6 against 36.6, chol_fwd 59.3 against 56.9, the one-sweep
+    # factor + forward 87.1 against 93.2).
+    nb_rev, nb_fac, nb_fwd = (args.nb, args.nb, args.nb) if args.nb else (256, 256, 128)
+    nb_ff = args.nb or 256
     log(f"[bench] building the N={n} workload on the device")
     inp = workloads.large_case_device(dev, N=n)
     Sigma, Lbar, Sdot = inp["Sigma"], inp["Lbar"], inp["Sdot"]
@@ -226,7 +234,7 @@ def main():
     Ab = torch.empty_like(Sigma)
     Ad = torch.empty_like(Sigma)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
-    ws_bytes = max(cg.workspace_bytes(op, n, nb) for op in ("factor", "rev", "fwd"))
+    ws_bytes = max(cg.workspace_bytes(op, n, b) for op in ("factor", "rev", "fwd") for b in {nb_rev, nb_fac, nb_fwd, nb_ff})
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d", "b", "r2", "d2")}
     times = {"f": 0.0, "r": 0.0, "d": 0.0, "b": 0.0}
@@ -242,15 +250,15 @@ def main():
     def step(record):
         A.copy_(Sigma)
         if record: ev["f"][0].record()
-        cg.chol_factor(A, nb=nb, workspace=ws, info=info)
+        cg.chol_factor(A, nb=nb_fac, workspace=ws, info=info)
         if record: ev["f"][1].record()
         Ab.copy_(Lbar)
         if record: ev["r"][0].record()
-        cg.chol_rev(A, Ab, nb=nb, workspace=ws)
+        cg.chol_rev(A, Ab, nb=nb_rev, workspace=ws)
         if record: ev["r"][1].record()
         Ad.copy_(Sdot)
         if record: ev["d"][0].record()
-        cg.chol_fwd(A, Ad, nb=nb, workspace=ws)
+        cg.chol_fwd(A, Ad, nb=nb_fwd, workspace=ws)
         if record: ev["d"][1].record()
         bat["work"].copy_(bat["master"])
         if record: ev["b"][0].record()
@@ -343,14 +351,14 @@ def main():
         m = workloads.se_case_device(4096, workloads.SEED_MEDIUM, 0.3, 1e-4, dev)
         n2 = 4096
         A2, B2, D2 = torch.empty_like(m["Sigma"]), torch.empty_like(m["Sigma"]), torch.empty_like(m["Sigma"])
-        ws2 = torch.empty(max(cg.workspace_bytes(op, n2, nbv) for op in ("factor", "rev", "fwd") for nbv in (32, 64, 128)),
+        ws2 = torch.empty(max(cg.workspace_bytes(op, n2, nbv) for op in ("factor", "rev", "fwd") for nbv in (64, 128, 256)),
                           dtype=torch.uint8, device=dev)
         info2 = torch.empty(1, dtype=torch.int32, device=dev)
         by_nb = {"workload": "squared-exponential kernel matrix N=4096 (3-D inputs, lengthscale 0.3, nugget "
                              "1e-4, built on the device); median of the timed passes per nb; chol_rev/chol_fwd "
                              "with the default (symbolic) diagonal-block variant and, as *_level2_ms, with the "
                              "Level-2 one"}
-        for nbv in (32, 64, 128):
+        for nbv in (64, 128, 256):
             t = {"f": [], "r": [], "d": []}
             for i in range(args.n4096_steps + 1):
                 A2.copy_(m["Sigma"])
@@ -376,8 +384,9 @@ def main():
                 "chol_factor_ms": round(med["f"], 3), "chol_factor_tflops": round(n2 ** 3 / 3.0 / (med["f"] * 1e-3) / 1e12, 2),
                 "chol_rev_ms": round(med["r"], 3), "chol_rev_tflops": round(2.0 / 3.0 * n2 ** 3 / (med["r"] * 1e-3) / 1e12, 2),
                 "chol_fwd_ms": round(med["d"], 3), "chol_fwd_tflops": round(2.0 / 3.0 * n2 ** 3 / (med["d"] * 1e-3) / 1e12, 2)}
-        # The Level-2 diagonal-block variant, in a pass of its own on the last factor (A2).
-        for nbv in (32, 64, 128):
+        # The Level-2 diagonal-block variant (blocks up to 128 wide), in a pass of its own on the
+        # last factor (A2).
+        for nbv in (64, 128):
             t = {"r2": [], "d2": []}
             for i in range(args.n4096_steps + 1):
                 B2.copy_(m["Lbar"])
@@ -405,7 +414,7 @@ def main():
             A.copy_(Sigma)
             Ad.copy_(Sdot)
             ev["f"][0].record()
-            cg.chol_factor_fwd(A, Ad, nb=nb, workspace=ws, info=info)
+            cg.chol_factor_fwd(A, Ad, nb=nb_ff, workspace=ws, info=info)
             ev["f"][1].record()
             torch.cuda.synchronize()
             if i > 0:
@@ -429,15 +438,15 @@ def main():
         for i in range(args.mixed_steps + 1):
             A.copy_(Sigma)
             ev["f"][0].record()
-            cg.chol_factor(A, nb=nb, workspace=ws, info=info, precision=mode)
+            cg.chol_factor(A, nb=nb_fac, workspace=ws, info=info, precision=mode)
             ev["f"][1].record()
             Ab.copy_(Lbar)
             ev["r"][0].record()
-            cg.chol_rev(A, Ab, nb=nb, workspace=ws, precision=mode)
+            cg.chol_rev(A, Ab, nb=nb_rev, workspace=ws, precision=mode)
             ev["r"][1].record()
             Ad.copy_(Sdot)
             ev["d"][0].record()
-            cg.chol_fwd(A, Ad, nb=nb, workspace=ws, precision=mode)
+            cg.chol_fwd(A, Ad, nb=nb_fwd, workspace=ws, precision=mode)
             ev["d"][1].record()
             torch.cuda.synchronize()
             if i > 0:
@@ -496,7 +505,9 @@ def main():
 
     # Serving: the Poisson request stream (200 requests/s, n log-uniform in [64, 4096], 2-D
     # squared-exponential kernels), factor + chol_rev per request through the continuous-batching
-    # loop, in FP64 and with FP32-MFMA trailing contractions for the large requests.
+    # loop, in FP64 and with FP32-MFMA trailing contractions for the large requests; then the same
+    # stream compressed in time (its first requests offered at higher rates) to find where each
+    # mode saturates, and the per-request error of the mixed mode against the FP64 one.
     serving = None
     if args.serve_seconds > 0:
         from paper_1602_07527_amd import serve
@@ -505,7 +516,8 @@ def main():
         serving = {"workload": f"Poisson arrivals at 200/s for {args.serve_seconds:g} s ({len(tr['t'])} "
                                "requests), n log-uniform in [64, 4096], SE kernel on U[0,1]^2 (lengthscale "
                                "U[0.1, 0.5]) + 1e-3 I, L-bar = tril N(0,1); one request = chol_factor + "
-                               "chol_rev; HBM budget 64 GiB", "n_mean": round(float(tr["n"].mean()), 1)}
+                               "chol_rev; HBM budget 64 GiB; inputs built on the device as each request "
+                               "arrives (included in the latency)", "n_mean": round(float(tr["n"].mean()), 1)}
         for mode in ("f64", "f64_trail_f32"):
             log(f"[bench] serving {args.serve_seconds:g} s in {mode}")
             srv = serve.Server(dev, hbm_budget=64 << 30, precision=mode)
@@ -516,6 +528,54 @@ def main():
             serving[mode]["launches"] = dict(srv.launches)
             serving[mode]["peak_admitted_gib"] = round(srv.peak_in_use / 2 ** 30, 3)
             del done, srv
+        # Saturation: the first SAT_REQ requests of the same stream with their arrival times divided
+        # by rate / 200, per mode; sustained = completed / wall clock.
+        SAT_REQ = min(len(tr["t"]), 1500)
+        sat = {"requests_per_point": SAT_REQ,
+               "note": "offered rate = the stream's first requests with arrival times compressed; "
+                       "p99 includes queueing once the offered rate exceeds what the loop sustains"}
+        for mode in ("f64", "f64_trail_f32"):
+            pts = []
+            for rate in (400.0, 800.0, 1600.0, 3200.0):
+                log(f"[bench] serving saturation {mode} at {rate:g}/s")
+                srv = serve.Server(dev, hbm_budget=64 << 30, precision=mode)
+                done, wall = serve.replay(srv, tr["t"][:SAT_REQ] * (200.0 / rate), make)
+                lat = np.array([r.latency for r in done]) * 1e3
+                pts.append({"offered_per_s": rate, "solves_per_s": round(len(done) / wall, 1),
+                            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                            "p99_ms": round(float(np.percentile(lat, 99)), 3)})
+                del done, srv
+            sat[mode] = pts
+        serving["saturation"] = sat
+        # Per-request error of the mixed mode: a seeded sample of the stream plus its ten
+        # worst-conditioned requests (largest n * lengthscale), each solved in both modes on the same
+        # GPU; relative Frobenius error of L and Sigma-bar against the FP64 result (which is within
+        # max(1e-10, 100 kappa u) of the oracle).
+        log("[bench] serving: mixed-precision error sample")
+        rng = np.random.default_rng(17)
+        pick = np.unique(np.concatenate([rng.choice(len(tr["t"]), size=min(150, len(tr["t"])), replace=False),
+                                         np.argsort(tr["n"] * tr["lengthscale"])[-10:]]))
+        eL, eS = [], []
+        for i in pick:
+            if tr["n"][i] <= serve.SMALL_MAX:   # small requests are served by the FP64 batched path
+                eL.append(0.0)
+                eS.append(0.0)
+                continue
+            res = {}
+            for mode in ("f64", "f64_trail_f32"):
+                S_i, Lb_i = make(int(i))
+                Lf, _ = cg.chol_factor(S_i, precision=mode)
+                cg.chol_rev(Lf, Lb_i, precision=mode)
+                res[mode] = (Lf, Lb_i)
+            (L64, S64), (L32, S32) = res["f64"], res["f64_trail_f32"]
+            eL.append(float(torch.linalg.norm(L32 - L64) / torch.linalg.norm(L64)))
+            eS.append(float(torch.linalg.norm(S32 - S64) / torch.linalg.norm(S64)))
+        eL, eS = np.array(eL), np.array(eS)
+        serving["f64_trail_f32"]["error_vs_f64"] = {
+            "requests": int(len(pick)), "rel_sbar_p50": float(np.percentile(eS, 50)),
+            "rel_sbar_p95": float(np.percentile(eS, 95)), "rel_sbar_max": float(eS.max()),
+            "rel_l_max": float(eL.max()), "stated_bound_rel_sbar": 2e-2, "stated_bound_rel_l": 6e-4,
+            "note": "requests with n <= 512 run on the FP64 batched path in both modes (error 0)"}
 
     K = args.steps
     ms_step = (t1 - t0) * 1e3 / K
@@ -548,7 +608,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"squared-exponential kernel matrix N={n} (3-D inputs, lengthscale "
                                f"0.2, nugget 1e-2); step = chol_factor + chol_rev + chol_fwd",
-                   "n": n, "nb": nb},
+                   "n": n, "nb": {"chol_rev": nb_rev, "chol_factor": nb_fac, "chol_fwd": nb_fwd,
+                                  "chol_factor_fwd": nb_ff}},
         "pct_fp64_peak": round(100 * rev_tflops / FP64_PEAK_TFLOPS, 2),
         "chol_rev_ms": round(rev_ms, 3), "chol_factor_ms": round(fac_ms, 3),
         "chol_fwd_ms": round(fwd_ms, 3),

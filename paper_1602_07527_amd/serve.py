@@ -284,12 +284,13 @@ class Server:
         self.running.append(ln)
 
 
-def replay(server, arrivals, make_inputs, on_done=None, poll_s=20e-6):
+def replay(server, arrivals, make_inputs, on_done=None, poll_s=20e-6, keep_buffers=False):
     """Drive `server` with an arrival schedule: arrivals[i] is request i's arrival time in seconds
     from the start; at that time make_inputs(i) -> (Sigma, Lbar) writes its inputs on the caller's
     current stream and the request is submitted with an event on that stream.  Latency runs from
     the scheduled arrival, so a loop that falls behind is charged for it.  Calls on_done(request)
-    for every completion (after which the request's buffers may be dropped).  Returns
+    for every completion; afterwards the request's device buffers (its L and Sigma-bar) are
+    released unless keep_buffers, so a long stream holds only the requests in flight.  Returns
     (completed requests, wall seconds)."""
     arrivals = np.asarray(arrivals, dtype=np.float64)
     done_all = []
@@ -307,6 +308,8 @@ def replay(server, arrivals, make_inputs, on_done=None, poll_s=20e-6):
         for r in done:
             if on_done is not None:
                 on_done(r)
+            if not keep_buffers:
+                r.Sigma = r.Lbar = None
         done_all += done
         if not done and (i >= len(arrivals) or arrivals[i] > time.perf_counter() - t0):
             time.sleep(poll_s)
