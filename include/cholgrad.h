@@ -58,11 +58,11 @@ extern "C" {
 
 /* Precision of the call.
  *   CHOL_PREC_F64 : double storage; every step in FP64 (FP64 MFMA for the contractions).
- *   CHOL_PREC_F32 : float storage (matrices, vectors and losses), batched calls only; each
- *                   problem's lower triangle is widened to FP64 in the workspace, computed exactly
- *                   as in CHOL_PREC_F64 and rounded to float once on output, so the result is the
- *                   FP64 result for the float input to within float rounding.  Single-matrix
- *                   calls return CHOL_ERR_UNSUPPORTED for it.
+ *   CHOL_PREC_F32 : float storage (matrices, vectors and losses); each input's lower triangle is
+ *                   widened to FP64 in the workspace (single-matrix calls: n*n doubles per matrix
+ *                   argument, included by chol_workspace_bytes), computed exactly as in
+ *                   CHOL_PREC_F64 and rounded to float once on output, so the result is the FP64
+ *                   result for the float input to within float rounding.
  *   CHOL_PREC_F64_TRAIL_F32 : double storage, single-matrix calls only (batched calls return
  *                   CHOL_ERR_UNSUPPORTED, as for the next mode).  The trailing contractions -- the block-column
  *                   updates of chol_factor and chol_fwd and the panel contraction and SYRK of
@@ -82,11 +82,22 @@ extern "C" {
  *                   lo = bf16(fp32(x) - hi)) and take hi*hi + hi*lo + lo*hi on bfloat16 MFMA
  *                   with FP32 accumulation (~16 significant bits per operand).  Stated relative
  *                   errors on the same N = 16384 workload: <= 1e-3 for L, <= 3e-4 for Sigma-bar
- *                   and L-dot (measured 3.0e-4, 2.3e-5, 2.1e-5). */
+ *                   and L-dot (measured 3.0e-4, 2.3e-5, 2.1e-5).
+ *   CHOL_PREC_F64_TRAIL_BF16X6 : as CHOL_PREC_F64_TRAIL_BF16X3 with three bfloat16 parts per operand
+ *                   (hi, mid = bf16(fp32(x) - hi), lo = bf16(fp32(x) - hi - mid)) and the six
+ *                   products hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid (~24 significant
+ *                   bits per operand, as FP32, on the bfloat16 matrix units).  Single-matrix calls.
+ *                   Stated relative errors on the N = 16384 workload: <= 5e-4 for L, <= 2e-4 for
+ *                   Sigma-bar, <= 3e-5 for L-dot (measured 4.6e-5, 2.0e-5, 1.9e-6).
+ *   CHOL_PREC_F32_TRAIL_BF16X3 : float storage as CHOL_PREC_F32, computed as
+ *                   CHOL_PREC_F64_TRAIL_BF16X3 on the widened copies (errors as that mode's, plus
+ *                   the final rounding to float).  Single-matrix calls. */
 #define CHOL_PREC_F64 0
 #define CHOL_PREC_F32 1
 #define CHOL_PREC_F64_TRAIL_F32 2
 #define CHOL_PREC_F64_TRAIL_BF16X3 3
+#define CHOL_PREC_F64_TRAIL_BF16X6 4
+#define CHOL_PREC_F32_TRAIL_BF16X3 5
 
 /* Which reverse-mode output (Sec. 3, eqns (symrev) and (symrevtril); S = L^-T Phi(L^T Lbar) L^-1):
  *   CHOL_SBAR_SYM  : (S + S^T)/2 in both triangles -- the symmetric gradient, for which

@@ -16,8 +16,17 @@ PREC_F64 = 0
 PREC_F32 = 1
 PREC_F64_TRAIL_F32 = 2
 PREC_F64_TRAIL_BF16X3 = 3
-# Precision modes of the single-matrix calls (FP64 storage).
-_PRECS = {"f64": PREC_F64, "f64_trail_f32": PREC_F64_TRAIL_F32, "f64_trail_bf16x3": PREC_F64_TRAIL_BF16X3}
+PREC_F64_TRAIL_BF16X6 = 4
+PREC_F32_TRAIL_BF16X3 = 5
+# Precision modes of the single-matrix calls: FP64 storage, or FP32 storage ('f32*', float32
+# tensors, computed on FP64 copies inside the library).
+_PRECS = {"f64": PREC_F64, "f64_trail_f32": PREC_F64_TRAIL_F32, "f64_trail_bf16x3": PREC_F64_TRAIL_BF16X3,
+          "f64_trail_bf16x6": PREC_F64_TRAIL_BF16X6, "f32": PREC_F32, "f32_trail_bf16x3": PREC_F32_TRAIL_BF16X3}
+
+
+def _storage(precision):
+    """Tensor dtype of a single-matrix precision mode."""
+    return (torch.float32,) if str(precision).startswith("f32") else (torch.float64,)
 SBAR_SYM, SBAR_TRIL = 0, 1
 OP_FACTOR, OP_REV, OP_FWD = 0, 1, 2
 _FORMS = {"sym": SBAR_SYM, "tril": SBAR_TRIL}
@@ -157,7 +166,7 @@ def chol_factor(A, nb=0, workspace=None, info=None, precision="f64", layout="row
     (LAPACK) storage of A."""
     lib = load_library()
     prec, lay = _pick(_PRECS, precision, "precision"), _pick(_LAYOUTS, layout, "layout")
-    n = _square("A", A, layout=layout)
+    n = _square("A", A, _storage(precision), layout)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
     ws = _workspace("factor", n, nb, A.device, workspace, precision, layout)
@@ -175,8 +184,8 @@ def chol_rev(L, A, form="sym", nb=0, workspace=None, precision="f64", diag="auto
     lib = load_library()
     prec, fm, dv = _pick(_PRECS, precision, "precision"), _pick(_FORMS, form, "form"), _pick(_DIAGS, diag, "diag")
     lay = _pick(_LAYOUTS, layout, "layout")
-    n = _square("L", L, layout=layout)
-    if _square("A", A, layout=layout) != n or A.device != L.device:
+    n = _square("L", L, _storage(precision), layout)
+    if _square("A", A, _storage(precision), layout) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("rev", n, nb, A.device, workspace, precision, layout)
     with torch.cuda.device(A.device):
@@ -206,8 +215,8 @@ def chol_fwd(L, A, nb=0, workspace=None, precision="f64", diag="auto", layout="r
     lib = load_library()
     prec, dv = _pick(_PRECS, precision, "precision"), _pick(_DIAGS, diag, "diag")
     lay = _pick(_LAYOUTS, layout, "layout")
-    n = _square("L", L, layout=layout)
-    if _square("A", A, layout=layout) != n or A.device != L.device:
+    n = _square("L", L, _storage(precision), layout)
+    if _square("A", A, _storage(precision), layout) != n or A.device != L.device:
         raise ValueError("L and A must have the same size and device")
     ws = _workspace("fwd", n, nb, A.device, workspace, precision, layout)
     with torch.cuda.device(A.device):
@@ -221,8 +230,8 @@ def chol_factor_fwd(A, D, nb=0, workspace=None, info=None, precision="f64"):
     upper triangles set to 0).  Returns (A, D, info)."""
     lib = load_library()
     prec = _pick(_PRECS, precision, "precision")
-    n = _square("A", A)
-    if _square("D", D) != n or D.device != A.device:
+    n = _square("A", A, _storage(precision))
+    if _square("D", D, _storage(precision)) != n or D.device != A.device:
         raise ValueError("A and D must have the same size and device")
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)

@@ -1164,6 +1164,33 @@ __global__ __launch_bounds__(256) void lower_to_upper_kernel(int64_t n, double *
   }
 }
 
+// FP32 storage of the single-matrix calls: dst[r * ldd + c] = element (r, c) of the float matrix
+// src for c <= r (src row-major with ld lds, or column-major when col is set), 0 above the
+// diagonal (the lower triangle is the input).
+__global__ __launch_bounds__(256) void widen_lower_kernel(int64_t n, const float *src, int64_t lds, int col,
+                                                          double *dst, int64_t ldd) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n, c = e - r * n;
+    dst[r * ldd + c] = c <= r ? (double)(col ? src[r + c * lds] : src[r * lds + c]) : 0.0;
+  }
+}
+
+// Element (r, c) of the float matrix dst (layout as above) = src[r * lds + c] rounded to float, for
+// every r, c < n.
+__global__ __launch_bounds__(256) void narrow_kernel(int64_t n, const double *src, int64_t lds, float *dst,
+                                                     int64_t ldd, int col) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n, c = e - r * n;
+    const float v = (float)src[r * lds + c];
+    if (col) dst[r + c * ldd] = v;
+    else dst[r * ldd + c] = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void sym_to_tril_kernel(int64_t n, double *A, int64_t lda) {
   const int64_t total = n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;

@@ -37,9 +37,16 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 //           lo = bf16(fp32(x) - hi), round to nearest even), the product taken as
 //           hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x16_bf16 and FP32 accumulation within
 //           one split; ~16 significant bits per operand.
+//   CP_BF16X6: each operand split into three bfloat16 parts (hi = bf16(fp32(x)), mid =
+//           bf16(fp32(x) - hi), lo = bf16(fp32(x) - hi - mid)) and the product taken as the six
+//           terms hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid (the terms below 2^-24 of
+//           the product dropped), FP32 accumulation within one split; ~24 significant bits per
+//           operand, as FP32.
 constexpr int CP_F64 = 0;
 constexpr int CP_F32 = 1;
 constexpr int CP_BF16X3 = 2;
+constexpr int CP_BF16X6 = 3;
+__host__ __device__ constexpr bool cp_split(int cp) { return cp == CP_BF16X3 || cp == CP_BF16X6; }
 
 typedef short shrt4 __attribute__((ext_vector_type(4)));
 
@@ -69,6 +76,50 @@ __device__ __forceinline__ flt4 mfma_bf16x3(const shrt4 &ah, const shrt4 &al, co
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
 }
 
+// The parts of four operand values in one split mode: hi, mid (BF16X6 only) and lo.
+struct Split4 {
+  shrt4 h, m, l;
+};
+
+// Split four doubles into bfloat16 parts: two (hi, lo) for BF16X3, three (hi, mid, lo) for
+// BF16X6, each the round-to-nearest-even bfloat16 of what the previous parts leave of fp32(x).
+template <int CP>
+__device__ __forceinline__ Split4 split4(double x0, double x1, double x2, double x3) {
+  Split4 s;
+  if constexpr (CP == CP_BF16X3) {
+    bf16_split4(x0, x1, x2, x3, s.h, s.l);
+  } else {
+    const double x[4] = {x0, x1, x2, x3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float f = (float)x[i];
+      const unsigned h = bf16_rne(f);
+      const float r1 = f - __uint_as_float(h << 16);
+      const unsigned m = bf16_rne(r1);
+      const float r2 = r1 - __uint_as_float(m << 16);
+      s.h[i] = (short)h;
+      s.m[i] = (short)m;
+      s.l[i] = (short)bf16_rne(r2);
+    }
+  }
+  return s;
+}
+
+// acc += a b over one 16-deep bfloat16 K-group in split mode CP, smallest terms first.
+template <int CP>
+__device__ __forceinline__ flt4 mfma_split(const Split4 &a, const Split4 &b, flt4 c) {
+  if constexpr (CP == CP_BF16X3) {
+    return mfma_bf16x3(a.h, a.l, b.h, b.l, c);
+  } else {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.m, b.m, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.l, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.l, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.m, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.m, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.h, c, 0, 0, 0);
+  }
+}
+
 template <int CP> struct Mfma;
 template <> struct Mfma<CP_F64> {
   typedef dbl4 acc_t;
@@ -84,6 +135,7 @@ template <> struct Mfma<CP_BF16X3> {  // accumulator and output layout of the FP
   static __device__ __forceinline__ acc_t zero() { return acc_t{0.0f, 0.0f, 0.0f, 0.0f}; }
   static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
+template <> struct Mfma<CP_BF16X6> : Mfma<CP_BF16X3> {};
 template <> struct Mfma<CP_F32> {
   typedef flt4 acc_t;
   static __device__ __forceinline__ acc_t zero() { return acc_t{0.0f, 0.0f, 0.0f, 0.0f}; }
@@ -226,20 +278,20 @@ __device__ void gemm_tile(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
     if (kt + 1 < nkt) load_tile(kbeg + (kt + 1) * BK);
     const double *as = As(buf);
     const double *bs = Bs(buf);
-    if constexpr (CP == CP_BF16X3) {
-      // one 16-deep bf16 MFMA per K-tile: the lanes of slot frag_k take k = 4 frag_k .. + 3
-      shrt4 ah[4], al[4], bh[4], bl[4];
+    if constexpr (cp_split(CP)) {
+      // one 16-deep bf16 K-group per K-tile: the lanes of slot frag_k take k = 4 frag_k .. + 3
+      Split4 sa[4], sb[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const double *pa = as + 4 * frag_k * LDA_S + wm * 64 + t * 16 + frag_i;
-        bf16_split4(pa[0], pa[LDA_S], pa[2 * LDA_S], pa[3 * LDA_S], ah[t], al[t]);
+        sa[t] = split4<CP>(pa[0], pa[LDA_S], pa[2 * LDA_S], pa[3 * LDA_S]);
         const double *pb = bs + 4 * frag_k * LDB_S + wn * 64 + t * 16 + frag_i;
-        bf16_split4(pb[0], pb[LDB_S], pb[2 * LDB_S], pb[3 * LDB_S], bh[t], bl[t]);
+        sb[t] = split4<CP>(pb[0], pb[LDB_S], pb[2 * LDB_S], pb[3 * LDB_S]);
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16x3(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma_split<CP>(sa[a], sb[b], acc[a][b]);
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
@@ -429,11 +481,11 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
     if (kt + 1 < nkt) issue(kt + 1, (kt + 1) & 1);
     const double *as = smem + (2 * (kt & 1)) * TILE;
     const double *bs = smem + (2 * (kt & 1) + 1) * TILE;
-    if constexpr (CP == CP_BF16X3) {
-      // one 16-deep bf16 MFMA per K-tile: the lanes of slot fk take k = 4 fk .. 4 fk + 3, i.e.
-      // 16-byte chunks 2 fk and 2 fk + 1 of a K-contiguous row
+    if constexpr (cp_split(CP)) {
+      // one 16-deep bf16 K-group per K-tile: the lanes of slot fk take k = 4 fk .. 4 fk + 3,
+      // i.e. 16-byte chunks 2 fk and 2 fk + 1 of a K-contiguous row
       static_assert(BK == 16, "the split-bf16 path takes one 16-deep K-tile per MFMA");
-      shrt4 ah[TMW], al[TMW], bh[TNW], bl[TNW];
+      Split4 sa[TMW], sb[TNW];
 #pragma unroll
       for (int t = 0; t < TMW; ++t) {
         const int m = wm * (BM / WM) + t * 16 + fi;
@@ -446,7 +498,7 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
           const dbl2v p1 = *(const dbl2v *)&as[m * BK + (((2 * fk + 1) ^ (m % CH)) << 1)];
           x0 = p0[0]; x1 = p0[1]; x2 = p1[0]; x3 = p1[1];
         }
-        bf16_split4(x0, x1, x2, x3, ah[t], al[t]);
+        sa[t] = split4<CP>(x0, x1, x2, x3);
       }
 #pragma unroll
       for (int t = 0; t < TNW; ++t) {
@@ -460,12 +512,12 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
           x0 = bs[(4 * fk) * BN + n]; x1 = bs[(4 * fk + 1) * BN + n];
           x2 = bs[(4 * fk + 2) * BN + n]; x3 = bs[(4 * fk + 3) * BN + n];
         }
-        bf16_split4(x0, x1, x2, x3, bh[t], bl[t]);
+        sb[t] = split4<CP>(x0, x1, x2, x3);
       }
 #pragma unroll
       for (int a = 0; a < TMW; ++a)
 #pragma unroll
-        for (int b = 0; b < TNW; ++b) acc[a][b] = mfma_bf16x3(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+        for (int b = 0; b < TNW; ++b) acc[a][b] = mfma_split<CP>(sa[a], sb[b], acc[a][b]);
     } else {
 #pragma unroll
       for (int u = 0; u < BK / 8; ++u) {

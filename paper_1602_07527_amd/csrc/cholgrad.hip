@@ -158,6 +158,7 @@ bool single_prec(int precision, int *cp) {
   if (precision == CHOL_PREC_F64) { *cp = cg::CP_F64; return true; }
   if (precision == CHOL_PREC_F64_TRAIL_F32) { *cp = cg::CP_F32; return true; }
   if (precision == CHOL_PREC_F64_TRAIL_BF16X3) { *cp = cg::CP_BF16X3; return true; }
+  if (precision == CHOL_PREC_F64_TRAIL_BF16X6) { *cp = cg::CP_BF16X6; return true; }
   return false;
 }
 
@@ -206,6 +207,7 @@ void launch_gemm(bool at, bool bt, bool fast, int tag, int cp, dim3 grid, const 
                  hipStream_t s) {
   if (cp == cg::CP_F32) launch_gemm_cp<cg::CP_F32>(at, bt, fast, tag, grid, p, s);
   else if (cp == cg::CP_BF16X3) launch_gemm_cp<cg::CP_BF16X3>(at, bt, fast, tag, grid, p, s);
+  else if (cp == cg::CP_BF16X6) launch_gemm_cp<cg::CP_BF16X6>(at, bt, fast, tag, grid, p, s);
   else launch_gemm_cp<cg::CP_F64>(at, bt, fast, tag, grid, p, s);
 }
 
@@ -563,6 +565,19 @@ int run_batched(cg::BatchArgs a, int64_t n_max, void *workspace, size_t workspac
 }
 
 
+// FP32 storage of the single-matrix calls (defined at the end of this file).
+bool f32_storage(int precision) {
+  return precision == CHOL_PREC_F32 || precision == CHOL_PREC_F32_TRAIL_BF16X3;
+}
+int f32_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int layout, int *info, void *ws,
+               size_t wsb, void *stream);
+int f32_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int sbar_form, int nb,
+            int diag, int layout, void *ws, size_t wsb, void *stream);
+int f32_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb, int diag,
+            int layout, void *ws, size_t wsb, void *stream);
+int f32_factor_fwd(int precision, int64_t n, void *A, int64_t lda, void *D, int64_t ldd, int nb, int *info,
+                   void *ws, size_t wsb, void *stream);
+
 }  // namespace
 
 extern "C" {
@@ -623,6 +638,11 @@ const char *chol_status_string(int status) {
 }
 
 size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
+  if (f32_storage(precision)) {  // FP64 copies of the matrices, then the FP64-storage sweep's own
+    const int inner = precision == CHOL_PREC_F32 ? CHOL_PREC_F64 : CHOL_PREC_F64_TRAIL_BF16X3;
+    const size_t base = chol_workspace_bytes(op, inner, n, nb);
+    return base ? base + (op == CHOL_OP_FACTOR ? 1 : 2) * align_up((size_t)n * n * sizeof(double)) : 0;
+  }
   int cp = cg::CP_F64;
   if (n <= 0 || !single_prec(precision, &cp) || !nb_ok(nb)) return 0;
   if (op != CHOL_OP_FACTOR && op != CHOL_OP_REV && op != CHOL_OP_FWD) return 0;
@@ -781,6 +801,9 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
 
 int chol_rev(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
              int sbar_form, int nb, void *workspace, size_t workspace_bytes, void *stream) {
+  if (f32_storage(precision))
+    return f32_rev(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_AUTO, CHOL_LAYOUT_ROW_MAJOR, workspace,
+                   workspace_bytes, stream);
   return rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_AUTO, workspace, workspace_bytes,
                   stream);
 }
@@ -845,7 +868,10 @@ int chol_rev_noalloc(int precision, int64_t n, const void *Lv, int64_t ldl, void
 
 int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *info,
                 void *workspace, size_t workspace_bytes, void *stream) {
-  if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
+  if (f32_storage(precision)) {
+    if (n > 0 && !info) return -6;
+    return f32_factor(precision, n, Av, lda, nb, CHOL_LAYOUT_ROW_MAJOR, info, workspace, workspace_bytes, stream);
+  }
   int cp = cg::CP_F64;
   if (!single_prec(precision, &cp)) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
@@ -1084,7 +1110,8 @@ static bool batched_prec_ok(int precision) {
 
 int chol_factor_fwd(int precision, int64_t n, void *Av, int64_t lda, void *Dv, int64_t ldd, int nb, int *info,
                     void *workspace, size_t workspace_bytes, void *stream) {
-  if (precision == CHOL_PREC_F32) return CHOL_ERR_UNSUPPORTED;
+  if (f32_storage(precision))
+    return f32_factor_fwd(precision, n, Av, lda, Dv, ldd, nb, info, workspace, workspace_bytes, stream);
   int cp = cg::CP_F64;
   if (!single_prec(precision, &cp)) return -1;
   if (n < 0 || n > (int64_t)1 << 30) return -2;
@@ -1209,7 +1236,9 @@ size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max) {
 }
 
 static int batched_common_checks(int precision, int batch, int64_t n_max) {
-  if (precision == CHOL_PREC_F64_TRAIL_F32 || precision == CHOL_PREC_F64_TRAIL_BF16X3) return CHOL_ERR_UNSUPPORTED;
+  if (precision == CHOL_PREC_F64_TRAIL_F32 || precision == CHOL_PREC_F64_TRAIL_BF16X3 ||
+      precision == CHOL_PREC_F64_TRAIL_BF16X6 || precision == CHOL_PREC_F32_TRAIL_BF16X3)
+    return CHOL_ERR_UNSUPPORTED;
   if (!batched_prec_ok(precision)) return -1;
   if (batch < 0) return -2;
   if (n_max < 0 || n_max > cg::BATCH_NMAX) return CHOL_ERR_UNSUPPORTED;
@@ -1251,6 +1280,9 @@ int chol_rev_batched(int precision, int batch, const int64_t *n, const void *con
 
 int chol_fwd(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb,
              void *workspace, size_t workspace_bytes, void *stream) {
+  if (f32_storage(precision))
+    return f32_fwd(precision, n, Lv, ldl, Av, lda, nb, CHOL_DIAG_AUTO, CHOL_LAYOUT_ROW_MAJOR, workspace,
+                   workspace_bytes, stream);
   return fwd_impl(precision, n, Lv, ldl, Av, lda, nb, CHOL_DIAG_AUTO, workspace, workspace_bytes, stream);
 }
 
@@ -1278,6 +1310,7 @@ static hipError_t launch_lower_to_upper(int64_t n, double *A, int64_t lda, hipSt
 
 size_t chol_workspace_bytes_ex(int op, int precision, int64_t n, int nb, int layout) {
   if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return 0;
+  if (f32_storage(precision)) return chol_workspace_bytes(op, precision, n, nb);  // copies take the layout
   const size_t base = chol_workspace_bytes(op, precision, n, nb);
   if (base == 0 || layout == CHOL_LAYOUT_ROW_MAJOR || op == CHOL_OP_FACTOR) return base;
   return transposed_l_bytes(n) + base;
@@ -1285,6 +1318,7 @@ size_t chol_workspace_bytes_ex(int op, int precision, int64_t n, int nb, int lay
 
 int chol_factor_ex(int precision, int64_t n, void *Av, int64_t lda, int nb, int layout, int *info,
                    void *workspace, size_t workspace_bytes, void *stream) {
+  if (f32_storage(precision)) return f32_factor(precision, n, Av, lda, nb, layout, info, workspace, workspace_bytes, stream);
   if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return -6;
   if (n > 0 && !info) return -7;
   if (layout == CHOL_LAYOUT_ROW_MAJOR || n <= 0)
@@ -1306,6 +1340,8 @@ int chol_factor_ex(int precision, int64_t n, void *Av, int64_t lda, int nb, int 
 
 int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int sbar_form,
                 int nb, int diag, int layout, void *workspace, size_t workspace_bytes, void *stream) {
+  if (f32_storage(precision))
+    return f32_rev(precision, n, Lv, ldl, Av, lda, sbar_form, nb, diag, layout, workspace, workspace_bytes, stream);
   if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return -10;
   if (layout == CHOL_LAYOUT_ROW_MAJOR || n <= 0)
     return rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, diag, workspace, workspace_bytes, stream);
@@ -1328,6 +1364,8 @@ int chol_rev_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av,
 
 int chol_fwd_ex(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda, int nb, int diag,
                 int layout, void *workspace, size_t workspace_bytes, void *stream) {
+  if (f32_storage(precision))
+    return f32_fwd(precision, n, Lv, ldl, Av, lda, nb, diag, layout, workspace, workspace_bytes, stream);
   if (layout != CHOL_LAYOUT_ROW_MAJOR && layout != CHOL_LAYOUT_COL_MAJOR) return -9;
   if (layout == CHOL_LAYOUT_ROW_MAJOR || n <= 0)
     return fwd_impl(precision, n, Lv, ldl, Av, lda, nb, diag, workspace, workspace_bytes, stream);
@@ -1407,3 +1445,131 @@ int chol_gp_nll_batched(int precision, int batch, const int64_t *n, void *const 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// FP32 storage for the single-matrix calls (CHOL_PREC_F32, CHOL_PREC_F32_TRAIL_BF16X3): the float
+// inputs are widened into FP64 row-major copies at the front of the workspace (from either
+// layout), the FP64-storage sweep runs on the copies (in CHOL_PREC_F64 or
+// CHOL_PREC_F64_TRAIL_BF16X3) with the rest of the workspace, and each output is rounded to float
+// once into the caller's array, in its layout.  Arguments are validated (a dry call of the FP64
+// sweep on the copies) before anything is enqueued.
+namespace {
+
+int f64_inner(int precision) { return precision == CHOL_PREC_F32 ? CHOL_PREC_F64 : CHOL_PREC_F64_TRAIL_BF16X3; }
+size_t copy_bytes(int64_t n) { return align_up((size_t)n * n * sizeof(double)); }
+bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+bool layout_ok(int layout) { return layout == CHOL_LAYOUT_ROW_MAJOR || layout == CHOL_LAYOUT_COL_MAJOR; }
+unsigned elem_blocks(int64_t n) { return (unsigned)std::min<int64_t>(cdiv(n * n, 256), 4096); }
+
+hipError_t widen(int64_t n, const void *src, int64_t lds, int layout, double *dst, hipStream_t s) {
+  hipLaunchKernelGGL(cg::widen_lower_kernel, dim3(elem_blocks(n)), dim3(256), 0, s, n, static_cast<const float *>(src),
+                     lds, layout == CHOL_LAYOUT_COL_MAJOR ? 1 : 0, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t narrow(int64_t n, const double *src, void *dst, int64_t ldd, int layout, hipStream_t s) {
+  hipLaunchKernelGGL(cg::narrow_kernel, dim3(elem_blocks(n)), dim3(256), 0, s, n, src, n, static_cast<float *>(dst),
+                     ldd, layout == CHOL_LAYOUT_COL_MAJOR ? 1 : 0);
+  return hipGetLastError();
+}
+
+bool ws_ok(void *ws, size_t wsb, size_t need) {
+  return ws && (reinterpret_cast<uintptr_t>(ws) % WS_ALIGN) == 0 && wsb >= need;
+}
+
+int f32_factor(int precision, int64_t n, void *A, int64_t lda, int nb, int layout, int *info, void *ws,
+               size_t wsb, void *stream) {
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!A || !aligned4(A)) return -3;
+  if (lda < n) return -4;
+  if (!nb_ok(nb)) return -5;
+  if (!layout_ok(layout)) return -6;
+  if (!info) return -7;
+  if (!ws_ok(ws, wsb, chol_workspace_bytes(CHOL_OP_FACTOR, precision, n, nb))) return CHOL_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *W = static_cast<double *>(ws);
+  const size_t cb = copy_bytes(n);
+  CG_TRY(widen(n, A, lda, layout, W, s));
+  const int rc = chol_factor(f64_inner(precision), n, W, n, nb, info, static_cast<char *>(ws) + cb, wsb - cb, stream);
+  if (rc != CHOL_SUCCESS) return rc;
+  CG_TRY(narrow(n, W, A, lda, layout, s));
+  return CHOL_SUCCESS;
+}
+
+int f32_rev(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int sbar_form, int nb,
+            int diag, int layout, void *ws, size_t wsb, void *stream) {
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!L || !aligned4(L)) return -3;
+  if (ldl < n) return -4;
+  if (!A || !aligned4(A)) return -5;
+  if (lda < n) return -6;
+  if (!layout_ok(layout)) return -10;
+  const size_t cb = copy_bytes(n);
+  double *Wl = static_cast<double *>(ws), *Wa = reinterpret_cast<double *>(static_cast<char *>(ws) + cb);
+  const int inner = f64_inner(precision);
+  double *const fake = reinterpret_cast<double *>((uintptr_t)WS_ALIGN);  // validation only: never touched
+  const int chk = rev_impl(inner, n, fake, n, fake, n, sbar_form, nb, diag, nullptr, 0, stream);
+  if (chk != CHOL_ERR_WORKSPACE) return chk;
+  if (!ws_ok(ws, wsb, chol_workspace_bytes(CHOL_OP_REV, precision, n, nb))) return CHOL_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CG_TRY(widen(n, L, ldl, layout, Wl, s));
+  CG_TRY(widen(n, A, lda, layout, Wa, s));
+  const int rc = rev_impl(inner, n, Wl, n, Wa, n, sbar_form, nb, diag, static_cast<char *>(ws) + 2 * cb,
+                          wsb - 2 * cb, stream);
+  if (rc != CHOL_SUCCESS) return rc;
+  CG_TRY(narrow(n, Wa, A, lda, layout, s));
+  return CHOL_SUCCESS;
+}
+
+int f32_fwd(int precision, int64_t n, const void *L, int64_t ldl, void *A, int64_t lda, int nb, int diag,
+            int layout, void *ws, size_t wsb, void *stream) {
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!L || !aligned4(L)) return -3;
+  if (ldl < n) return -4;
+  if (!A || !aligned4(A)) return -5;
+  if (lda < n) return -6;
+  if (!layout_ok(layout)) return -9;
+  const size_t cb = copy_bytes(n);
+  double *Wl = static_cast<double *>(ws), *Wa = reinterpret_cast<double *>(static_cast<char *>(ws) + cb);
+  const int inner = f64_inner(precision);
+  double *const fake = reinterpret_cast<double *>((uintptr_t)WS_ALIGN);
+  const int chk = fwd_impl(inner, n, fake, n, fake, n, nb, diag, nullptr, 0, stream);
+  if (chk != CHOL_ERR_WORKSPACE) return chk;
+  if (!ws_ok(ws, wsb, chol_workspace_bytes(CHOL_OP_FWD, precision, n, nb))) return CHOL_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CG_TRY(widen(n, L, ldl, layout, Wl, s));
+  CG_TRY(widen(n, A, lda, layout, Wa, s));
+  const int rc = fwd_impl(inner, n, Wl, n, Wa, n, nb, diag, static_cast<char *>(ws) + 2 * cb, wsb - 2 * cb, stream);
+  if (rc != CHOL_SUCCESS) return rc;
+  CG_TRY(narrow(n, Wa, A, lda, layout, s));
+  return CHOL_SUCCESS;
+}
+
+int f32_factor_fwd(int precision, int64_t n, void *A, int64_t lda, void *D, int64_t ldd, int nb, int *info,
+                   void *ws, size_t wsb, void *stream) {
+  if (n < 0 || n > (int64_t)1 << 30) return -2;
+  if (n == 0) return CHOL_SUCCESS;
+  if (!A || !aligned4(A)) return -3;
+  if (lda < n) return -4;
+  if (!D || !aligned4(D)) return -5;
+  if (ldd < n) return -6;
+  if (!nb_ok(nb)) return -7;
+  if (!info) return -8;
+  if (!ws_ok(ws, wsb, chol_workspace_bytes(CHOL_OP_FWD, precision, n, nb))) return CHOL_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t cb = copy_bytes(n);
+  double *Wa = static_cast<double *>(ws), *Wd = reinterpret_cast<double *>(static_cast<char *>(ws) + cb);
+  CG_TRY(widen(n, A, lda, CHOL_LAYOUT_ROW_MAJOR, Wa, s));
+  CG_TRY(widen(n, D, ldd, CHOL_LAYOUT_ROW_MAJOR, Wd, s));
+  const int rc = chol_factor_fwd(f64_inner(precision), n, Wa, n, Wd, n, nb, info, static_cast<char *>(ws) + 2 * cb,
+                                 wsb - 2 * cb, stream);
+  if (rc != CHOL_SUCCESS) return rc;
+  CG_TRY(narrow(n, Wa, A, lda, CHOL_LAYOUT_ROW_MAJOR, s));
+  CG_TRY(narrow(n, Wd, D, ldd, CHOL_LAYOUT_ROW_MAJOR, s));
+  return CHOL_SUCCESS;
+}
+
+}  // namespace

@@ -101,19 +101,15 @@ def test_invalid_arguments_rejected_on_host():
 
 
 def test_precision_modes_on_host():
-    """FP32 storage exists only for the batched calls and the reduced-precision trailing modes
-    (FP32 and split-bf16) only for the single-matrix calls; the other combinations are refused as
-    unsupported before any launch."""
+    """The reduced-precision trailing modes (FP32 and split-bf16) exist only for the single-matrix
+    calls; the batched calls refuse them as unsupported before any launch."""
     lib = _lib()
     fake = ctypes.c_void_p(4096)
     ws = ctypes.c_void_p(1 << 20)
     big = 1 << 40
     assert lib.chol_workspace_bytes(1, 2, 1000, 0) == lib.chol_workspace_bytes(1, 0, 1000, 0) > 0
     assert lib.chol_workspace_bytes(1, 3, 1000, 0) == lib.chol_workspace_bytes(1, 0, 1000, 0)
-    assert lib.chol_workspace_bytes(1, 4, 1000, 0) == 0       # no mode 4
-    assert lib.chol_workspace_bytes(1, 1, 1000, 0) == 0
-    assert lib.chol_rev(1, 10, fake, 10, fake, 10, 0, 0, ws, big, None) == -103
-    assert lib.chol_factor(1, 10, fake, 10, 0, fake, ws, big, None) == -103
+    assert lib.chol_workspace_bytes(1, 6, 1000, 0) == 0       # no mode 6
     assert lib.chol_batched_workspace_bytes(2, 1, 4) == 0
     assert lib.chol_batched_workspace_bytes(1, 1, 512) > lib.chol_batched_workspace_bytes(0, 1, 512) > 0
     assert lib.chol_factor_batched(2, 1, None, None, None, 4, None, None, 0, None) == -103
@@ -140,3 +136,31 @@ def test_noalloc_entry_rejects_on_host():
     assert f(1, 10, fake, 10, fake, 10, 0, 0, None) == -103
     assert f(0, 0, None, 0, None, 0, 0, 0, None) == 0
     assert lib.chol_status_string(-104).startswith(b"problem larger")
+
+
+def test_storage_and_split_modes_on_host():
+    """CHOL_PREC_F64_TRAIL_BF16X6 (4) and the FP32-storage single-matrix modes (1 and
+    CHOL_PREC_F32_TRAIL_BF16X3 = 5): the FP32-storage workspace adds n*n doubles per matrix
+    argument (one for the factor, two for rev / fwd) to the FP64 sweep's; the batched calls refuse
+    the split and FP32-trailing modes as unsupported."""
+    lib = _lib()
+    n = 1000
+    copy = 8 * n * n
+    for op, copies in ((0, 1), (1, 2), (2, 2)):
+        f64 = lib.chol_workspace_bytes(op, 0, n, 0)
+        assert lib.chol_workspace_bytes(op, 4, n, 0) == f64
+        assert lib.chol_workspace_bytes(op, 1, n, 0) == f64 + copies * copy
+        assert lib.chol_workspace_bytes(op, 5, n, 0) == f64 + copies * copy
+        assert lib.chol_workspace_bytes_ex(op, 1, n, 0, 1) == f64 + copies * copy   # no transposed copy of L
+    for prec in (2, 3, 4, 5):
+        assert lib.chol_batched_workspace_bytes(prec, 4, 100) == 0
+        assert lib.chol_factor_batched(prec, 1, None, None, None, 4, None, None, 0, None) == -103
+    fake = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    big = 1 << 40
+    assert lib.chol_rev(1, 10, ctypes.c_void_p(4098), 10, fake, 10, 0, 0, ws, big, None) == -3   # float alignment
+    assert lib.chol_rev(1, 10, fake, 10, fake, 10, 0, 0, ws, 16, None) == -102
+    assert lib.chol_rev_ex(5, 10, fake, 10, fake, 10, 0, 256, 2, 0, ws, big, None) == -103        # Level-2, nb > 128
+    assert lib.chol_factor(1, 10, fake, 10, 0, None, ws, big, None) == -6
+    assert lib.chol_fwd_ex(1, 10, fake, 10, fake, 10, 0, 0, 3, ws, big, None) == -9
+    assert lib.chol_rev_noalloc(1, 10, fake, 10, fake, 10, 0, 0, None) == -103

@@ -9,10 +9,12 @@ numbers ~3e4 and ~1e5):
 
     f64_trail_f32     relL <= 3e-4, rel Sigma-bar <= 1e-4, rel L-dot <= 3e-5
     f64_trail_bf16x3  relL <= 1e-3, rel Sigma-bar <= 3e-4, rel L-dot <= 3e-4
+    f64_trail_bf16x6  relL <= 5e-4, rel Sigma-bar <= 2e-4, rel L-dot <= 3e-5
 
 The Sigma-bar and L-dot bounds are about 10x the largest error measured on MI355X (N = 16384:
 FP32 trailing relL 7.6e-5, rel Sigma-bar 7.1e-6, rel L-dot 2.6e-6; split-bf16 relL 3.0e-4,
-rel Sigma-bar 2.3e-5, rel L-dot 2.1e-5), so a 10x loss of accuracy fails them; the relL bounds
+rel Sigma-bar 2.3e-5, rel L-dot 2.1e-5; split-bf16 x6 relL 4.6e-5, rel Sigma-bar 2.0e-5,
+rel L-dot 1.9e-6), so a 10x loss of accuracy fails them; the relL bounds
 keep a 3-4x margin over the factor's measured error, which grows with N.  Every result must also
 differ from the oracle by more than 1e-9 (the FP64 path is ~1e-13 away), which shows the
 reduced-precision kernels really ran.
@@ -24,7 +26,8 @@ import oracle as O
 import workloads as W
 
 pytestmark = pytest.mark.gpu
-TOLS = {"f64_trail_f32": (3e-4, 1e-4, 3e-5), "f64_trail_bf16x3": (1e-3, 3e-4, 3e-4)}
+TOLS = {"f64_trail_f32": (3e-4, 1e-4, 3e-5), "f64_trail_bf16x3": (1e-3, 3e-4, 3e-4),
+        "f64_trail_bf16x6": (5e-4, 2e-4, 3e-5)}
 MODES = list(TOLS)
 FLOOR = 1e-9
 
