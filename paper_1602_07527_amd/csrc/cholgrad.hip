@@ -25,12 +25,15 @@ namespace {
 constexpr size_t WS_ALIGN = 256;
 constexpr int DEFAULT_NB = 128;
 constexpr int TARGET_WGS = 512;  // two contraction workgroups per compute unit on 256 CUs
-// Workgroups of a stream-K contraction: a little below the 512 resident slots.  The diagonal
-// block kernels of the sweeps run beside the contractions on the other stream and hold most of a
-// compute unit's LDS; with more workgroups than this, some of them wait for a slot until that
-// kernel ends (measured on MI355X in the N = 16384 sweeps: 480 beats 448, 464, 496 and 504).
-// Short launches (under SK_SHORT_KTILES K-tiles per workgroup) lose the most to such a wait, and
-// take SK_WGS_SHORT workgroups (chol_rev 64.9 -> 64.2 ms, chol_factor 39.6 -> 38.8 ms, same GPU).
+// Workgroups of a stream-K contraction in a sweep with a side stream: a little below the 512
+// resident slots.  The diagonal block kernels of such a sweep run beside the contractions and
+// hold most of a compute unit's LDS; with more workgroups than this, some of them wait for a slot
+// until that kernel ends (measured on MI355X in the N = 16384 sweeps: 480 beats 448, 464, 496 and
+// 504).  Short launches (under SK_SHORT_KTILES K-tiles per workgroup) lose the most to such a
+// wait, and take SK_WGS_SHORT workgroups (chol_rev 64.9 -> 64.2 ms, chol_factor 39.6 -> 38.8 ms,
+// same GPU).  A sweep whose products run alone on its stream (the symbolic diagonal block) takes
+// all TARGET_WGS slots: N = 16384, nb = 256 chol_rev 53.3 -> 51.0 ms, nb = 128 chol_fwd 56.7 ->
+// 54.6 ms, while chol_factor, with POTF2 beside, goes 35.5 -> 40.6 ms at 512.
 constexpr int SK_WGS = 480;
 constexpr int SK_WGS_SHORT = 448;
 constexpr int64_t SK_SHORT_KTILES = 48;
@@ -42,6 +45,7 @@ constexpr int64_t TILE_ELEMS = (int64_t)cg::GEMM_BM * cg::GEMM_BN;
 struct PartBuf {
   double *p = nullptr;
   int64_t slots = 0;
+  int sk_wgs = 0;  // stream-K workgroups when set (nothing else of the sweep runs beside)
   PartBuf() = default;
   PartBuf(std::nullptr_t) {}
   PartBuf(double *base, int64_t n) : p(base), slots(base ? n : 0) {}
@@ -251,7 +255,7 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   int64_t skw = 0;
   if (part.p && fast && !lower_only && Kt > 0 && tiles >= 2) {
     const int64_t units = (int64_t)tiles * (Kt / cg::DMA_BK);
-    skw = units < SK_SHORT_KTILES * SK_WGS ? SK_WGS_SHORT : SK_WGS;
+    skw = part.sk_wgs ? part.sk_wgs : (units < SK_SHORT_KTILES * SK_WGS ? SK_WGS_SHORT : SK_WGS);
     skw = std::min<int64_t>(skw, units * cg::DMA_BK / std::max(min_kchunk, cg::DMA_BK));
     skw = std::min<int64_t>(skw, part.slots - tiles + 1);
     if (skw <= tiles) skw = 0;
@@ -699,6 +703,8 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
   if (any_level2) {
     CG_TRY(side_for(s, &side));
     s2 = side->s;
+  } else {
+    ws.part.sk_wgs = TARGET_WGS;
   }
 
   CG_TRY(block_inverses(n, nb, L, ldl, ws.dinv, ws.panel, s));  // the panel is free until the sweep
@@ -982,6 +988,8 @@ static int fwd_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
   if (b0 > 0) {
     CG_TRY(side_for(s, &side));
     s2 = side->s;
+  } else {
+    ws.part.sk_wgs = TARGET_WGS;
   }
   CG_TRY(block_inverses(n, nb, L, ldl, ws.dinv, ws.panel, s));  // the panel is free until the sweep
   if (b0 > 0) {
