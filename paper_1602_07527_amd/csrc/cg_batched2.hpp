@@ -286,14 +286,6 @@ __device__ __forceinline__ void t64_each(const dbl4 (&acc)[2][2], F out) {
 constexpr int B2W_WAVES = 4;
 constexpr int B2W_LDS = 2 * B2_PACKED;  // doubles per wave
 
-// Orders this wave's LDS writes before its later LDS reads (a wave's LDS accesses are processed in
-// order; this keeps the compiler from moving them across).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Packed lower triangle of a w x w block (w <= 64, row-major source) into Dp, by one wave, sixteen
 // rows of loads in flight.
 __device__ __forceinline__ void wave_load_lower(double *Dp, const double *src, int64_t ld, int w) {
@@ -314,17 +306,15 @@ __device__ __forceinline__ void wave_load_lower(double *Dp, const double *src, i
 }
 
 // D <- chol_unblocked(D) and Xp = D^-1 for the w x w block (w <= 64) packed in Dp, by one wave:
-// inner block 0 (Level-2 core), the rows below it solved lane by lane, the update of inner block 1
+// inner block 0 with the rows below it (one pass of the Level-2 core), the update of inner block 1
 // (three 16 x 16 MFMA tiles), inner block 1, then X00, X11 and X10 = -X11 (D10 X00).  Returns the
 // first column with a non-positive or NaN pivot, or -1.
-__device__ int wave_potf2_64(double *Dp, double *Xp, int w) {
-  const int lane = threadIdx.x & 63;
+__device__ int wave_potf2_64(double *Dp_, double *Xp_, int w) {
+  lds_double *Dp = lds_view(Dp_), *Xp = lds_view(Xp_);
   const int ib0 = min(INNER, w), ib1 = w - ib0;
-  int bad = level2_potf2_wave(Dp, 0, ib0);
+  int bad = panel_core32<false>(Dp_, 0, ib0, w, INNER, true);
   wave_sync();
   if (ib1 > 0) {
-    if (lane < ib1) panel_solve_row(Dp, 0, INNER, INNER + lane);
-    wave_sync();
     // D11 <- D11 - D10 D10^T, lower 16 x 16 tiles, K = 32
     dbl4 acc[3];
     const int nt = (ib1 + 15) / 16;
@@ -350,13 +340,13 @@ __device__ int wave_potf2_64(double *Dp, double *Xp, int w) {
       }
     }
     wave_sync();
-    const int f = level2_potf2_wave(Dp, INNER, ib1);
+    const int f = panel_core32<false>(Dp_, INNER, ib1, w, 2 * INNER, true);
     if (bad < 0 && f >= 0) bad = INNER + f;
     wave_sync();
   }
-  wave_trinv32(Dp, Xp, 0, ib0);
+  wave_trinv32(Dp_, Xp_, 0, ib0);
   if (ib1 > 0) {
-    wave_trinv32(Dp, Xp, INNER, ib1);
+    wave_trinv32(Dp_, Xp_, INNER, ib1);
     wave_sync();
     // Y = D10 X00 (ib1 x 32), then X10 = -X11 Y, each as up to 2 x 2 tiles held in registers
     const int nt = (ib1 + 15) / 16;
@@ -416,10 +406,11 @@ __device__ int wave_potf2_64(double *Dp, double *Xp, int w) {
 // D-bar <- chol_unblocked_rev(D, D-bar) for a w x w block (w <= 64), D packed in Dp, D-bar in Bp,
 // by one wave: the blocked reverse sweep over its two inner blocks from the bottom-right, as
 // diag_rev_core, with D_0^-1 read from Dinv (ld 64).
-__device__ void wave_diag_rev_64(double *Dp, double *Bp, const double *Dinv, int w) {
+__device__ void wave_diag_rev_64(double *Dp_, double *Bp_, const double *Dinv, int w) {
+  lds_double *Dp = lds_view(Dp_), *Bp = lds_view(Bp_);
   const int ib0 = min(INNER, w), ib1 = w - ib0;
   if (ib1 > 0) {
-    level2_rev_wave(Dp, Bp, INNER, ib1);
+    level2_rev_wave(Dp_, Bp_, INNER, ib1);
     wave_sync();
     // R-bar -= (D-bar_1 + D-bar_1^T) R   (rows [32, w) x cols [0, 32), K = ib1)
     const int nt = (ib1 + 15) / 16;
@@ -497,7 +488,7 @@ __device__ void wave_diag_rev_64(double *Dp, double *Bp, const double *Dinv, int
     }
     wave_sync();
   }
-  level2_rev_wave(Dp, Bp, 0, ib0);
+  level2_rev_wave(Dp_, Bp_, 0, ib0);
   wave_sync();
 }
 
@@ -750,7 +741,8 @@ __device__ __forceinline__ bool b2_rev_skip(const B2Args &a, int i) {
 // block per reverse step.  Thread (h, r) = (wave, lane) walks rows k + h, k + h + 4, ... of column
 // j + r (coalesced, sixteen loads in flight) and the four partial sums are added in a fixed order.
 // tb and pt: B2_NB and 4 * B2_NB doubles of LDS.
-__device__ void b2_gp_w(const B2Args &a, int p, int n, int b, double *tb, double *pt) {
+__device__ void b2_gp_w(const B2Args &a, int p, int n, int b, double *tb_, double *pt_) {
+  lds_double *tb = lds_view(tb_), *pt = lds_view(pt_);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = a.order[p];
   const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j;

@@ -37,6 +37,13 @@ __device__ __forceinline__ double *as_lds(double *p) {
   return (double *)(__attribute__((address_space(3))) double *)p;
 }
 
+// An LDS array seen through an LDS-typed pointer.  Indexing it compiles to ds_read / ds_write even
+// inside a function the compiler keeps out of line, whose pointer parameters are generic (through
+// those, LDS accesses become flat loads and stores, which wait on the vector-memory counter).
+typedef __attribute__((address_space(3))) double lds_double;
+__device__ __forceinline__ lds_double *lds_view(double *p) { return (lds_double *)p; }
+__device__ __forceinline__ const lds_double *lds_view(const double *p) { return (const lds_double *)p; }
+
 // Uniform copy of lane `src`'s value (two 32-bit v_readlane).  src must be wave-uniform.
 __device__ __forceinline__ double wave_bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -175,7 +182,9 @@ __device__ __forceinline__ int tile_col() { return threadIdx.x & 15; }
 // lane j's column with v_readlane.  Lane j scales its column by 1/d before the broadcast, and a
 // lane l > j holds D[j][l] = 0 (the zero-padded upper triangle), so every lane runs the same two
 // FMAs per broadcast element with no per-element select.
-__device__ void level2_rev_wave(const double *Dp, double *Bp, int a, int ib) {
+__device__ void level2_rev_wave(const double *Dp_, double *Bp_, int a, int ib) {
+  const lds_double *Dp = lds_view(Dp_);
+  lds_double *Bp = lds_view(Bp_);
   const int c = threadIdx.x & 63;
   double Dc[INNER], Bc[INNER];
 #pragma unroll
@@ -226,7 +235,9 @@ __device__ void level2_rev_wave(const double *Dp, double *Bp, int a, int ib) {
 // Sec. 4.1 chol_unblocked_fwd on the block at offset a: lane i < 32 owns row i of D and D-dot.
 // For j = 0 .. 31:  d-dot <- (d-dot/2 - r r-dot^T) / d;
 // c-dot <- (c-dot - B-dot r^T - B r-dot^T - c d-dot) / d.
-__device__ void level2_fwd_wave(const double *Dp, double *Ap, int a, int ib) {
+__device__ void level2_fwd_wave(const double *Dp_, double *Ap_, int a, int ib) {
+  const lds_double *Dp = lds_view(Dp_);
+  lds_double *Ap = lds_view(Ap_);
   const int i = threadIdx.x & 63;
   double Dr[INNER], Ar[INNER];
 #pragma unroll
@@ -265,103 +276,121 @@ __device__ void level2_fwd_wave(const double *Dp, double *Ap, int a, int ib) {
     if ((i < ib) && (l <= i)) Ap[pidx(a + i, a + l)] = Ar[l];
 }
 
-// Sec. 4.1 chol_unblocked (DPOTF2) on the block at offset a, in place: lane i < 32 owns row i.
-// Column j: d <- sqrt(d - r r^T); c <- (c - B r^T) / d.  Returns (uniformly) the first column
-// with a non-positive or NaN pivot, or -1.
-__device__ int level2_potf2_wave(double *Dp, int a, int ib) {
+// Orders this wave's LDS writes before its later LDS reads (a wave's LDS accesses are processed in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// d = sqrt(x) and rd = 1/sqrt(x) from v_rsq_f64 and two Goldschmidt steps (each about doubles the
+// correct bits), with a last Newton correction of d; inputs below 2^-767 are scaled by 2^256 first
+// so the steps stay in range.  A pivot column is then scaled by the multiplication with rd (as
+// LAPACK's DPOTF2 scales by 1/L_jj).  x = 0, x < 0 and NaN give NaN in both.
+__device__ __forceinline__ void sqrt_rsqrt(double x, double &d, double &rd) {
+  const bool tiny = x < 0x1p-767;
+  const double xs = tiny ? __builtin_ldexp(x, 256) : x;
+  const double y = __builtin_amdgcn_rsq(xs);
+  double g = xs * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, xs), h, g);
+  d = tiny ? __builtin_ldexp(g, -128) : g;
+  rd = tiny ? __builtin_ldexp(2.0 * h, 128) : 2.0 * h;
+}
+
+// Sec. 4.1 chol_unblocked (DPOTF2) on the 32 columns [a, a + ib) of the packed block, for the
+// diagonal rows [a, a + ib) and up to 32 rows below them, by one wave: lane i < ib holds diagonal
+// row a + i, lane 32 + t holds row rb + t (if rb + t < w).  Right-looking: at column j the pivot
+// row's lane gives d = sqrt(D_jj), every lane scales its entry by 1/d, and each lane then
+// subtracts its multiple of column j from its later entries, taking column j's entry of row k from
+// lane k (v_readlane).  Rows below the diagonal block go through the same steps as the diagonal
+// rows with i > j, so the panel below comes out solved (C <- C D^-T) in the same pass.  Several
+// waves can share one diagonal block, each with its own rows below; every wave then holds the
+// diagonal rows and only the one with diag_out writes them back.  WG: all threads of the
+// workgroup call this (a barrier separates the loads from the stores); otherwise only the wave.
+// Returns (uniformly) the first column < ib with a non-positive or NaN pivot, or -1.
+template <bool WG>
+__device__ int panel_core32(double *Dp_, int a, int ib, int w, int rb, bool diag_out) {
+  lds_double *Dp = lds_view(Dp_);
   const int i = threadIdx.x & 63;
+  const bool low = i >= INNER;
+  const int row = low ? rb + (i - INNER) : a + i;
+  const bool own = low ? row < w : i < ib;
   double Dr[INNER];
 #pragma unroll
-  for (int l = 0; l < INNER; ++l) {
-    const bool ok = (i < ib) && (l <= i);
-    Dr[l] = ok ? Dp[pidx(a + i, a + l)] : (l == i ? 1.0 : 0.0);
-  }
+  for (int l = 0; l < INNER; ++l) Dr[l] = (own && l < ib && (low || l <= i)) ? Dp[pidx(row, a + l)] : 0.0;
+  if (WG) __syncthreads();
+  else wave_sync();
   int bad = -1;
 #pragma unroll
   for (int j = 0; j < INNER; ++j) {
-    double p0 = 0.0, p1 = 0.0;
+    const double piv = wave_bcast(Dr[j], j);
+    if (bad < 0 && j < ib && !(piv > 0.0)) bad = j;
+    double d, rd;
+    sqrt_rsqrt(piv, d, rd);
+    Dr[j] = (i == j) ? d : Dr[j] * rd;
 #pragma unroll
-    for (int l = 0; l < j; ++l) {
-      const double r = wave_bcast(Dr[l], j);
-      if (l & 1) p1 = fma(Dr[l], r, p1);
-      else p0 = fma(Dr[l], r, p0);
-    }
-    const double s = Dr[j] - (p0 + p1);
-    const double piv = wave_bcast(s, j);
-    if (bad < 0 && !(piv > 0.0) && j < ib) bad = j;
-    const double d = sqrt(piv);
-    Dr[j] = (i > j) ? s / d : ((i == j) ? d : Dr[j]);
+    for (int k = j + 1; k < INNER; ++k) Dr[k] = fma(-Dr[j], wave_bcast(Dr[j], k), Dr[k]);
   }
 #pragma unroll
   for (int l = 0; l < INNER; ++l)
-    if ((i < ib) && (l <= i)) Dp[pidx(a + i, a + l)] = Dr[l];
+    if (own && l < ib && (low || (diag_out && l <= i))) Dp[pidx(row, a + l)] = Dr[l];
   return bad;
 }
 
-// Row r (> the inner block) of the panel solve  X D^T = C  against the lower-triangular inner
-// block D = Dp[a:a+ib, a:a+ib], in place in packed Dp.  Called by the lane that owns row r.
-__device__ __noinline__ void panel_solve_row(double *Dp, int a, int ib, int r) {
-  Dp = as_lds(Dp);
+// Inverse of the lower-triangular ib x ib block (ib <= 32) of Dp at offset a, by ONE wave (D X = I
+// by forward substitution): lane c < ib builds column c of X, x_r = (delta_rc - sum_{l<r} D_rl x_l)
+// / D_rr, reading row r of D with LDS loads whose address is the same in every lane (broadcasts);
+// x_l = 0 for l < c comes out by itself.  Row r's loads wait (through an empty asm that takes
+// x_{r-2}) until row r - 2 is done, which keeps the compiler from hoisting the whole triangle's
+// loads into registers.  Writes the lower triangle of X into packed Xp at offset a.
+__device__ void wave_trinv32(const double *Dp, double *Xp_, int a, int ib) {
+  const lds_double *D = lds_view(Dp);
+  lds_double *Xp = lds_view(Xp_);
+  const int c = threadIdx.x & 63;
+  const double inv_own = (c < ib) ? 1.0 / D[pidx(a + c, a + c)] : 0.0;
   double x[INNER];
-  const int base = pidx(r, a);
 #pragma unroll
-  for (int c = 0; c < INNER; ++c) x[c] = (c < ib) ? Dp[base + c] : 0.0;
+  for (int r = 0; r < INNER; ++r) {
+    x[r] = 0.0;
+    if (r < ib) {
+      int base = pidx(a + r, a);
+      if (r >= 2) asm volatile("" : "+v"(base) : "v"(x[r - 2]));
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-  for (int c = 0; c < INNER; ++c) {
-    if (c < ib) {
-      const int rc = pidx(a + c, a);
-      double s0 = x[c], s1 = 0.0;
-#pragma unroll
-      for (int l = 0; l < c; ++l) {
-        if (l & 1) s1 = fma(-x[l], Dp[rc + l], s1);
-        else s0 = fma(-x[l], Dp[rc + l], s0);
+      for (int l = 0; l < r; ++l) {
+        const double dv = D[base + l];
+        if ((l & 3) == 0) s0 = fma(dv, x[l], s0);
+        else if ((l & 3) == 1) s1 = fma(dv, x[l], s1);
+        else if ((l & 3) == 2) s2 = fma(dv, x[l], s2);
+        else s3 = fma(dv, x[l], s3);
       }
-      x[c] = (s0 + s1) / Dp[rc + c];
+      x[r] = (((r == c) ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3))) * wave_bcast(inv_own, r);
     }
   }
 #pragma unroll
-  for (int c = 0; c < INNER; ++c)
-    if (c < ib) Dp[base + c] = x[c];
-}
-
-// Inverse of the lower-triangular 32 x 32 block of Dp at offset a, by ONE wave (D X = I by
-// forward substitution).  Lane i < 32 holds row i of D; lane c < 32 builds column c of X, taking
-// D[i][l] from lane i with v_readlane.  Writes the lower triangle of X into packed Xp at offset a.
-__device__ void wave_trinv32(const double *Dp, double *Xp, int a, int ib) {
-  const int lane = threadIdx.x & 63;
-  double Dr[INNER], Xc[INNER];
-#pragma unroll
-  for (int l = 0; l < INNER; ++l) {
-    const bool ok = (lane < ib) && (l <= lane);
-    Dr[l] = ok ? Dp[pidx(a + lane, a + l)] : (l == lane ? 1.0 : 0.0);
-  }
-#pragma unroll
-  for (int i = 0; i < INNER; ++i) {
-    double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
-#pragma unroll
-    for (int l = 0; l < i; ++l) {
-      const double dil = wave_bcast(Dr[l], i);
-      if (l & 1) s1 = fma(-dil, Xc[l], s1);
-      else s0 = fma(-dil, Xc[l], s0);
-    }
-    const double inv_dii = 1.0 / wave_bcast(Dr[i], i);
-    Xc[i] = (i >= lane) ? (s0 + s1) * inv_dii : 0.0;
-  }
-#pragma unroll
-  for (int i = 0; i < INNER; ++i)
-    if ((lane < ib) && (i < ib) && (i >= lane)) Xp[pidx(a + i, a + lane)] = Xc[i];
+  for (int r = 0; r < INNER; ++r)
+    if (c < ib && r < ib && r >= c) Xp[pidx(a + r, a + c)] = x[r];
 }
 
 // X = D^-1 for the whole w x w block (packed; the workgroup cooperates).  The 32 x 32 diagonal
 // blocks are inverted one per wave; block row p then follows from the rows above it:
 //   X_pq = -X_pp (sum_{q <= l < p} D_pl X_lq)      (q < p),
 // each product as MFMA tiles.  Ends with a barrier.
-__device__ void block_inverse(const double *Dp, double *Xp, int w) {
+__device__ void block_inverse(const double *Dp_, double *Xp_, int w) {
+  const lds_double *Dp = lds_view(Dp_);
+  lds_double *Xp = lds_view(Xp_);
   const int wave = threadIdx.x >> 6;
   const int nI = (w + INNER - 1) / INNER;
   for (int p = wave; p < nI; p += DIAG_WAVES) {
     const int a = p * INNER;
-    wave_trinv32(Dp, Xp, a, min(INNER, w - a));
+    wave_trinv32(Dp_, Xp_, a, min(INNER, w - a));
   }
   __syncthreads();
   for (int p = 1; p < nI; ++p) {
@@ -725,7 +754,6 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
   for (int a = 0; a < w; a += INNER) {
     const int b = min(w, a + INNER);
     const int ib = b - a;
-    const int rest = w - b;
     if (a > 0) {
       // rows [a, w) x cols [a, b) -= [R; B] R^T  (K = a)
       const int tr = (w - a + 15) / 16, tc = (ib + 15) / 16;
@@ -743,19 +771,10 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
       }
       __syncthreads();
     }
-    if (wave == 0) {
-      const int f = level2_potf2_wave(Dp, a, ib);
-      if ((tid & 63) == 0 && f >= 0 && bad < 0) bad = a + f;
-    }
+    // the diagonal rows in every wave, the rows below split 32 per wave (w - b <= 96)
+    const int f = panel_core32<true>(Dp, a, ib, w, b + INNER * wave, wave == 0);
+    if (tid == 0 && f >= 0 && bad < 0) bad = a + f;
     __syncthreads();
-    if (rest > 0) {
-      // C <- C D_i^-T by forward substitution, one row of C per lane (rows are independent):
-      // x_c = (c_c - sum_{l < c} x_l D_i[c][l]) / D_i[c][c]; every lane reads the same D_i entry,
-      // an LDS broadcast.  rest <= 96, so waves 0 and 1 cover all rows.
-      const int r = b + tid;
-      if (tid < rest) panel_solve_row(Dp, a, ib, r);
-      __syncthreads();
-    }
   }
   if (tid == 0 && bad >= 0 && *info == 0) *info = (int)(col0 + bad + 1);
   block_inverse(Dp, Xp, w);
