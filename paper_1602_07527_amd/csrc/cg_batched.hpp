@@ -78,7 +78,7 @@ __device__ __noinline__ void nl_diag_fwd_block(int w, const double *Ld, int64_t 
 }
 __device__ __noinline__ void nl_potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int nb, int *info,
                                             int64_t col0, double *Dp, double *Xp, int &bad) {
-  potf2_block(w, Ad, lda, Dinv, nb, nb, 0, info, col0, as_lds(Dp), as_lds(Xp), bad);
+  potf2_block(w, Ad, lda, Dinv, nb, nb, 0, info, col0, as_lds(Dp), bad);
 }
 
 // C = alpha op(A) op(B) + beta Cin over all 128 x 128 output tiles, by the whole workgroup.

@@ -446,6 +446,76 @@ __device__ void block_inverse(const double *Dp_, double *Xp_, int w) {
   }
 }
 
+// X = D^-1 for the whole w x w block IN PLACE (packed; the workgroup cooperates; whatever still
+// needs D must have read it first).  The 32 x 32 diagonal blocks are inverted in place, one per
+// wave (each wave reads its block whole before it writes); block column p of X then follows from
+// the block columns right of it, right to left:
+//   X_qp = -(sum_{p < r <= q} X_qr D_rp) X_pp      (q > p),
+// the sum first written over D's own block column p below the diagonal (which it consumes) and
+// then multiplied by X_pp, each product as MFMA tiles.  Half the LDS of block_inverse, which lets
+// the POTF2 kernel share a compute unit with a contraction workgroup.  Ends with a barrier.
+__device__ void block_inverse_inplace(double *Dp_, int w) {
+  lds_double *Dp = lds_view(Dp_);
+  const int wave = threadIdx.x >> 6;
+  const int nI = (w + INNER - 1) / INNER;
+  for (int p = wave; p < nI; p += DIAG_WAVES) {
+    const int a = p * INNER;
+    wave_trinv32(Dp_, Dp_, a, min(INNER, w - a));
+  }
+  __syncthreads();
+  for (int p = nI - 2; p >= 0; --p) {
+    const int ap = p * INNER, bp = ap + INNER;  // block p is full: only the last block can be short
+    const int tr = (w - bp + 15) / 16, tc = INNER / 16;
+    dbl4 acc[3];
+    // Y = X[bp:w, bp:w] D[bp:w, ap:bp]   (tiles of rows [bp, w) x columns [ap, bp))
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = bp + (t / tc) * 16, c0 = ap + (t % tc) * 16;
+      auto A = [&](int i, int k) { const int r = r0 + i, c = bp + k; return (r < w && c <= r) ? Dp[pidx(r, c)] : 0.0; };
+      auto B = [&](int k, int j) { return Dp[pidx(bp + k, c0 + j)]; };
+      acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, min(w, r0 + 16) - bp);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = bp + (t / tc) * 16, c0 = ap + (t % tc) * 16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + tile_row(e);
+        if (r < w) Dp[pidx(r, c0 + tile_col())] = acc[sl][e];
+      }
+    }
+    __syncthreads();
+    // X_qp = -Y X_pp
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = bp + (t / tc) * 16, c0 = ap + (t % tc) * 16;
+      auto A = [&](int i, int k) { const int r = r0 + i; return (r < w) ? Dp[pidx(r, ap + k)] : 0.0; };
+      auto B = [&](int k, int j) { const int c = c0 + j; return (ap + k >= c) ? Dp[pidx(ap + k, c)] : 0.0; };
+      acc[sl] = tile_mma(dbl4{0, 0, 0, 0}, A, B, INNER);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      const int t = wave + DIAG_WAVES * sl;
+      if (t >= tr * tc) continue;
+      const int r0 = bp + (t / tc) * 16, c0 = ap + (t % tc) * 16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + tile_row(e);
+        if (r < w) Dp[pidx(r, c0 + tile_col())] = -acc[sl][e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Write the packed lower triangle of a w x w block into the ext x ext region at dst (row-major,
 // leading dimension ld, ext <= 128), zero elsewhere in the region, and zero `right` (<= 128) more
 // columns to the right of the region in its rows (the part of a wider block's inverse above the
@@ -739,14 +809,15 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const dou
 
 // ---------------------------------------------------------------------------------------------
 // D <- chol_unblocked(D) (Sec. 4.1, DPOTF2) for one w x w diagonal block (w <= 128), left-looking
-// over 32-column inner blocks [a, b):  [D_i; C] -= [R; B] R^T;  D_i <- Level-2 factor (one wave);
-// C <- C D_i^-T.  Then D^-1 for the panel solve.  The first non-positive (or NaN) pivot sets
-// *info = col0 + column + 1 unless an earlier block already set it; the sweep then continues
-// with NaN so that every kernel still exits normally.
+// over 32-column inner blocks [a, b):  [D_i; C] -= [R; B] R^T (MFMA tiles);  then D_i <- its
+// Level-2 factor and C <- C D_i^-T in one pass of panel_core32 (every wave holds D_i, the rows of
+// C are split 32 per wave).  Then D^-1 for the panel solve, formed in place after L is stored.
+// The first non-positive (or NaN) pivot sets *info = col0 + column + 1 unless an earlier block
+// already set it; the sweep then continues with NaN so that every kernel still exits normally.
 // In/out: A + (j, j) (lower triangle in, factor out, strict upper set to 0).  Out: Dinv (w x w
-// inverse, ld nb, zero above the diagonal).
+// inverse, ld nb, zero above the diagonal).  Dp: packed LDS block (DIAG_PACKED doubles).
 __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int64_t ld, int ext,
-                                            int right, int *info, int64_t col0, double *Dp, double *Xp, int &bad) {
+                                            int right, int *info, int64_t col0, double *Dp, int &bad) {
   const int tid = threadIdx.x, wave = tid >> 6;
   load_packed2(Dp, Ad, lda, nullptr, nullptr, 0, w);
   if (tid == 0) bad = -1;
@@ -777,21 +848,23 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
     __syncthreads();
   }
   if (tid == 0 && bad >= 0 && *info == 0) *info = (int)(col0 + bad + 1);
-  block_inverse(Dp, Xp, w);
+  // L out first (its stores drain while the inverse is formed in place over it)
   store_block(Ad, lda, w, w, [&](int r, int c) { return (c <= r) ? Dp[pidx(r, c)] : 0.0; });
-  store_lower_region(Dinv, ld, ext, Xp, w, right);
+  __syncthreads();
+  block_inverse_inplace(Dp, w);
+  store_lower_region(Dinv, ld, ext, Dp, w, right);
   __syncthreads();
 }
 
 // POTF2 of one w x w block (w <= 128) with its inverse written to the ext x ext region at Dinv
-// (leading dimension ld) and `right` zero columns beside it (see store_lower_region).
+// (leading dimension ld) and `right` zero columns beside it (see store_lower_region).  66 KB of
+// LDS: it fits beside one 64 KB contraction workgroup on a compute unit.
 __global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, int64_t lda, double *Dinv,
                                                              int64_t ld, int ext, int right, int *info,
                                                              int64_t col0) {
   __shared__ double Dp[DIAG_PACKED];
-  __shared__ double Xp[DIAG_PACKED];
   __shared__ int bad;
-  potf2_block(w, Ad, lda, Dinv, ld, ext, right, info, col0, Dp, Xp, bad);
+  potf2_block(w, Ad, lda, Dinv, ld, ext, right, info, col0, Dp, bad);
 }
 
 // Zero the strict upper triangle of an n x n matrix.
