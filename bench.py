@@ -545,6 +545,10 @@ def main():
             pts = []
             for rate in (400.0, 600.0, 800.0, 1000.0, 1200.0):
                 log(f"[bench] serving saturation {mode} at {rate:g}/s")
+                # every point starts from an empty allocator cache (the previous point's blocks
+                # are released outside the timed replay)
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
                 srv = serve.Server(dev, hbm_budget=64 << 30, precision=mode)
                 done, wall = serve.replay(srv, tr["t"][:SAT_REQ] * (200.0 / rate), make_sat)
                 lat = np.array([r.latency for r in done]) * 1e3
