@@ -117,7 +117,9 @@ extern "C" {
  *                        halving of the diagonal) in one workgroup per block, on a side stream
  *                        overlapped with the next step's trailing products.
  *   CHOL_DIAG_AUTO     : the library's choice; currently the symbolic form for every n and nb,
- *                        the faster of the two on MI355X at n = 256 to 16384, nb = 32, 64, 128. */
+ *                        the faster of the two on MI355X at n = 256 to 16384, nb = 32 to 128
+ *                        (the Level-2 variant holds blocks of at most 128: nb > 128 with
+ *                        CHOL_DIAG_LEVEL2 returns CHOL_ERR_UNSUPPORTED). */
 #define CHOL_DIAG_AUTO 0
 #define CHOL_DIAG_SYMBOLIC 1
 #define CHOL_DIAG_LEVEL2 2
@@ -245,18 +247,25 @@ int chol_factor_fwd(int precision, int64_t n, void *A, int64_t lda, void *D, int
                     void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Batched forms: many independent problems in ONE persistent launch (Sec. 4.2 algorithms applied
- * per problem, nb = 128; a problem with n <= 128 is one diagonal block and stays in LDS).  All
- * per-problem arguments are DEVICE arrays with `batch` entries: n[b] is the size of problem b,
- * A[b] (and L[b], y[b], G[b]) are device pointers to its row-major data with leading dimensions
- * lda[b] (ldl[b], ldg[b]) >= n[b].  n_max (host value, <= 512) bounds every n[b]; n_max above 512
- * returns CHOL_ERR_UNSUPPORTED.  A problem whose size is outside [0, n_max] or whose leading
- * dimension is smaller than its size is skipped (its info entry, where there is one, becomes -1).
- * Problems are processed largest first; each problem's result does not depend on the batch it is
- * in.  Workspace: chol_batched_workspace_bytes(precision, batch, n_max) bytes, 256-byte aligned
- * (about 1.2 MB of scratch per workgroup, one workgroup per problem up to 256: about 300 MB for
- * 256 or more problems; CHOL_PREC_F32 adds 16 * n_max^2 bytes of FP64 staging per workgroup,
- * 1.07 GB for 256 workgroups at n_max = 512).
+ * Batched forms: many independent problems per call, Sec. 4.2's blocked algorithms applied per
+ * problem.  FP64 chol_factor_batched, chol_rev_batched, chol_factor_rev_batched and
+ * chol_gp_nll_batched run step-synchronous on 64-wide blocks: a plan built on the device orders
+ * the problems largest first, then each block step is one grouped launch per kind over every
+ * problem that has that step (block-column updates and panel products as 64 x 64 MFMA tiles,
+ * diagonal blocks one wave each).  chol_fwd_batched and FP32 storage run one persistent launch
+ * (one workgroup per problem at a time, nb = 128).  All per-problem arguments are DEVICE arrays
+ * with `batch` entries: n[b] is the size of problem b, A[b] (and L[b], y[b], G[b]) are device
+ * pointers to its row-major data with leading dimensions lda[b] (ldl[b], ldg[b]) >= n[b].  n_max
+ * (host value, <= 512) bounds every n[b]; n_max above 512 returns CHOL_ERR_UNSUPPORTED.  A problem
+ * whose size is outside [0, n_max] or whose leading dimension is smaller than its size is skipped
+ * (its info entry, where there is one, becomes -1).  Each problem's result does not depend on the
+ * batch it is in.  Workspace: chol_batched_workspace_bytes(precision, batch, n_max) bytes, 256-byte
+ * aligned: for FP64 the larger of the two paths' needs -- the step-synchronous path's plan, the
+ * inverses of every problem's 64-blocks and two vectors per problem (about 528 * n_max bytes per
+ * problem: 554 MB for 2048 problems at n_max = 512) and the persistent kernel's scratch (about
+ * 1.2 MB per workgroup, one workgroup per problem up to 256: 304 MB); CHOL_PREC_F32 takes the
+ * persistent kernel's scratch plus 16 * n_max^2 bytes of FP64 staging per workgroup (1.38 GB for
+ * 256 or more problems at n_max = 512).
  * Semantics per problem are those of the single-matrix calls above.
  */
 size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max);
