@@ -364,18 +364,24 @@ __host__ __device__ constexpr int waitcnt_vm(int n) {  // s_waitcnt immediate: v
   return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
 }
 
-template <bool AT, bool BT, int TAG, int CP = CP_F64, bool P2 = false>
-__global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p) {
+// WIDE: 128 x 256 output tiles (each wave 64 x 64): the A strip of a K-tile is loaded once for
+// both 128-column halves, 96 KB of LDS and up to 256 registers, one workgroup per compute unit.
+template <bool AT, bool BT, int TAG, int CP = CP_F64, bool P2 = false, bool WIDE = false>
+__global__ __launch_bounds__(DMA_THREADS, WIDE ? 2 : 4) void gemm_f64_dma_kernel(GemmArgs p) {
   typedef Mfma<CP> MM;
-  constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = DMA_BK, TILE = BM * BK;
+  constexpr int BM = GEMM_BM, BN = WIDE ? 2 * GEMM_BN : GEMM_BN, BK = DMA_BK;
+  constexpr int TILE_A = BM * BK, TILE_B = BN * BK, STAGE = TILE_A + TILE_B;
   constexpr int WM = 2, WN = 4, NW = WM * WN;
-  constexpr int NQ = TILE * 8 / 1024 / NW;     // 1 KB DMA instructions per wave per operand per tile
-  static_assert(NQ * NW * 1024 == TILE * 8, "tile must split evenly over the waves");
+  constexpr int NQA = TILE_A * 8 / 1024 / NW;  // 1 KB DMA instructions per wave per K-tile of A
+  constexpr int NQB = TILE_B * 8 / 1024 / NW;  // ... and of B
+  static_assert(NQA * NW * 1024 == TILE_A * 8 && NQB * NW * 1024 == TILE_B * 8,
+                "tiles must split evenly over the waves");
   static_assert(BK % 8 == 0, "paired fragment reads take k in groups of 8");
   constexpr int CH = BK / 2;                   // 16-byte chunks in a K-contiguous row
   constexpr int RPI = 64 / CH;                 // K-contiguous rows per DMA instruction
+  constexpr int NH = BN / GEMM_BN;             // 1 KB pieces of an N-contiguous row of B
   constexpr int TMW = BM / WM / 16, TNW = BN / WN / 16;
-  __shared__ __attribute__((aligned(16))) double smem[2 * 2 * TILE];
+  __shared__ __attribute__((aligned(16))) double smem[2 * STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   // Work of this workgroup: one (tile, K-range) piece under uniform splits, or the pieces of its
@@ -402,14 +408,14 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
   // wave-uniform.  K is a multiple of BK, so no K-tile straddles the two pairs.  P2 (a second
   // operand pair, in A2 and B2) is a template parameter so single products carry no pair logic.
   constexpr int NP = P2 ? 2 : 1;
-  uint32_t offA[NP][NQ], offB[NP][NQ];
-  int ldsA[NQ], ldsB[NQ];
+  uint32_t offA[NP][NQA], offB[NP][NQB];
+  int ldsA[NQA], ldsB[NQB];
 #pragma unroll
   for (int h = 0; h < NP; ++h) {
     const int64_t la = h ? p.lda2 : p.lda, lb = h ? p.ldb2 : p.ldb;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = wave * NQ + q;
+    for (int q = 0; q < NQA; ++q) {
+      const int i = wave * NQA + q;
       if (!AT) {
         const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
         offA[h][q] = (uint32_t)(r * la * 8 + c * 16);
@@ -418,9 +424,13 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
         offA[h][q] = (uint32_t)(i * la * 8 + lane * 16);
         ldsA[q] = i * BM;
       }
-      if (!BT) {
-        offB[h][q] = (uint32_t)(i * lb * 8 + lane * 16);
-        ldsB[q] = i * BN;
+    }
+#pragma unroll
+    for (int q = 0; q < NQB; ++q) {
+      const int i = wave * NQB + q;
+      if (!BT) {  // K-row i / NH, 128-column piece i % NH
+        offB[h][q] = (uint32_t)((i / NH) * lb * 8 + (i % NH) * 1024 + lane * 16);
+        ldsB[q] = (i / NH) * BN + (i % NH) * GEMM_BN;
       } else {
         const int r = i * RPI + lane / CH, c = (lane % CH) ^ (r % CH);
         offB[h][q] = (uint32_t)(r * lb * 8 + c * 16);
@@ -437,13 +447,14 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
     const int64_t la = h ? p.lda2 : p.lda, lb = h ? p.ldb2 : p.ldb;
     const char *ga = (const char *)(AT ? Ab + (int64_t)kl * la + m0 : Ab + (int64_t)m0 * la + kl);
     const char *gb = (const char *)(BT ? Bb + (int64_t)n0 * lb + kl : Bb + (int64_t)kl * lb + n0);
-    double *as = smem + (2 * st) * TILE;
-    double *bs = smem + (2 * st + 1) * TILE;
+    double *as = smem + st * STAGE;
+    double *bs = as + TILE_A;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < NQA; ++q)
       __builtin_amdgcn_global_load_lds((const void *)(ga + offA[P2 ? h : 0][q]), (lds_void *)(as + ldsA[q]), 16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < NQB; ++q)
       __builtin_amdgcn_global_load_lds((const void *)(gb + offB[P2 ? h : 0][q]), (lds_void *)(bs + ldsB[q]), 16, 0, 0);
-    }
   };
 
   const int fk = lane >> 4, fi = lane & 15;
@@ -479,8 +490,8 @@ __global__ __launch_bounds__(DMA_THREADS, 4) void gemm_f64_dma_kernel(GemmArgs p
     __builtin_amdgcn_s_waitcnt(W0);
     __builtin_amdgcn_s_barrier();
     if (kt + 1 < nkt) issue(kt + 1, (kt + 1) & 1);
-    const double *as = smem + (2 * (kt & 1)) * TILE;
-    const double *bs = smem + (2 * (kt & 1) + 1) * TILE;
+    const double *as = smem + (kt & 1) * STAGE;
+    const double *bs = as + TILE_A;
     if constexpr (cp_split(CP)) {
       // one 16-deep bf16 K-group per K-tile: the lanes of slot fk take k = 4 fk .. 4 fk + 3,
       // i.e. 16-byte chunks 2 fk and 2 fk + 1 of a K-contiguous row
@@ -647,20 +658,21 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(int M, int N, const 
 // Sum of the stream-K pieces: element (m, n) lies in tile t = m / 128 + (n / 128) tm, whose units
 // [t KT, (t+1) KT) were taken by workgroups wf .. wl (w takes [w T / W, (w+1) T / W)); their partial
 // slots w + t are added in workgroup order, so the result is bitwise reproducible.
-__global__ __launch_bounds__(256) void reduce_streamk_kernel(int M, int N, const double *P, int64_t sstride,
-                                                             int64_t W, int64_t KT, int tm, double alpha,
-                                                             const double *Cin, int64_t ldcin, double beta,
-                                                             double *C, int64_t ldc, double *Cm, int64_t ldcm) {
+__global__ __launch_bounds__(256) void reduce_streamk_kernel(int M, int N, int bn, const double *P,
+                                                             int64_t sstride, int64_t W, int64_t KT, int tm,
+                                                             double alpha, const double *Cin, int64_t ldcin,
+                                                             double beta, double *C, int64_t ldc, double *Cm,
+                                                             int64_t ldcm) {
   const int64_t total = (int64_t)M * N;
-  const int64_t T = KT * tm * ((N + GEMM_BN - 1) / GEMM_BN);
+  const int64_t T = KT * tm * ((N + bn - 1) / bn);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int m = (int)(e / N), n = (int)(e % N);
-    const int64_t t = m / GEMM_BM + (int64_t)(n / GEMM_BN) * tm;
+    const int64_t t = m / GEMM_BM + (int64_t)(n / bn) * tm;
     // last workgroup whose range starts at or before unit x: floor(((x + 1) W - 1) / T)
     const int64_t wf = ((t * KT + 1) * W - 1) / T;
     const int64_t wl = (((t + 1) * KT) * W - 1) / T;
-    const double *src = P + (wf + t) * sstride + (int64_t)(m % GEMM_BM) * GEMM_BN + (n % GEMM_BN);
+    const double *src = P + (wf + t) * sstride + (int64_t)(m % GEMM_BM) * bn + (n % bn);
     double s = 0.0;
     for (int64_t w = wf; w <= wl; ++w, src += sstride) s += *src;
     double v = alpha * s;

@@ -38,6 +38,7 @@ constexpr int SK_WGS = 480;
 constexpr int SK_WGS_SHORT = 448;
 constexpr int64_t SK_SHORT_KTILES = 48;
 constexpr int64_t PART_SLOTS = 2 * TARGET_WGS;  // 128 x 128 partial tiles per buffer
+constexpr bool WIDE_TILES = true;               // 128 x 256 tiles for the 256-wide sweep contractions
 constexpr int64_t TILE_ELEMS = (int64_t)cg::GEMM_BM * cg::GEMM_BN;
 
 // A buffer of 128 x 128 partial tiles for split-K and stream-K products: base and capacity in
@@ -173,7 +174,15 @@ bool nb_ok(int nb) { return nb == 0 || (nb >= 16 && nb <= NB_MAX && nb % 16 == 0
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 template <int TAG, int CP>
-void launch_gemm_tag(bool at, bool bt, bool fast, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+void launch_gemm_tag(bool at, bool bt, bool fast, bool wide, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+  if constexpr (CP == cg::CP_F64 && (TAG == 1 || TAG == 2)) {
+    if (fast && wide) {  // 128 x 256 output tiles (gemm() allows them only here, for A and B row-major or B^T)
+      const dim3 block(cg::DMA_THREADS);
+      if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, true, TAG, CP, false, true>), grid, block, 0, s, p);
+      else hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, false, TAG, CP, false, true>), grid, block, 0, s, p);
+      return;
+    }
+  }
   if (fast && p.A2) {  // paired products (the forward sweep's symmetric updates: B transposed)
     const dim3 block(cg::DMA_THREADS);
     if (!at && bt) hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, true, TAG, CP, true>), grid, block, 0, s, p);
@@ -198,21 +207,22 @@ void launch_gemm_tag(bool at, bool bt, bool fast, dim3 grid, const cg::GemmArgs 
 }
 
 template <int CP>
-void launch_gemm_cp(bool at, bool bt, bool fast, int tag, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+void launch_gemm_cp(bool at, bool bt, bool fast, bool wide, int tag, dim3 grid, const cg::GemmArgs &p,
+                    hipStream_t s) {
   switch (tag) {
-    case 1: launch_gemm_tag<1, CP>(at, bt, fast, grid, p, s); break;
-    case 2: launch_gemm_tag<2, CP>(at, bt, fast, grid, p, s); break;
-    case 3: launch_gemm_tag<3, CP>(at, bt, fast, grid, p, s); break;
-    default: launch_gemm_tag<0, CP>(at, bt, fast, grid, p, s); break;
+    case 1: launch_gemm_tag<1, CP>(at, bt, fast, wide, grid, p, s); break;
+    case 2: launch_gemm_tag<2, CP>(at, bt, fast, wide, grid, p, s); break;
+    case 3: launch_gemm_tag<3, CP>(at, bt, fast, wide, grid, p, s); break;
+    default: launch_gemm_tag<0, CP>(at, bt, fast, wide, grid, p, s); break;
   }
 }
 
-void launch_gemm(bool at, bool bt, bool fast, int tag, int cp, dim3 grid, const cg::GemmArgs &p,
+void launch_gemm(bool at, bool bt, bool fast, bool wide, int tag, int cp, dim3 grid, const cg::GemmArgs &p,
                  hipStream_t s) {
-  if (cp == cg::CP_F32) launch_gemm_cp<cg::CP_F32>(at, bt, fast, tag, grid, p, s);
-  else if (cp == cg::CP_BF16X3) launch_gemm_cp<cg::CP_BF16X3>(at, bt, fast, tag, grid, p, s);
-  else if (cp == cg::CP_BF16X6) launch_gemm_cp<cg::CP_BF16X6>(at, bt, fast, tag, grid, p, s);
-  else launch_gemm_cp<cg::CP_F64>(at, bt, fast, tag, grid, p, s);
+  if (cp == cg::CP_F32) launch_gemm_cp<cg::CP_F32>(at, bt, fast, wide, tag, grid, p, s);
+  else if (cp == cg::CP_BF16X3) launch_gemm_cp<cg::CP_BF16X3>(at, bt, fast, wide, tag, grid, p, s);
+  else if (cp == cg::CP_BF16X6) launch_gemm_cp<cg::CP_BF16X6>(at, bt, fast, wide, tag, grid, p, s);
+  else launch_gemm_cp<cg::CP_F64>(at, bt, fast, wide, tag, grid, p, s);
 }
 
 bool aligned16(const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
@@ -236,9 +246,6 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
                 PartBuf part, int min_kchunk, hipStream_t s, int tag = 0, int cp = cg::CP_F64,
                 Pair2 q = Pair2()) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, cg::GEMM_BN);
-  int tiles = tm * tn;
-  if (lower_only && tm == tn) tiles = (tm * (tm + 1)) / 2;
   const int Kt = q.A2 ? 2 * K : K;  // combined K range
   // The direct-to-LDS kernel needs whole 128 x 128 output tiles, whole 16-deep K-tiles in every
   // split (and in each operand pair), even leading dimensions below 2^21 (32-bit lane offsets)
@@ -247,6 +254,16 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   const bool fast = (M % cg::GEMM_BM == 0) && (N % cg::GEMM_BN == 0) && (K > 0) && (K % cg::DMA_BK == 0) &&
                     dma_ld_ok(lda) && dma_ld_ok(ldb) && aligned16(A) && aligned16(B) &&
                     (!q.A2 || (dma_ld_ok(q.lda2) && dma_ld_ok(q.ldb2) && aligned16(q.A2) && aligned16(q.B2)));
+  // 128 x 256 output tiles (one workgroup per compute unit) for the FP64 sweep contractions whose
+  // output is one 256-wide column of tiles: each K-tile of the tall operand is loaded once for
+  // both halves.
+  const bool wide = WIDE_TILES && fast && !q.A2 && !lower_only && !at && N == 2 * cg::GEMM_BN &&
+                    cp == cg::CP_F64 && (tag == 1 || tag == 2);
+  const int bn = wide ? 2 * cg::GEMM_BN : cg::GEMM_BN;
+  const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, bn);
+  int tiles = tm * tn;
+  if (lower_only && tm == tn) tiles = (tm * (tm + 1)) / 2;
+  const int64_t slots = part.slots / (bn / cg::GEMM_BN);  // partial tiles of this product's size
   const int kstep = fast ? cg::DMA_BK : cg::GEMM_BK;
   // Stream-K on the fast kernel when the output has too few tiles: SK_WGS (or SK_WGS_SHORT)
   // workgroups take equal shares of the (tile, K-tile) units, each piece deep enough
@@ -256,14 +273,15 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   if (part.p && fast && !lower_only && Kt > 0 && tiles >= 2) {
     const int64_t units = (int64_t)tiles * (Kt / cg::DMA_BK);
     skw = part.sk_wgs ? part.sk_wgs : (units < SK_SHORT_KTILES * SK_WGS ? SK_WGS_SHORT : SK_WGS);
+    if (wide) skw /= 2;  // one wide-tile workgroup per compute unit
     skw = std::min<int64_t>(skw, units * cg::DMA_BK / std::max(min_kchunk, cg::DMA_BK));
-    skw = std::min<int64_t>(skw, part.slots - tiles + 1);
+    skw = std::min<int64_t>(skw, slots - tiles + 1);
     if (skw <= tiles) skw = 0;
   }
   int S = 1;
   int kchunk = (int)(cdiv(Kt > 0 ? Kt : 1, kstep) * kstep);
   if (part.p && Kt > 0 && !skw) {
-    int64_t s_want = TARGET_WGS / tiles;
+    int64_t s_want = (wide ? TARGET_WGS / 2 : TARGET_WGS) / tiles;
     s_want = std::min<int64_t>(s_want, cdiv(Kt, min_kchunk));
     s_want = std::min<int64_t>(s_want, part.slots * TILE_ELEMS / ((int64_t)M * N));
     if (s_want > 1) {
@@ -279,8 +297,8 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   p.lower_only = lower_only;
   const dim3 grid = skw ? dim3((unsigned)skw, 1, 1) : dim3(tm, tn, S);
   if (skw) {
-    p.C = part.p; p.ldc = cg::GEMM_BN; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
-    p.Cm = nullptr; p.ldcm = 0; p.split_stride = (int64_t)cg::GEMM_BM * cg::GEMM_BN;
+    p.C = part.p; p.ldc = bn; p.Cin = nullptr; p.ldcin = 0; p.alpha = 1.0; p.beta = 0.0;
+    p.Cm = nullptr; p.ldcm = 0; p.split_stride = (int64_t)cg::GEMM_BM * bn;
     p.sk_wgs = (int)skw; p.sk_kt = Kt / cg::DMA_BK; p.sk_tm = tm; p.sk_tiles = tiles;
   } else if (S == 1) {
     p.C = C; p.ldc = ldc; p.Cin = Cin; p.ldcin = ldcin; p.alpha = alpha; p.beta = beta;
@@ -300,7 +318,7 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
     const double mn = (double)M * (double)N * (lower_only ? 0.5 : 1.0);
     g_prof.bytes[u] = 8.0 * ((double)M * Kt + (double)Kt * N + mn * ((beta != 0.0 ? 2.0 : 1.0) + (Cm ? 1.0 : 0.0)));
   }
-  launch_gemm(at, bt, fast, tag, cp, grid, p, s);
+  launch_gemm(at, bt, fast, wide, tag, cp, grid, p, s);
   if (timed) {
     if (hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s) != hipSuccess) return hipErrorUnknown;
     ++g_prof.used;
@@ -309,8 +327,8 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   const int64_t total = (int64_t)M * N;
   if (e == hipSuccess && skw) {
     const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 4096);
-    hipLaunchKernelGGL(cg::reduce_streamk_kernel, dim3(blocks), dim3(256), 0, s, M, N, (const double *)part.p,
-                       (int64_t)cg::GEMM_BM * cg::GEMM_BN, skw, (int64_t)(Kt / cg::DMA_BK), tm, alpha,
+    hipLaunchKernelGGL(cg::reduce_streamk_kernel, dim3(blocks), dim3(256), 0, s, M, N, bn, (const double *)part.p,
+                       (int64_t)cg::GEMM_BM * bn, skw, (int64_t)(Kt / cg::DMA_BK), tm, alpha,
                        Cin, ldcin, beta, C, ldc, Cm, ldcm);
     return hipGetLastError();
   }
