@@ -12,10 +12,11 @@
 //              R0  X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k]        (64-row tiles, in place)
 //              R1  C-bar / 2 = X D^-1 / 2 with its mirrored store          (64-row tiles)
 //              R2  D-bar = tril(L-bar_D) - tril(C-bar^T C)                  (one workgroup per problem)
-//              R3  chol_unblocked_rev(D, D-bar) with the Phi halving        (one wave per problem)
+//              R3  D-bar <- D^-T Phi(D^T D-bar) D^-1, symmetric part (eqn (symrev) on the
+//                  block: the symbolic form of chol_unblocked_rev)   (one wave per problem)
 // so the block products of the large problems spread over the whole GPU, and the diagonal-block
-// routines (the single-wave Level-2 cores of cg_diag.hpp on 64-wide blocks) run four per compute
-// unit with every wave busy.  Problems are ordered largest first; a plan (order, per-step tile counts
+// routines (POTF2 with the single-wave cores of cg_diag.hpp, the reverse block as MFMA tiles) run
+// four per compute unit with every wave busy.  Problems are ordered largest first; a plan (order, per-step tile counts
 // and their prefix sums) is built on the device once per call, so the host needs only n_max.
 // Every output element is computed by the same operations in the same order whatever the batch,
 // so results are bitwise independent of the other problems.
@@ -403,93 +404,76 @@ __device__ int wave_potf2_64(double *Dp_, double *Xp_, int w) {
   return bad;
 }
 
-// D-bar <- chol_unblocked_rev(D, D-bar) for a w x w block (w <= 64), D packed in Dp, D-bar in Bp,
-// by one wave: the blocked reverse sweep over its two inner blocks from the bottom-right, as
-// diag_rev_core, with D_0^-1 read from Dinv (ld 64).
-__device__ void wave_diag_rev_64(double *Dp_, double *Bp_, const double *Dinv, int w) {
+// The symmetric gradient of a w x w diagonal block (w <= 64) from its symbolic form (eqn (symrev)
+// on the block, as the single-matrix sweeps take by default), by one wave on 16 x 16 MFMA tiles
+// with triangular K ranges:
+//   P = tril(D)^T tril(D-bar)   (lower tiles);   Y = (Phi(P) + Phi(P)^T) / 2, written over D-bar;
+//   then per 16-column block of R = Y D^-1 (four tiles, in registers) the lower tiles of
+//   S = D^-T R, whose B operand is R's accumulator layout as it stands (element e of a tile holds
+//   rows 4e + lane/16, the rows of K-slice e); S is symmetric and goes to both triangles of G.
+// D packed in Dp, D-bar packed in Bp (both overwritten), Dinv row-major 64 x 64 with zeros outside
+// w x w (staged into Dp once P is formed); G: the block's place in the output, leading dim ldg.
+__device__ void wave_diag_rev_sym64(double *Dp_, double *Bp_, const double *Dinv, int w, double *G, int64_t ldg) {
   lds_double *Dp = lds_view(Dp_), *Bp = lds_view(Bp_);
-  const int ib0 = min(INNER, w), ib1 = w - ib0;
-  if (ib1 > 0) {
-    level2_rev_wave(Dp_, Bp_, INNER, ib1);
-    wave_sync();
-    // R-bar -= (D-bar_1 + D-bar_1^T) R   (rows [32, w) x cols [0, 32), K = ib1)
-    const int nt = (ib1 + 15) / 16;
-    dbl4 acc[2][2];
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  dbl4 P[10];
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0, u = 0; ti < 4; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        acc[ti][tj] = dbl4{0, 0, 0, 0};
-        if (ti >= nt) continue;
-        auto A = [&](int i, int k) {
-          const int m = 16 * ti + i;
-          if (m >= ib1 || k >= ib1) return 0.0;
-          return (k < m) ? Bp[pidx(INNER + m, INNER + k)]
-                         : (k > m) ? Bp[pidx(INNER + k, INNER + m)] : 2.0 * Bp[pidx(INNER + m, INNER + m)];
-        };
-        auto B = [&](int k, int j) { return k < ib1 ? Dp[pidx(INNER + k, 16 * tj + j)] : 0.0; };
-        acc[ti][tj] = tile_mma(acc[ti][tj], A, B, ib1);
+    for (int tj = 0; tj <= ti; ++tj, ++u) {
+      dbl4 acc = dbl4{0, 0, 0, 0};
+      const int ci = 16 * ti + li, cj = 16 * tj + li;
+#pragma unroll
+      for (int k0 = 16 * ti; k0 < B2_NB; k0 += 4) {
+        const int k = k0 + lk;
+        const double a = (k < w && k >= ci) ? Dp[pidx(k, ci)] : 0.0;  // D[k][i]
+        const double b = (k < w && k >= cj) ? Bp[pidx(k, cj)] : 0.0;  // D-bar[k][j]
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
-    wave_sync();
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        if (ti >= nt) continue;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int m = 16 * ti + tile_row(e);
-          if (m < ib1) Bp[pidx(INNER + m, 16 * tj + tile_col())] -= acc[ti][tj][e];
-        }
-      }
-    wave_sync();
-    // C-bar <- C-bar D_0^-1   (rows [32, w) x cols [0, 32), K = 32)
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        acc[ti][tj] = dbl4{0, 0, 0, 0};
-        if (ti >= nt) continue;
-        auto A = [&](int i, int k) { const int r = 16 * ti + i; return r < ib1 ? Bp[pidx(INNER + r, k)] : 0.0; };
-        auto B = [&](int k, int j) { return Dinv[k * B2_NB + 16 * tj + j]; };
-        acc[ti][tj] = tile_mma(acc[ti][tj], A, B, INNER);
-      }
-    wave_sync();
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        if (ti >= nt) continue;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = 16 * ti + tile_row(e);
-          if (r < ib1) Bp[pidx(INNER + r, 16 * tj + tile_col())] = acc[ti][tj][e];
-        }
-      }
-    wave_sync();
-    // D-bar_0 -= tril(C-bar^T C)   (three lower 16 x 16 tiles, K = ib1)
-    dbl4 d[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int r0 = (u == 0) ? 0 : 16, c0 = (u == 2) ? 16 : 0;
-      auto A = [&](int i, int k) { return k < ib1 ? Bp[pidx(INNER + k, r0 + i)] : 0.0; };
-      auto B = [&](int k, int j) { return k < ib1 ? Dp[pidx(INNER + k, c0 + j)] : 0.0; };
-      d[u] = tile_mma(dbl4{0, 0, 0, 0}, A, B, ib1);
+      P[u] = acc;
     }
-    wave_sync();
+  wave_sync();
+  wave_load_lower(Dp_, Dinv, B2_NB, w);
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int r0 = (u == 0) ? 0 : 16, c0 = (u == 2) ? 16 : 0;
+  for (int ti = 0, u = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj <= ti; ++tj, ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = r0 + tile_row(e), cc = c0 + tile_col();
-        if (cc <= r) Bp[pidx(r, cc)] -= d[u][e];
+        const int r = 16 * ti + 4 * e + lk, c = 16 * tj + li;
+        if (c <= r) Bp[pidx(r, c)] = 0.5 * P[u][e];
+      }
+  wave_sync();
+  auto Y = [&](int r, int c) { return r >= c ? Bp[pidx(r, c)] : Bp[pidx(c, r)]; };
+  auto X = [&](int r, int c) { return (r >= c && r < w) ? Dp[pidx(r, c)] : 0.0; };  // D^-1 (rows >= w: stale)
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) {
+    if (16 * tj >= w) break;
+    dbl4 R[4];
+#pragma unroll
+    for (int tk = 0; tk < 4; ++tk) {
+      R[tk] = dbl4{0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 16 * tj; k0 < B2_NB; k0 += 4)
+        R[tk] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y(16 * tk + li, k0 + lk), X(k0 + lk, 16 * tj + li), R[tk], 0,
+                                                      0, 0);
+    }
+#pragma unroll
+    for (int ti = tj; ti < 4; ++ti) {
+      dbl4 S = dbl4{0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 16 * ti; k0 < B2_NB; k0 += 4)
+        S = __builtin_amdgcn_mfma_f64_16x16x4f64(X(k0 + lk, 16 * ti + li), R[k0 >> 4][(k0 & 15) >> 2], S, 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 16 * ti + 4 * e + lk, c = 16 * tj + li;
+        if (r < w && c <= r) {
+          G[(int64_t)r * ldg + c] = S[e];
+          if (c < r) G[(int64_t)c * ldg + r] = S[e];
+        }
       }
     }
-    wave_sync();
   }
-  level2_rev_wave(Dp_, Bp_, 0, ib0);
-  wave_sync();
 }
 
 // F1: POTF2 of block s of every problem with more than s blocks, and its inverse, one wave per
@@ -891,9 +875,11 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
   }
 }
 
-// R3: chol_unblocked_rev (Sec. 4.1, Phi halving) on the diagonal block b = nblk - 1 - t of every
-// problem that has it, one wave per problem, from D = L's block and D-bar in the lower triangle of
-// G's block; the symmetric gradient's block goes to both triangles of G.
+// R3: the diagonal block's adjoint (eqn (symrev) on the block: D^-T Phi(D^T D-bar) D^-1, the
+// symbolic form of Sec. 4.1's chol_unblocked_rev with its Phi halving) on the diagonal block
+// b = nblk - 1 - t of every problem that has it, one wave per problem, from D = L's block and
+// D-bar in the lower triangle of G's block; the symmetric gradient's block goes to both
+// triangles of G.
 __global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
   __shared__ double lds[B2W_WAVES * B2W_LDS];
   __shared__ double wv[B2W_WAVES * B2_NB];
@@ -941,11 +927,7 @@ __global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
       wave_load_lower(Bp, Gd, ldg, w);
     }
     wave_sync();
-    wave_diag_rev_64(Dp, Bp, Di, w);
-    for (int r = 0; r < w; ++r)
-      if (lane < w)
-        Gd[(int64_t)r * ldg + lane] = lane < r ? 0.5 * Bp[pidx(r, lane)]
-                                               : (lane == r ? Bp[pidx(r, r)] : 0.5 * Bp[pidx(lane, r)]);
+    wave_diag_rev_sym64(Dp, Bp, Di, w, Gd, ldg);
     wave_sync();
   }
 }
