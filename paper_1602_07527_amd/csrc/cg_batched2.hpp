@@ -308,7 +308,7 @@ __device__ __forceinline__ void wave_load_lower(double *Dp, const double *src, i
 
 // D <- chol_unblocked(D) and Xp = D^-1 for the w x w block (w <= 64) packed in Dp, by one wave:
 // inner block 0 with the rows below it (one pass of the Level-2 core), the update of inner block 1
-// (three 16 x 16 MFMA tiles), inner block 1, then X00, X11 and X10 = -X11 (D10 X00).  Returns the
+// (three 16 x 16 MFMA tiles), inner block 1, then X00 and X11 in one pass and X10 = -X11 (D10 X00).  Returns the
 // first column with a non-positive or NaN pivot, or -1.
 __device__ int wave_potf2_64(double *Dp_, double *Xp_, int w) {
   lds_double *Dp = lds_view(Dp_), *Xp = lds_view(Xp_);
@@ -345,9 +345,8 @@ __device__ int wave_potf2_64(double *Dp_, double *Xp_, int w) {
     if (bad < 0 && f >= 0) bad = INNER + f;
     wave_sync();
   }
-  wave_trinv32(Dp_, Xp_, 0, ib0);
+  wave_trinv32x2(Dp_, Xp_, ib0, ib1);
   if (ib1 > 0) {
-    wave_trinv32(Dp_, Xp_, INNER, ib1);
     wave_sync();
     // Y = D10 X00 (ib1 x 32), then X10 = -X11 Y, each as up to 2 x 2 tiles held in registers
     const int nt = (ib1 + 15) / 16;
@@ -516,9 +515,8 @@ __global__ __launch_bounds__(256) void b2_trinv_kernel(B2Args a) {
     wave_load_lower(Dp, Li + (int64_t)j * ldl + j, ldl, w);
     wave_sync();
     const int ib0 = min(INNER, w), ib1 = w - ib0;
-    wave_trinv32(Dp, Xp, 0, ib0);
+    wave_trinv32x2(Dp, Xp, ib0, ib1);
     if (ib1 > 0) {
-      wave_trinv32(Dp, Xp, INNER, ib1);
       wave_sync();
       const int nt = (ib1 + 15) / 16;
       dbl4 y[2][2];

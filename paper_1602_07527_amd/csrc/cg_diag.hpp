@@ -379,6 +379,38 @@ __device__ void wave_trinv32(const double *Dp, double *Xp_, int a, int ib) {
     if (c < ib && r < ib && r >= c) Xp[pidx(a + r, a + c)] = x[r];
 }
 
+// The inverses of the two 32 x 32 diagonal blocks of a packed 64-block in ONE pass of one wave:
+// lanes 0..31 build the columns of the block at offset 0 (size ib0), lanes 32..63 those of the
+// block at offset 32 (size ib1 >= 0), as wave_trinv32 does for one block (each half's LDS loads
+// share one address per half).  Rows past a block's size compute values that are never stored.
+__device__ void wave_trinv32x2(const double *Dp, double *Xp_, int ib0, int ib1) {
+  const lds_double *D = lds_view(Dp);
+  lds_double *Xp = lds_view(Xp_);
+  const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31, a = h * INNER;
+  const int ib = h ? ib1 : ib0;
+  const double inv_own = (c < ib) ? 1.0 / D[pidx(a + c, a + c)] : 0.0;
+  double x[INNER];
+#pragma unroll
+  for (int r = 0; r < INNER; ++r) {
+    int base = pidx(a + r, a);
+    if (r >= 2) asm volatile("" : "+v"(base) : "v"(x[r - 2]));
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int l = 0; l < r; ++l) {
+      const double dv = D[base + l];
+      if ((l & 3) == 0) s0 = fma(dv, x[l], s0);
+      else if ((l & 3) == 1) s1 = fma(dv, x[l], s1);
+      else if ((l & 3) == 2) s2 = fma(dv, x[l], s2);
+      else s3 = fma(dv, x[l], s3);
+    }
+    const double inv_r = h ? wave_bcast(inv_own, INNER + r) : wave_bcast(inv_own, r);
+    x[r] = (((r == c) ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3))) * inv_r;
+  }
+#pragma unroll
+  for (int r = 0; r < INNER; ++r)
+    if (c < ib && r < ib && r >= c) Xp[pidx(a + r, a + c)] = x[r];
+}
+
 // X = D^-1 for the whole w x w block (packed; the workgroup cooperates).  The 32 x 32 diagonal
 // blocks are inverted one per wave; block row p then follows from the rows above it:
 //   X_pq = -X_pp (sum_{q <= l < p} D_pl X_lq)      (q < p),
