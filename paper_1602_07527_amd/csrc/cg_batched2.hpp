@@ -196,7 +196,8 @@ __device__ __forceinline__ int b2_find(const int *pr, int batch, int it) {
 // 32 wn + 16 b + lane % 16).  AK / BK: the operand is contiguous along k in memory (the load
 // mapping follows it so that loads coalesce).
 constexpr int T64_LD = B2_NB + 4;
-constexpr int T64_LDS = 4 * 16 * T64_LD;  // doubles: two stages of A and B
+constexpr int T64_BK = 16;                     // K depth of one LDS stage
+constexpr int T64_LDS = 4 * T64_BK * T64_LD;  // doubles: two stages of A and B
 
 __device__ __forceinline__ int t64_row(int a, int e) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -212,34 +213,35 @@ __device__ __forceinline__ void t64_mma(dbl4 (&acc)[2][2], FA A, FB B, int K, do
   double *const lb = (double *)(__attribute__((address_space(3))) double *)lds;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  auto As = [&](int st) { return lb + st * 16 * T64_LD; };
-  auto Bs = [&](int st) { return lb + (2 + st) * 16 * T64_LD; };
+  auto As = [&](int st) { return lb + st * T64_BK * T64_LD; };
+  auto Bs = [&](int st) { return lb + (2 + st) * T64_BK * T64_LD; };
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0, 0, 0, 0};
-  double ra[4], rb[4];
+  constexpr int NL = T64_BK / 4;  // loads per thread per operand and stage
+  double ra[NL], rb[NL];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NL; ++u) {
       const int e = u * 256 + tid;
-      const int i = AK ? (e >> 4) : (e & 63), k = AK ? (e & 15) : (e >> 6);
+      const int i = AK ? (e / T64_BK) : (e & 63), k = AK ? (e % T64_BK) : (e >> 6);
       ra[u] = (k0 + k < K) ? A(i, k0 + k) : 0.0;
-      const int j = BK ? (e >> 4) : (e & 63), kb = BK ? (e & 15) : (e >> 6);
+      const int j = BK ? (e / T64_BK) : (e & 63), kb = BK ? (e % T64_BK) : (e >> 6);
       rb[u] = (k0 + kb < K) ? B(k0 + kb, j) : 0.0;
     }
   };
   auto store = [&](int st) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NL; ++u) {
       const int e = u * 256 + tid;
-      const int i = AK ? (e >> 4) : (e & 63), k = AK ? (e & 15) : (e >> 6);
+      const int i = AK ? (e / T64_BK) : (e & 63), k = AK ? (e % T64_BK) : (e >> 6);
       As(st)[k * T64_LD + i] = ra[u];
-      const int j = BK ? (e >> 4) : (e & 63), kb = BK ? (e & 15) : (e >> 6);
+      const int j = BK ? (e / T64_BK) : (e & 63), kb = BK ? (e % T64_BK) : (e >> 6);
       Bs(st)[kb * T64_LD + j] = rb[u];
     }
   };
-  const int nkt = (K + 15) / 16;
+  const int nkt = (K + T64_BK - 1) / T64_BK;
   if (nkt > 0) {
     load(0);
     store(0);
@@ -248,10 +250,10 @@ __device__ __forceinline__ void t64_mma(dbl4 (&acc)[2][2], FA A, FB B, int K, do
   const int fk = lane >> 4, fi = lane & 15;
   for (int kt = 0; kt < nkt; ++kt) {
     const int st = kt & 1;
-    if (kt + 1 < nkt) load((kt + 1) * 16);
+    if (kt + 1 < nkt) load((kt + 1) * T64_BK);
     const double *as = As(st), *bs = Bs(st);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    for (int kk = 0; kk < T64_BK; kk += 4) {
       double af[2], bf[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) af[t] = as[(kk + fk) * T64_LD + 32 * wm + 16 * t + fi];
