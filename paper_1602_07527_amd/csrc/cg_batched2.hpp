@@ -5,7 +5,10 @@
 //              U   [D_s; C] -= [R; B] R^T over the columns left of block s   (64-row tiles)
 //              F1  D_s <- chol_unblocked(D_s) and D_s^-1          (one wave per problem)
 //              F2  C <- C D_s^-T                                   (64-row tiles)
-//   GP loss  z = L^-1 y, w = L^-T z, f, L-bar = diag(1/L_ii) - tril(w z^T)   (one workgroup each)
+//   GP loss  z = L^-1 y by block substitution inside the factor steps (F1 forms z_s = D_s^-1 t_s,
+//            F2 subtracts L_rs z_s from the t of the rows below) and f at each problem's last
+//            block; L-bar = diag(1/L_ii) - tril(w z^T), w = L^-T z, is never stored: the reverse
+//            steps compute w block by block (b2_gp_w) and form L-bar's entries where they read them
 //   reverse  (chol_blocked_rev in the left-looking order of the single-matrix sweep), problem p
 //            at step t takes its block b = nblk_p - 1 - t, so every problem starts with its last
 //            block:
@@ -477,6 +480,37 @@ __device__ void wave_diag_rev_sym64(double *Dp_, double *Bp_, const double *Dinv
   }
 }
 
+// GP forward solve inside the factorisation, block s of problem p (Sec. 2's z = L^-1 y, block
+// forward substitution): t_s = y_s - sum_{b<s} L_sb z_b has been accumulated in the w slot of the
+// problem's vector by the panel solves of the earlier steps (b2_f2_kernel); z_s = D_s^-1 t_s with
+// the inverse just formed in Xp, by the wave that factored the block.  At the problem's last block
+// the wave also forms f = sum_i log L_ii + |z|^2 / 2 (per-lane partial sums over a fixed stride,
+// then a fixed xor tree: reproducible), NaN when the factorisation failed.  Dp is free here (L has
+// been stored); its first 64 entries stage t_s.
+__device__ void b2_gp_forward_block(const B2Args &a, int p, int n, int s, double *Dp_, const double *Xp_) {
+  lds_double *Dp = lds_view(Dp_);
+  const lds_double *Xp = lds_view(Xp_);
+  const int lane = threadIdx.x & 63, i = a.order[p];
+  const int j = s * B2_NB, w = min(B2_NB, n - j);
+  double *zg = a.vec + p * a.vec_stride, *tg = zg + a.n_max;
+  if (lane < w) Dp[lane] = s == 0 ? a.y[i][lane] : tg[j + lane];
+  wave_sync();
+  double z = 0.0;
+  for (int c = 0; c < w; ++c)
+    if (c <= lane) z = fma(Xp[pidx(lane, c)], Dp[c], z);
+  if (lane < w) zg[j + lane] = z;
+  if (j + w < n) return;
+  // last block: f over the whole problem (earlier blocks' z were written by earlier launches)
+  const double *L = a.A[i];
+  const int64_t ldl = a.lda[i];
+  double part = 0.0;
+  for (int ii = lane; ii < j; ii += 64) part += log(L[(int64_t)ii * ldl + ii]) + 0.5 * zg[ii] * zg[ii];
+  if (lane < w) part += log(L[(int64_t)(j + lane) * ldl + j + lane]) + 0.5 * z * z;
+  const double f = wave_sum(part);
+  if (lane == 0) a.f[i] = a.info[i] != 0 ? __builtin_nan("") : f;
+  wave_sync();
+}
+
 // F1: POTF2 of block s of every problem with more than s blocks, and its inverse, one wave per
 // problem.
 __global__ __launch_bounds__(256) void b2_potf2_kernel(B2Args a, int s) {
@@ -498,6 +532,7 @@ __global__ __launch_bounds__(256) void b2_potf2_kernel(B2Args a, int s) {
     double *X = a.dinv + p * a.dinv_stride + s * B2_BLK;
     for (int r = 0; r < B2_NB; ++r) X[r * B2_NB + lane] = (r < w && lane <= r) ? Xp[pidx(r, lane)] : 0.0;
     wave_sync();
+    if (a.op == BATCH_GP) b2_gp_forward_block(a, p, n, s, Dp, Xp);
   }
 }
 
@@ -603,6 +638,22 @@ __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
         Ai[(int64_t)(j + c) * lda + r0 + r] = 0.0;
       }
     });
+    if (a.op == BATCH_GP) {
+      // GP forward solve: t_r -= L[r, block s] z_s for this tile's rows (t starts as y at step 0);
+      // the tile goes through LDS (free after the product) and one thread sums each row in order
+      __syncthreads();
+      lds_double *T = lds_view(lds);
+      t64_each(acc, [&](int r, int c, double v) { T[r * (B2_NB + 1) + c] = v; });
+      __syncthreads();
+      if ((int)threadIdx.x < R) {
+        const int r = threadIdx.x;
+        const double *zg = a.vec + p * a.vec_stride;
+        double *tg = (double *)zg + a.n_max;
+        double acc2 = 0.0;
+        for (int c = 0; c < w; ++c) acc2 = fma(T[r * (B2_NB + 1) + c], zg[j + c], acc2);
+        tg[r0 + r] = (s == 0 ? a.y[i][r0 + r] : tg[r0 + r]) - acc2;
+      }
+    }
     __syncthreads();
   }
 }
@@ -635,86 +686,6 @@ __global__ __launch_bounds__(256) void b2_up_kernel(B2Args a, int s) {
   }
 }
 
-// GP loss per problem (after the factor): z = L^-1 y by block substitution with the block inverses
-// (kept in the workspace) and f = sum_i log L_ii + |z|^2 / 2.  The reverse-mode input
-// L-bar = diag(1 / L_ii) - tril(w z^T), w = L^-T z, is never stored: the reverse steps compute w
-// block by block (b2_gp_w) and form the entries of L-bar where they read them.  A problem whose
-// factorisation failed gets f = NaN and G untouched.
-__global__ __launch_bounds__(256) void b2_loss_kernel(B2Args a) {
-  __shared__ double t[B2_NB];
-  __shared__ double zl[BATCH_NMAX];
-  __shared__ double red[256];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int cnt = a.count[0];
-  for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
-    const int i = a.order[p], n = a.nv[p];
-    if (a.info[i] != 0) {
-      if (threadIdx.x == 0) a.f[i] = __builtin_nan("");
-      continue;  // workgroup-uniform
-    }
-    const double *L = a.A[i];
-    const int64_t ldl = a.lda[i];
-    const double *y = a.y[i];
-    const double *dinv = a.dinv + p * a.dinv_stride;
-    double *zg = a.vec + p * a.vec_stride;
-    const int nblk = b2_nblk(n);
-    // forward: z_b = D_b^-1 (y_b - L[b, :j] z[:j]).  Wave h takes rows h, h + 4, ... of the block
-    // with its lanes along the columns (coalesced, sixteen loads in flight per lane), and reduces
-    // each row with a fixed xor tree.
-    for (int b = 0; b < nblk; ++b) {
-      const int j = b * B2_NB, w = min(B2_NB, n - j);
-      double acc[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-      for (int q0 = 0; q0 < j; q0 += B2_NB) {
-        const double zv = zl[q0 + lane];
-        double v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int r = wave + 4 * u;
-          v[u] = r < w ? L[(int64_t)(j + r) * ldl + q0 + lane] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] = fma(v[u], zv, acc[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int r = wave + 4 * u;
-        const double tot = wave_sum(acc[u]);
-        if (lane == 0 && r < w) t[r] = y[j + r] - tot;
-      }
-      __syncthreads();
-      const double *Di = dinv + b * B2_BLK;
-      const double tv = lane < w ? t[lane] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int r = wave + 4 * u;
-        acc[u] = (r < w && lane <= r) ? Di[r * B2_NB + lane] * tv : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int r = wave + 4 * u;
-        const double tot = wave_sum(acc[u]);
-        if (lane == 0 && r < w) {
-          zg[j + r] = tot;
-          zl[j + r] = tot;
-        }
-      }
-      __syncthreads();
-    }
-    // f: per-thread partial sums over a fixed stride, then a fixed-order tree
-    double part = 0.0;
-    for (int ii = threadIdx.x; ii < n; ii += blockDim.x) part += log(L[(int64_t)ii * ldl + ii]) + 0.5 * zl[ii] * zl[ii];
-    red[threadIdx.x] = part;
-    __syncthreads();
-    for (int hh = blockDim.x / 2; hh > 0; hh >>= 1) {
-      if ((int)threadIdx.x < hh) red[threadIdx.x] += red[threadIdx.x + hh];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) a.f[i] = red[0];
-    __syncthreads();
-  }
-}
 
 __device__ __forceinline__ bool b2_rev_skip(const B2Args &a, int i) {
   return (a.op == BATCH_GP || a.op == BATCH_FACTOR_REV) && a.info[i] != 0;

@@ -517,7 +517,7 @@ int run_batched2(const cg::BatchArgs &a, int64_t n_max, void *workspace, hipStre
   CG_TRY(hipGetLastError());
   const bool factor = a.op != cg::BATCH_REV;
   const unsigned gd = (unsigned)std::min<int64_t>(cdiv(a.batch, cg::B2W_WAVES), B2_GRID_DIAG);
-  const unsigned gl = (unsigned)std::min(a.batch, 1024);  // GP loss: one workgroup per problem
+  const unsigned gl = (unsigned)std::min(a.batch, 1024);  // one workgroup per problem (R2, form)
   if (factor) {
     for (int st = 0; st < nsteps; ++st) {
       if (st > 0) {
@@ -536,10 +536,6 @@ int run_batched2(const cg::BatchArgs &a, int64_t n_max, void *workspace, hipStre
     CG_TRY(hipGetLastError());
   }
   if (a.op == cg::BATCH_FACTOR) return CHOL_SUCCESS;
-  if (a.op == cg::BATCH_GP) {
-    hipLaunchKernelGGL(cg::b2_loss_kernel, dim3(gl), dim3(256), 0, s, b);
-    CG_TRY(hipGetLastError());
-  }
   for (int t = 0; t < nsteps; ++t) {
     if (t > 0) {
       hipLaunchKernelGGL(cg::b2_r0_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, t);
