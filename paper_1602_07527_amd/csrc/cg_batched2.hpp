@@ -503,9 +503,16 @@ __device__ void b2_gp_forward_block(const B2Args &a, int p, int n, int s, double
   // last block: f over the whole problem (earlier blocks' z were written by earlier launches)
   const double *L = a.A[i];
   const int64_t ldl = a.lda[i];
-  double part = 0.0;
-  for (int ii = lane; ii < j; ii += 64) part += log(L[(int64_t)ii * ldl + ii]) + 0.5 * zg[ii] * zg[ii];
-  if (lane < w) part += log(L[(int64_t)(j + lane) * ldl + j + lane]) + 0.5 * z * z;
+  double dv[B2_MAXBLK], zv[B2_MAXBLK];  // earlier blocks' entries, all loads in flight at once
+#pragma unroll
+  for (int u = 0; u < B2_MAXBLK; ++u) {
+    const int ii = lane + B2_NB * u;
+    dv[u] = ii < j ? L[(int64_t)ii * ldl + ii] : 1.0;
+    zv[u] = ii < j ? zg[ii] : 0.0;
+  }
+  double part = lane < w ? log(L[(int64_t)(j + lane) * ldl + j + lane]) + 0.5 * z * z : 0.0;
+#pragma unroll
+  for (int u = 0; u < B2_MAXBLK; ++u) part += log(dv[u]) + 0.5 * zv[u] * zv[u];
   const double f = wave_sum(part);
   if (lane == 0) a.f[i] = a.info[i] != 0 ? __builtin_nan("") : f;
   wave_sync();
@@ -618,6 +625,7 @@ __global__ __launch_bounds__(256) void b2_trinv_kernel(B2Args a) {
 // diagonal are set to 0 (the factor's strict upper triangle).
 __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
   __shared__ double lds[T64_LDS];
+  __shared__ double gpbuf[B2_NB + 4 * B2_NB];  // GP: z_s and the row partial sums
   const int *pr = a.pref + (int64_t)(B2_Q_F2 + s) * (a.batch + 1);
   const int total = pr[a.batch];
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
@@ -640,18 +648,28 @@ __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
     });
     if (a.op == BATCH_GP) {
       // GP forward solve: t_r -= L[r, block s] z_s for this tile's rows (t starts as y at step 0);
-      // the tile goes through LDS (free after the product) and one thread sums each row in order
+      // the tile and z_s go through LDS (free after the product), four threads per row take 16
+      // columns each and the four partial sums are added in a fixed order
       __syncthreads();
       lds_double *T = lds_view(lds);
+      lds_double *Z = lds_view(gpbuf), *Q = Z + B2_NB;
+      const double *zg = a.vec + p * a.vec_stride;
+      double *tg = (double *)zg + a.n_max;
       t64_each(acc, [&](int r, int c, double v) { T[r * (B2_NB + 1) + c] = v; });
+      if ((int)threadIdx.x < B2_NB) Z[threadIdx.x] = (int)threadIdx.x < w ? zg[j + threadIdx.x] : 0.0;
+      __syncthreads();
+      {
+        const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+        double acc2 = 0.0;
+#pragma unroll
+        for (int c = 16 * q; c < 16 * q + 16; ++c) acc2 = fma(T[r * (B2_NB + 1) + c], Z[c], acc2);
+        Q[threadIdx.x] = acc2;
+      }
       __syncthreads();
       if ((int)threadIdx.x < R) {
         const int r = threadIdx.x;
-        const double *zg = a.vec + p * a.vec_stride;
-        double *tg = (double *)zg + a.n_max;
-        double acc2 = 0.0;
-        for (int c = 0; c < w; ++c) acc2 = fma(T[r * (B2_NB + 1) + c], zg[j + c], acc2);
-        tg[r0 + r] = (s == 0 ? a.y[i][r0 + r] : tg[r0 + r]) - acc2;
+        const double sum = (Q[4 * r] + Q[4 * r + 1]) + (Q[4 * r + 2] + Q[4 * r + 3]);
+        tg[r0 + r] = (s == 0 ? a.y[i][r0 + r] : tg[r0 + r]) - sum;
       }
     }
     __syncthreads();
