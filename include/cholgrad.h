@@ -58,11 +58,17 @@ extern "C" {
 
 /* Precision of the call.
  *   CHOL_PREC_F64 : double storage; every step in FP64 (FP64 MFMA for the contractions).
- *   CHOL_PREC_F32 : float storage (matrices, vectors and losses); each input's lower triangle is
- *                   widened to FP64 in the workspace (single-matrix calls: n*n doubles per matrix
- *                   argument, included by chol_workspace_bytes), computed exactly as in
- *                   CHOL_PREC_F64 and rounded to float once on output, so the result is the FP64
- *                   result for the float input to within float rounding.
+ *   CHOL_PREC_F32 : float storage (matrices, vectors and losses).  Single-matrix calls and
+ *                   chol_fwd_batched: each input's lower triangle is widened to FP64 (single-
+ *                   matrix calls: n*n doubles of the workspace per matrix argument, included by
+ *                   chol_workspace_bytes), computed exactly as in CHOL_PREC_F64 and rounded to
+ *                   float once on output, so the result is the FP64 result for the float input to
+ *                   within float rounding.  The other batched calls compute in FP64 within each
+ *                   64-wide block step and round every value they store to float (the problems'
+ *                   arrays are updated in place between steps): against the FP64 result for the
+ *                   float inputs, relative Frobenius errors <= 3e-7 for L, <= 7e-6 for Sigma-bar
+ *                   and <= 6e-7 for f on well-conditioned problems (kappa <= ~40; measured
+ *                   3.4e-8, 6.8e-7, 5.6e-8).
  *   CHOL_PREC_F64_TRAIL_F32 : double storage, single-matrix calls only (batched calls return
  *                   CHOL_ERR_UNSUPPORTED, as for the next mode).  The trailing contractions -- the block-column
  *                   updates of chol_factor and chol_fwd and the panel contraction and SYRK of

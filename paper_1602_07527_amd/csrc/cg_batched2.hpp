@@ -92,23 +92,34 @@ __device__ __forceinline__ bool b2_factor_op(int op) {
   return op == BATCH_FACTOR || op == BATCH_GP || op == BATCH_FACTOR_REV;
 }
 
-// The factor of problem i (the factor ops overwrite A with it; REV reads L) and the array the
-// reverse sweep works in (REV: A; GP and FACTOR_REV: G).
-__device__ __forceinline__ const double *b2_L(const B2Args &a, int i, int64_t &ld) {
-  if (a.op == BATCH_REV) { ld = a.ldl[i]; return a.L[i]; }
+// The problems' arrays in their storage type T (double, or float for FP32 storage: the kernels
+// compute in FP64 and round every value they store): A, the factor of problem i (the factor ops
+// overwrite A with it; REV reads L), the array the reverse sweep works in (REV: A; GP and
+// FACTOR_REV: G), y and the losses.
+template <typename T>
+__device__ __forceinline__ T *b2_A(const B2Args &a, int i) { return reinterpret_cast<T *>(a.A[i]); }
+template <typename T>
+__device__ __forceinline__ const T *b2_L(const B2Args &a, int i, int64_t &ld) {
+  if (a.op == BATCH_REV) { ld = a.ldl[i]; return reinterpret_cast<const T *>(a.L[i]); }
   ld = a.lda[i];
-  return a.A[i];
+  return reinterpret_cast<const T *>(a.A[i]);
 }
-__device__ __forceinline__ double *b2_G(const B2Args &a, int i, int64_t &ld) {
-  if (a.op == BATCH_REV) { ld = a.lda[i]; return a.A[i]; }
+template <typename T>
+__device__ __forceinline__ T *b2_G(const B2Args &a, int i, int64_t &ld) {
+  if (a.op == BATCH_REV) { ld = a.lda[i]; return reinterpret_cast<T *>(a.A[i]); }
   ld = a.ldg[i];
-  return a.G[i];
+  return reinterpret_cast<T *>(a.G[i]);
 }
+template <typename T>
+__device__ __forceinline__ double b2_y(const B2Args &a, int i, int r) { return reinterpret_cast<const T *>(a.y[i])[r]; }
+template <typename T>
+__device__ __forceinline__ void b2_set_f(const B2Args &a, int i, double v) { reinterpret_cast<T *>(a.f)[i] = (T)v; }
 
 // Plan, part 1 (one workgroup of 1024 threads): validate each problem (size in [0, n_max],
 // leading dimensions >= size; otherwise it is skipped: size 0 in the plan, info -1), order the
 // problems by decreasing size (counting sort), count the positions with more than s blocks, and
 // initialise info (0) and, for n == 0, the loss (0).
+template <typename T>
 __global__ __launch_bounds__(1024) void b2_order_kernel(B2Args a) {
   __shared__ int cnt[BATCH_NMAX + 2];
   __shared__ int blk[B2_MAXBLK];
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(1024) void b2_order_kernel(B2Args a) {
     a.order[pos] = i;
     a.nv[pos] = max(0, key);
     if (b2_factor_op(a.op)) a.info[i] = key < 0 ? -1 : 0;
-    if (a.op == BATCH_GP && key == 0) a.f[i] = 0.0;
+    if (a.op == BATCH_GP && key == 0) b2_set_f<T>(a, i, 0.0);
   }
   if (tid < B2_MAXBLK) a.count[tid] = blk[tid];
 }
@@ -294,7 +305,8 @@ constexpr int B2W_LDS = 2 * B2_PACKED;  // doubles per wave
 
 // Packed lower triangle of a w x w block (w <= 64, row-major source) into Dp, by one wave, sixteen
 // rows of loads in flight.
-__device__ __forceinline__ void wave_load_lower(double *Dp, const double *src, int64_t ld, int w) {
+template <typename T>
+__device__ __forceinline__ void wave_load_lower(double *Dp, const T *src, int64_t ld, int w) {
   const int lane = threadIdx.x & 63;
   for (int r0 = 0; r0 < w; r0 += 16) {
     double v[16];
@@ -417,7 +429,8 @@ __device__ int wave_potf2_64(double *Dp_, double *Xp_, int w) {
 //   rows 4e + lane/16, the rows of K-slice e); S is symmetric and goes to both triangles of G.
 // D packed in Dp, D-bar packed in Bp (both overwritten), Dinv row-major 64 x 64 with zeros outside
 // w x w (staged into Dp once P is formed); G: the block's place in the output, leading dim ldg.
-__device__ void wave_diag_rev_sym64(double *Dp_, double *Bp_, const double *Dinv, int w, double *G, int64_t ldg) {
+template <typename T>
+__device__ void wave_diag_rev_sym64(double *Dp_, double *Bp_, const double *Dinv, int w, T *G, int64_t ldg) {
   lds_double *Dp = lds_view(Dp_), *Bp = lds_view(Bp_);
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   dbl4 P[10];
@@ -472,8 +485,8 @@ __device__ void wave_diag_rev_sym64(double *Dp_, double *Bp_, const double *Dinv
       for (int e = 0; e < 4; ++e) {
         const int r = 16 * ti + 4 * e + lk, c = 16 * tj + li;
         if (r < w && c <= r) {
-          G[(int64_t)r * ldg + c] = S[e];
-          if (c < r) G[(int64_t)c * ldg + r] = S[e];
+          G[(int64_t)r * ldg + c] = (T)S[e];
+          if (c < r) G[(int64_t)c * ldg + r] = (T)S[e];
         }
       }
     }
@@ -487,13 +500,14 @@ __device__ void wave_diag_rev_sym64(double *Dp_, double *Bp_, const double *Dinv
 // the wave also forms f = sum_i log L_ii + |z|^2 / 2 (per-lane partial sums over a fixed stride,
 // then a fixed xor tree: reproducible), NaN when the factorisation failed.  Dp is free here (L has
 // been stored); its first 64 entries stage t_s.
+template <typename T>
 __device__ void b2_gp_forward_block(const B2Args &a, int p, int n, int s, double *Dp_, const double *Xp_) {
   lds_double *Dp = lds_view(Dp_);
   const lds_double *Xp = lds_view(Xp_);
   const int lane = threadIdx.x & 63, i = a.order[p];
   const int j = s * B2_NB, w = min(B2_NB, n - j);
   double *zg = a.vec + p * a.vec_stride, *tg = zg + a.n_max;
-  if (lane < w) Dp[lane] = s == 0 ? a.y[i][lane] : tg[j + lane];
+  if (lane < w) Dp[lane] = s == 0 ? b2_y<T>(a, i, lane) : tg[j + lane];
   wave_sync();
   double z = 0.0;
   for (int c = 0; c < w; ++c)
@@ -501,7 +515,7 @@ __device__ void b2_gp_forward_block(const B2Args &a, int p, int n, int s, double
   if (lane < w) zg[j + lane] = z;
   if (j + w < n) return;
   // last block: f over the whole problem (earlier blocks' z were written by earlier launches)
-  const double *L = a.A[i];
+  const T *L = b2_A<T>(a, i);
   const int64_t ldl = a.lda[i];
   double dv[B2_MAXBLK], zv[B2_MAXBLK];  // earlier blocks' entries, all loads in flight at once
 #pragma unroll
@@ -514,12 +528,13 @@ __device__ void b2_gp_forward_block(const B2Args &a, int p, int n, int s, double
 #pragma unroll
   for (int u = 0; u < B2_MAXBLK; ++u) part += log(dv[u]) + 0.5 * zv[u] * zv[u];
   const double f = wave_sum(part);
-  if (lane == 0) a.f[i] = a.info[i] != 0 ? __builtin_nan("") : f;
+  if (lane == 0) b2_set_f<T>(a, i, a.info[i] != 0 ? __builtin_nan("") : f);
   wave_sync();
 }
 
 // F1: POTF2 of block s of every problem with more than s blocks, and its inverse, one wave per
 // problem.
+template <typename T>
 __global__ __launch_bounds__(256) void b2_potf2_kernel(B2Args a, int s) {
   __shared__ double lds[B2W_WAVES * B2W_LDS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -528,22 +543,23 @@ __global__ __launch_bounds__(256) void b2_potf2_kernel(B2Args a, int s) {
   for (int p = blockIdx.x * B2W_WAVES + wave; p < cnt; p += gridDim.x * B2W_WAVES) {
     const int i = a.order[p], n = a.nv[p];
     const int j = s * B2_NB, w = min(B2_NB, n - j);
-    double *Ad = a.A[i] + (int64_t)j * a.lda[i] + j;
+    T *Ad = b2_A<T>(a, i) + (int64_t)j * a.lda[i] + j;
     const int64_t lda = a.lda[i];
     wave_load_lower(Dp, Ad, lda, w);
     wave_sync();
     const int bad = wave_potf2_64(Dp, Xp, w);
     if (lane == 0 && bad >= 0 && a.info[i] == 0) a.info[i] = j + bad + 1;
     for (int r = 0; r < w; ++r)
-      if (lane < w) Ad[(int64_t)r * lda + lane] = lane <= r ? Dp[pidx(r, lane)] : 0.0;
+      if (lane < w) Ad[(int64_t)r * lda + lane] = (T)(lane <= r ? Dp[pidx(r, lane)] : 0.0);
     double *X = a.dinv + p * a.dinv_stride + s * B2_BLK;
     for (int r = 0; r < B2_NB; ++r) X[r * B2_NB + lane] = (r < w && lane <= r) ? Xp[pidx(r, lane)] : 0.0;
     wave_sync();
-    if (a.op == BATCH_GP) b2_gp_forward_block(a, p, n, s, Dp, Xp);
+    if (a.op == BATCH_GP) b2_gp_forward_block<T>(a, p, n, s, Dp, Xp);
   }
 }
 
 // Inverses of every diagonal block of L (REV, which is given L), one wave per block.
+template <typename T>
 __global__ __launch_bounds__(256) void b2_trinv_kernel(B2Args a) {
   __shared__ double lds[B2W_WAVES * B2W_LDS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -555,7 +571,7 @@ __global__ __launch_bounds__(256) void b2_trinv_kernel(B2Args a) {
     const int i = a.order[p], n = a.nv[p];
     const int j = b * B2_NB, w = min(B2_NB, n - j);
     int64_t ldl;
-    const double *Li = b2_L(a, i, ldl);
+    const T *Li = b2_L<T>(a, i, ldl);
     wave_load_lower(Dp, Li + (int64_t)j * ldl + j, ldl, w);
     wave_sync();
     const int ib0 = min(INNER, w), ib1 = w - ib0;
@@ -623,6 +639,7 @@ __global__ __launch_bounds__(256) void b2_trinv_kernel(B2Args a) {
 // F2: rows below block s, C <- C D_s^-T, one 64-row tile per item (the tile spans all of the
 // block's columns, so it is read before it is written); the mirrored positions above the
 // diagonal are set to 0 (the factor's strict upper triangle).
+template <typename T>
 __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
   __shared__ double lds[T64_LDS];
   __shared__ double gpbuf[B2_NB + 4 * B2_NB];  // GP: z_s and the row partial sums
@@ -633,7 +650,7 @@ __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
     const int i = a.order[p], n = a.nv[p];
     const int j = s * B2_NB, w = min(B2_NB, n - j), k = j + w;
     const int r0 = k + ti * B2_NB, R = min(B2_NB, n - r0);
-    double *Ai = a.A[i];
+    T *Ai = b2_A<T>(a, i);
     const int64_t lda = a.lda[i];
     const double *Di = a.dinv + p * a.dinv_stride + s * B2_BLK;
     dbl4 acc[2][2];
@@ -642,8 +659,8 @@ __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
         [&](int kk, int c) { return (c < w && kk <= c) ? Di[c * B2_NB + kk] : 0.0; }, w, lds);
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w) {
-        Ai[(int64_t)(r0 + r) * lda + j + c] = v;
-        Ai[(int64_t)(j + c) * lda + r0 + r] = 0.0;
+        Ai[(int64_t)(r0 + r) * lda + j + c] = (T)v;
+        Ai[(int64_t)(j + c) * lda + r0 + r] = (T)0;
       }
     });
     if (a.op == BATCH_GP) {
@@ -651,25 +668,25 @@ __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
       // the tile and z_s go through LDS (free after the product), four threads per row take 16
       // columns each and the four partial sums are added in a fixed order
       __syncthreads();
-      lds_double *T = lds_view(lds);
+      lds_double *Tl = lds_view(lds);
       lds_double *Z = lds_view(gpbuf), *Q = Z + B2_NB;
       const double *zg = a.vec + p * a.vec_stride;
       double *tg = (double *)zg + a.n_max;
-      t64_each(acc, [&](int r, int c, double v) { T[r * (B2_NB + 1) + c] = v; });
+      t64_each(acc, [&](int r, int c, double v) { Tl[r * (B2_NB + 1) + c] = v; });
       if ((int)threadIdx.x < B2_NB) Z[threadIdx.x] = (int)threadIdx.x < w ? zg[j + threadIdx.x] : 0.0;
       __syncthreads();
       {
         const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
         double acc2 = 0.0;
 #pragma unroll
-        for (int c = 16 * q; c < 16 * q + 16; ++c) acc2 = fma(T[r * (B2_NB + 1) + c], Z[c], acc2);
+        for (int c = 16 * q; c < 16 * q + 16; ++c) acc2 = fma(Tl[r * (B2_NB + 1) + c], Z[c], acc2);
         Q[threadIdx.x] = acc2;
       }
       __syncthreads();
       if ((int)threadIdx.x < R) {
         const int r = threadIdx.x;
         const double sum = (Q[4 * r] + Q[4 * r + 1]) + (Q[4 * r + 2] + Q[4 * r + 3]);
-        tg[r0 + r] = (s == 0 ? a.y[i][r0 + r] : tg[r0 + r]) - sum;
+        tg[r0 + r] = (s == 0 ? b2_y<T>(a, i, r0 + r) : tg[r0 + r]) - sum;
       }
     }
     __syncthreads();
@@ -679,6 +696,7 @@ __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
 // U: left-looking update of block column s, [D_s; C] -= [R; B] R^T over columns [0, 64 s), one
 // 64-row tile of rows [64 s, n) per item (in place: it reads only columns left of the block).  The
 // diagonal block's strict upper part is not needed (POTF2 reads the lower triangle).
+template <typename T>
 __global__ __launch_bounds__(256) void b2_up_kernel(B2Args a, int s) {
   __shared__ double lds[T64_LDS];
   const int *pr = a.pref + (int64_t)(B2_Q_UP + s) * (a.batch + 1);
@@ -688,16 +706,16 @@ __global__ __launch_bounds__(256) void b2_up_kernel(B2Args a, int s) {
     const int i = a.order[p], n = a.nv[p];
     const int j = s * B2_NB, w = min(B2_NB, n - j);
     const int r0 = j + ti * B2_NB, R = min(B2_NB, n - r0);
-    double *Ai = a.A[i];
+    T *Ai = b2_A<T>(a, i);
     const int64_t lda = a.lda[i];
     dbl4 acc[2][2];
     t64_mma<true, true>(
-        acc, [&](int r, int kk) { return (r < R) ? Ai[(int64_t)(r0 + r) * lda + kk] : 0.0; },
-        [&](int kk, int c) { return (c < w) ? Ai[(int64_t)(j + c) * lda + kk] : 0.0; }, j, lds);
+        acc, [&](int r, int kk) { return (r < R) ? (double)Ai[(int64_t)(r0 + r) * lda + kk] : 0.0; },
+        [&](int kk, int c) { return (c < w) ? (double)Ai[(int64_t)(j + c) * lda + kk] : 0.0; }, j, lds);
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w && (ti > 0 || c <= r)) {
-        double *d = Ai + (int64_t)(r0 + r) * lda + j + c;
-        *d = *d - v;
+        T *d = Ai + (int64_t)(r0 + r) * lda + j + c;
+        *d = (T)((double)*d - v);
       }
     });
     __syncthreads();
@@ -714,12 +732,13 @@ __device__ __forceinline__ bool b2_rev_skip(const B2Args &a, int i) {
 // block per reverse step.  Thread (h, r) = (wave, lane) walks rows k + h, k + h + 4, ... of column
 // j + r (coalesced, sixteen loads in flight) and the four partial sums are added in a fixed order.
 // tb and pt: B2_NB and 4 * B2_NB doubles of LDS.
+template <typename T>
 __device__ void b2_gp_w(const B2Args &a, int p, int n, int b, double *tb_, double *pt_) {
   lds_double *tb = lds_view(tb_), *pt = lds_view(pt_);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = a.order[p];
   const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j;
-  const double *L = a.A[i];
+  const T *L = b2_A<T>(a, i);
   const int64_t ldl = a.lda[i];
   const double *zg = a.vec + p * a.vec_stride;
   double *wg = (double *)zg + a.n_max;
@@ -760,14 +779,16 @@ __device__ void b2_gp_w(const B2Args &a, int p, int n, int b, double *tb_, doubl
 }
 
 // GP mode: entry (r, c), r >= c, of L-bar = diag(1 / L_ii) - tril(w z^T).
-__device__ __forceinline__ double b2_gp_lbar(const double *zg, const double *wg, const double *L, int64_t ldl,
+template <typename T>
+__device__ __forceinline__ double b2_gp_lbar(const double *zg, const double *wg, const T *L, int64_t ldl,
                                              int r, int c) {
   const double v = -wg[r] * zg[c];
-  return r == c ? 1.0 / L[(int64_t)r * ldl + r] + v : v;
+  return r == c ? 1.0 / (double)L[(int64_t)r * ldl + r] + v : v;
 }
 
 // R0: X = L-bar_C - 2 S_sym[k:, k:] L[k:, j:k] for the rows below block b = nblk - 1 - t, in place
 // in the block column of G (one 64-row tile per item; it reads only columns >= k of G).
+template <typename T>
 __global__ __launch_bounds__(256) void b2_r0_kernel(B2Args a, int t) {
   __shared__ double lds[T64_LDS];
   const int *pr = a.pref + (int64_t)(B2_Q_RV + t) * (a.batch + 1);
@@ -780,8 +801,8 @@ __global__ __launch_bounds__(256) void b2_r0_kernel(B2Args a, int t) {
     const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j, m = n - k;
     const int r0 = k + ti * B2_NB, R = min(B2_NB, n - r0);
     int64_t ldl, ldg;
-    const double *Li = b2_L(a, i, ldl);
-    double *Gi = b2_G(a, i, ldg);
+    const T *Li = b2_L<T>(a, i, ldl);
+    T *Gi = b2_G<T>(a, i, ldg);
     dbl4 acc[2][2];
     t64_mma<true, false>(
         acc, [&](int r, int kk) { return (r < R && kk < m) ? Gi[(int64_t)(r0 + r) * ldg + k + kk] : 0.0; },
@@ -790,9 +811,9 @@ __global__ __launch_bounds__(256) void b2_r0_kernel(B2Args a, int t) {
     const double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w) {
-        double *d = Gi + (int64_t)(r0 + r) * ldg + j + c;
-        const double lbar = gp ? -wg[r0 + r] * zg[j + c] : *d;
-        *d = lbar - 2.0 * v;
+        T *d = Gi + (int64_t)(r0 + r) * ldg + j + c;
+        const double lbar = gp ? -wg[r0 + r] * zg[j + c] : (double)*d;
+        *d = (T)(lbar - 2.0 * v);
       }
     });
     __syncthreads();
@@ -801,6 +822,7 @@ __global__ __launch_bounds__(256) void b2_r0_kernel(B2Args a, int t) {
 
 // R1: C-bar / 2 = X D_b^-1 / 2 for one 64-row tile (in place: the tile spans all of the block's
 // columns, so it is read before it is written), mirrored to the upper triangle.
+template <typename T>
 __global__ __launch_bounds__(256) void b2_r1_kernel(B2Args a, int t) {
   __shared__ double lds[T64_LDS];
   const int *pr = a.pref + (int64_t)(B2_Q_RV + t) * (a.batch + 1);
@@ -813,7 +835,7 @@ __global__ __launch_bounds__(256) void b2_r1_kernel(B2Args a, int t) {
     const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j;
     const int r0 = k + ti * B2_NB, R = min(B2_NB, n - r0);
     int64_t ldg;
-    double *Gi = b2_G(a, i, ldg);
+    T *Gi = b2_G<T>(a, i, ldg);
     const double *Di = a.dinv + p * a.dinv_stride + b * B2_BLK;
     dbl4 acc[2][2];
     t64_mma<true, false>(
@@ -822,8 +844,8 @@ __global__ __launch_bounds__(256) void b2_r1_kernel(B2Args a, int t) {
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w) {
         const double h = 0.5 * v;
-        Gi[(int64_t)(r0 + r) * ldg + j + c] = h;
-        Gi[(int64_t)(j + c) * ldg + r0 + r] = h;
+        Gi[(int64_t)(r0 + r) * ldg + j + c] = (T)h;
+        Gi[(int64_t)(j + c) * ldg + r0 + r] = (T)h;
       }
     });
     __syncthreads();
@@ -833,6 +855,7 @@ __global__ __launch_bounds__(256) void b2_r1_kernel(B2Args a, int t) {
 // R2: D-bar = tril(L-bar_D) - tril(C-bar^T C) for block b = nblk - 1 - t, C-bar = 2 G[k:, j:k]
 // (after R1) and C = L[k:, j:k], K = m; one workgroup per problem, written in place into the
 // lower triangle of G's diagonal block.
+template <typename T>
 __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
   __shared__ double lds[T64_LDS];
   __shared__ double tb[B2_NB];
@@ -845,9 +868,9 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
     const int b = b2_nblk(n) - 1 - t;
     const int j = b * B2_NB, k = min(n, j + B2_NB), w = k - j, m = n - k;
     int64_t ldl, ldg;
-    const double *Li = b2_L(a, i, ldl);
-    double *Gi = b2_G(a, i, ldg);
-    if (gp) b2_gp_w(a, p, n, b, as_lds(tb), as_lds(pt));
+    const T *Li = b2_L<T>(a, i, ldl);
+    T *Gi = b2_G<T>(a, i, ldg);
+    if (gp) b2_gp_w<T>(a, p, n, b, as_lds(tb), as_lds(pt));
     const double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
     dbl4 acc[2][2];
     t64_mma<false, false>(
@@ -855,9 +878,9 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
         [&](int kk, int y) { return (y < w) ? Li[(int64_t)(k + kk) * ldl + j + y] : 0.0; }, m, lds);
     t64_each(acc, [&](int x, int y, double v) {
       if (x < w && y <= x) {
-        double *d = Gi + (int64_t)(j + x) * ldg + j + y;
-        const double lbar = gp ? b2_gp_lbar(zg, wg, Li, ldl, j + x, j + y) : *d;
-        *d = lbar - 2.0 * v;
+        T *d = Gi + (int64_t)(j + x) * ldg + j + y;
+        const double lbar = gp ? b2_gp_lbar<T>(zg, wg, Li, ldl, j + x, j + y) : (double)*d;
+        *d = (T)(lbar - 2.0 * v);
       }
     });
     __syncthreads();
@@ -869,6 +892,7 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
 // b = nblk - 1 - t of every problem that has it, one wave per problem, from D = L's block and
 // D-bar in the lower triangle of G's block; the symmetric gradient's block goes to both
 // triangles of G.
+template <typename T>
 __global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
   __shared__ double lds[B2W_WAVES * B2W_LDS];
   __shared__ double wv[B2W_WAVES * B2_NB];
@@ -882,8 +906,8 @@ __global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
     const int b = b2_nblk(n) - 1 - t;
     const int j = b * B2_NB, w = min(B2_NB, n - j);
     int64_t ldl, ldg;
-    const double *Ld = b2_L(a, i, ldl) + (int64_t)j * ldl + j;
-    double *Gd = b2_G(a, i, ldg) + (int64_t)j * ldg + j;
+    const T *Ld = b2_L<T>(a, i, ldl) + (int64_t)j * ldl + j;
+    T *Gd = b2_G<T>(a, i, ldg) + (int64_t)j * ldg + j;
     const double *Di = a.dinv + p * a.dinv_stride + b * B2_BLK;
     wave_load_lower(Dp, Ld, ldl, w);
     if (gp0) {
@@ -910,31 +934,32 @@ __global__ __launch_bounds__(256) void b2_r3_kernel(B2Args a, int t) {
       for (int r = 0; r < w; ++r)
         if (lane <= r) {
           const double v = -wl[r] * zg[j + lane];
-          Bp[pidx(r, lane)] = lane == r ? 1.0 / Ld[(int64_t)r * ldl + r] + v : v;
+          Bp[pidx(r, lane)] = lane == r ? 1.0 / (double)Ld[(int64_t)r * ldl + r] + v : v;
         }
     } else {
       wave_load_lower(Bp, Gd, ldg, w);
     }
     wave_sync();
-    wave_diag_rev_sym64(Dp, Bp, Di, w, Gd, ldg);
+    wave_diag_rev_sym64<T>(Dp, Bp, Di, w, Gd, ldg);
     wave_sync();
   }
 }
 
 // Paper's lower-triangular form T = Phi(S + S^T) from the symmetric gradient (strict lower doubled,
 // strict upper 0), per problem.
+template <typename T>
 __global__ __launch_bounds__(256) void b2_form_kernel(B2Args a) {
   const int cnt = a.count[0];
   for (int p = blockIdx.x; p < cnt; p += gridDim.x) {
     const int i = a.order[p], n = a.nv[p];
     if (b2_rev_skip(a, i)) continue;
     int64_t ldg;
-    double *Gi = b2_G(a, i, ldg);
+    T *Gi = b2_G<T>(a, i, ldg);
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
       const int r = e / n, c = e - r * n;
-      double *d = Gi + (int64_t)r * ldg + c;
-      if (c > r) *d = 0.0;
-      else if (c < r) *d = 2.0 * *d;
+      T *d = Gi + (int64_t)r * ldg + c;
+      if (c > r) *d = (T)0;
+      else if (c < r) *d = (T)(2.0 * (double)*d);
     }
   }
 }

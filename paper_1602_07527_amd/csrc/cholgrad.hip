@@ -484,7 +484,6 @@ size_t carve_batch2(int batch, int64_t n_max, void *base, Batch2Ws *w) {
 size_t batched_ws_bytes(int batch, int64_t n_max, bool f32) {
   BatchWs w;
   const size_t v1 = carve_batch(batch, n_max, f32, nullptr, &w);
-  if (f32) return v1;
   Batch2Ws w2;
   return std::max(v1, carve_batch2(batch, n_max, nullptr, &w2));
 }
@@ -496,10 +495,11 @@ constexpr int B2_GRID_DIAG = 256;    // diagonal blocks, one per wave: 133 KB of
 constexpr int B2_GRID_TILE = 1024;   // 64 x 64 tile products: 35 KB of LDS, four per compute unit
 
 bool batch2_op(const cg::BatchArgs &a) {
-  return !a.f32 && (a.op == cg::BATCH_FACTOR || a.op == cg::BATCH_REV || a.op == cg::BATCH_GP ||
-                    a.op == cg::BATCH_FACTOR_REV);
+  return a.op == cg::BATCH_FACTOR || a.op == cg::BATCH_REV || a.op == cg::BATCH_GP || a.op == cg::BATCH_FACTOR_REV;
 }
 
+// T: the problems' storage type (double, or float for FP32 storage).
+template <typename T>
 int run_batched2(const cg::BatchArgs &a, int64_t n_max, void *workspace, hipStream_t s) {
   Batch2Ws ws;
   carve_batch2(a.batch, n_max, workspace, &ws);
@@ -511,7 +511,7 @@ int run_batched2(const cg::BatchArgs &a, int64_t n_max, void *workspace, hipStre
   b.dinv = ws.dinv; b.vec = ws.vec;
   b.dinv_stride = ws.dinv_stride; b.vec_stride = ws.vec_stride;
   const int nsteps = (int)cdiv(std::max<int64_t>(n_max, 1), cg::B2_NB);
-  hipLaunchKernelGGL(cg::b2_order_kernel, dim3(1), dim3(1024), 0, s, b);
+  hipLaunchKernelGGL(cg::b2_order_kernel<T>, dim3(1), dim3(1024), 0, s, b);
   CG_TRY(hipGetLastError());
   hipLaunchKernelGGL(cg::b2_prefix_kernel, dim3(cg::B2_NPREF), dim3(1024), 0, s, b);
   CG_TRY(hipGetLastError());
@@ -521,35 +521,35 @@ int run_batched2(const cg::BatchArgs &a, int64_t n_max, void *workspace, hipStre
   if (factor) {
     for (int st = 0; st < nsteps; ++st) {
       if (st > 0) {
-        hipLaunchKernelGGL(cg::b2_up_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, st);
+        hipLaunchKernelGGL(cg::b2_up_kernel<T>, dim3(B2_GRID_TILE), dim3(256), 0, s, b, st);
         CG_TRY(hipGetLastError());
       }
-      hipLaunchKernelGGL(cg::b2_potf2_kernel, dim3(gd), dim3(256), 0, s, b, st);
+      hipLaunchKernelGGL(cg::b2_potf2_kernel<T>, dim3(gd), dim3(256), 0, s, b, st);
       CG_TRY(hipGetLastError());
       if (st + 1 < nsteps) {
-        hipLaunchKernelGGL(cg::b2_f2_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, st);
+        hipLaunchKernelGGL(cg::b2_f2_kernel<T>, dim3(B2_GRID_TILE), dim3(256), 0, s, b, st);
         CG_TRY(hipGetLastError());
       }
     }
   } else {
-    hipLaunchKernelGGL(cg::b2_trinv_kernel, dim3(B2_GRID_DIAG), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(cg::b2_trinv_kernel<T>, dim3(B2_GRID_DIAG), dim3(256), 0, s, b);
     CG_TRY(hipGetLastError());
   }
   if (a.op == cg::BATCH_FACTOR) return CHOL_SUCCESS;
   for (int t = 0; t < nsteps; ++t) {
     if (t > 0) {
-      hipLaunchKernelGGL(cg::b2_r0_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, t);
+      hipLaunchKernelGGL(cg::b2_r0_kernel<T>, dim3(B2_GRID_TILE), dim3(256), 0, s, b, t);
       CG_TRY(hipGetLastError());
-      hipLaunchKernelGGL(cg::b2_r1_kernel, dim3(B2_GRID_TILE), dim3(256), 0, s, b, t);
+      hipLaunchKernelGGL(cg::b2_r1_kernel<T>, dim3(B2_GRID_TILE), dim3(256), 0, s, b, t);
       CG_TRY(hipGetLastError());
-      hipLaunchKernelGGL(cg::b2_r2_kernel, dim3(gl), dim3(256), 0, s, b, t);
+      hipLaunchKernelGGL(cg::b2_r2_kernel<T>, dim3(gl), dim3(256), 0, s, b, t);
       CG_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(cg::b2_r3_kernel, dim3(gd), dim3(256), 0, s, b, t);
+    hipLaunchKernelGGL(cg::b2_r3_kernel<T>, dim3(gd), dim3(256), 0, s, b, t);
     CG_TRY(hipGetLastError());
   }
   if (a.sbar_form == CHOL_SBAR_TRIL) {
-    hipLaunchKernelGGL(cg::b2_form_kernel, dim3(gl), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(cg::b2_form_kernel<T>, dim3(gl), dim3(256), 0, s, b);
     CG_TRY(hipGetLastError());
   }
   return CHOL_SUCCESS;
@@ -560,7 +560,7 @@ int run_batched(cg::BatchArgs a, int64_t n_max, void *workspace, size_t workspac
   const size_t need = batched_ws_bytes(a.batch, n_max, a.f32 != 0);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
     return CHOL_ERR_WORKSPACE;
-  if (batch2_op(a)) return run_batched2(a, n_max, workspace, s);
+  if (batch2_op(a)) return a.f32 ? run_batched2<float>(a, n_max, workspace, s) : run_batched2<double>(a, n_max, workspace, s);
   carve_batch(a.batch, n_max, a.f32 != 0, workspace, &ws);
   a.order = ws.order;
   a.counter = ws.counter;

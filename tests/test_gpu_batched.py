@@ -180,13 +180,17 @@ def test_gp_batch_of_2048(cg, dev):
 
 
 # ------------------------------------------------------------------------------------------------
-# FP32 storage (computed in FP64 inside the library, rounded once on output).  Against the oracle
-# on the same float inputs the only difference is that final rounding: relative Frobenius error at
-# most 2^-24 plus the FP64 gate, so F32_SAME = 1e-7.  End to end against the FP64 oracle on the
-# FP64 inputs (input rounding amplified by conditioning, kappa <= 41 on the batched workload):
-# stated tolerances relL <= 3e-7, rel Sigma-bar <= 3e-6, rel f <= 1e-6 (CPU emulation of the same
-# rounding measured at most 5.0e-8, 3.4e-7 and 2.1e-7).
+# FP32 storage.  chol_fwd_batched widens each problem to FP64 and rounds once on output: against
+# the oracle on the same float inputs the only difference is that rounding (relative Frobenius
+# error at most 2^-24 plus the FP64 gate), F32_SAME = 1e-7.  The factor, reverse and GP calls
+# compute in FP64 inside each block step and round every value they store to FP32 (the matrices
+# are updated in place between steps): against the oracle on the same float inputs, stated
+# relL <= 3e-7, rel Sigma-bar <= 7e-6, rel f <= 6e-7 (measured on the SIZES problems 3.4e-8,
+# 6.8e-7, 5.6e-8: about a tenth).  End to end against the FP64 oracle on the FP64 inputs (input
+# rounding amplified by conditioning, kappa <= 41 on the batched workload): stated relL <= 3e-7,
+# rel Sigma-bar <= 3e-6, rel f <= 1e-6 (measured over 64 sampled problems 5.8e-8, 4.2e-7, 1.9e-7).
 F32_SAME = 1e-7
+F32_STEP_L, F32_STEP_SBAR, F32_STEP_F = 3e-7, 7e-6, 6e-7
 
 
 def f32(x):
@@ -204,7 +208,7 @@ def test_factor_batched_f32(cg, dev):
     assert info.cpu().tolist() == [0] * len(P)
     for p, m in zip(P, mats):
         Lg = m.cpu().numpy().astype(np.float64)
-        assert rel(Lg, O.chol(widened(p["S"]))[0]) <= F32_SAME
+        assert rel(Lg, O.chol(widened(p["S"]))[0]) <= F32_STEP_L
         assert rel(Lg, O.chol(p["S"])[0]) <= 3e-7
         assert np.all(np.triu(Lg, 1) == 0)
 
@@ -217,7 +221,7 @@ def test_rev_batched_f32(cg, dev, form):
     cg.chol_rev_batched(Ls, As, form=form)
     for p, a in zip(P, As):
         want = O.chol_rev(widened(p["L"]), widened(p["Lb"]), form)
-        assert rel(a.cpu().numpy().astype(np.float64), want) <= F32_SAME
+        assert rel(a.cpu().numpy().astype(np.float64), want) <= F32_STEP_SBAR
 
 
 def test_fwd_batched_f32(cg, dev):
@@ -244,9 +248,9 @@ def test_gp_batched_f32(cg, dev):
     for i, (p, g) in enumerate(zip(P, Gs)):
         Lo, _ = O.chol(widened(p["S"]))
         fo, Lbar = O.gp_loss_and_lbar(Lo, widened(p["y"]))
-        assert f[i] == pytest.approx(fo, rel=6e-8, abs=1e-30)
-        assert rel(g.cpu().numpy().astype(np.float64), O.chol_rev(Lo, Lbar)) <= F32_SAME
-        assert rel(As[i].cpu().numpy().astype(np.float64), Lo) <= F32_SAME
+        assert f[i] == pytest.approx(fo, rel=F32_STEP_F, abs=1e-30)
+        assert rel(g.cpu().numpy().astype(np.float64), O.chol_rev(Lo, Lbar)) <= F32_STEP_SBAR
+        assert rel(As[i].cpu().numpy().astype(np.float64), Lo) <= F32_STEP_L
 
 
 def test_f32_alone_equals_in_batch_bitwise(cg, dev):

@@ -51,12 +51,14 @@ def test_factor_rev_batched(cg, dtype):
     G = [to_dev(cast(Lb)) for Lb in Lb_list]
     info = cg.chol_factor_rev_batched(A, G)
     assert info.cpu().tolist() == [0] * len(sizes)
-    tol = 1e-10 if dtype == "f64" else 1e-7
+    # FP32 storage rounds the values each block step stores (stated in include/cholgrad.h):
+    # against the oracle on the same float inputs relL <= 3e-7, rel Sigma-bar <= 7e-6
+    tol_l, tol_s = (1e-10, 1e-10) if dtype == "f64" else (3e-7, 7e-6)
     for S, Lb, a, g in zip(S_list, Lb_list, A, G):
         S, Lb = cast(S).astype(np.float64), cast(Lb).astype(np.float64)
         L = O.chol(S)[0]
-        assert rel(a.cpu().numpy().astype(np.float64), L) <= tol
-        assert rel(g.cpu().numpy().astype(np.float64), O.chol_rev(L, Lb)) <= tol
+        assert rel(a.cpu().numpy().astype(np.float64), L) <= tol_l
+        assert rel(g.cpu().numpy().astype(np.float64), O.chol_rev(L, Lb)) <= tol_s
     del torch
 
 
