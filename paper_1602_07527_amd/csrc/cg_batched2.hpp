@@ -294,6 +294,31 @@ __device__ __forceinline__ void t64_each(const dbl4 (&acc)[2][2], F out) {
       for (int e = 0; e < 4; ++e) out(t64_row(x, e), t64_col(y), acc[x][y][e]);
 }
 
+// Split-K SYRK partials of the single-matrix reverse sweep on 64 x 64 tiles:
+//   P[z][x][y] = sum_{k in split z} Cb[k][x] L[k][y]   for the lower 64-tiles (x >= y) of a w x w
+// output (w <= 256; K = m rows of the block column), workgroup blockIdx.x = u + ntiles * z with u
+// the lower tile in row order.  Many small tiles fill the GPU with short K-splits and write less
+// partial data than 128 x 128 tiles would; the splits are summed in order by the caller's reduction.
+__global__ __launch_bounds__(256) void syrk_t64_kernel(int m, int w, const double *Cb, int64_t ldcb, const double *L,
+                                                        int64_t ldl, int kchunk, double *P) {
+  __shared__ double lds[T64_LDS];
+  const int nt = (w + B2_NB - 1) / B2_NB, ntiles = nt * (nt + 1) / 2;
+  const int u = blockIdx.x % ntiles, z = blockIdx.x / ntiles;
+  int ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
+  const int tj = u - ti * (ti + 1) / 2;
+  const int k0 = z * kchunk, K = min(m, k0 + kchunk) - k0;
+  const int x0 = ti * B2_NB, y0 = tj * B2_NB;
+  dbl4 acc[2][2];
+  t64_mma<false, false>(
+      acc, [&](int x, int kk) { return (x0 + x < w) ? Cb[(int64_t)(k0 + kk) * ldcb + x0 + x] : 0.0; },
+      [&](int kk, int y) { return (y0 + y < w) ? L[(int64_t)(k0 + kk) * ldl + y0 + y] : 0.0; }, K, lds);
+  double *Pz = P + (int64_t)z * w * w;
+  t64_each(acc, [&](int r, int c, double v) {
+    if (x0 + r < w && y0 + c < w) Pz[(int64_t)(x0 + r) * w + y0 + c] = v;
+  });
+}
+
 // ---------------------------------------------------------------------------------------------
 // Diagonal blocks (w <= 64) one WAVE each: the Level-2 cores of cg_diag.hpp are single-wave
 // already, so a wave can run a whole 64-block -- its two 32-column inner blocks, the products

@@ -427,6 +427,36 @@ hipError_t panel_solve_t(int M, int w, double *C, int64_t ldc, const double *din
   return copy_scaled(M, w, tmp, nb, 1.0, C, ldc, 0, s);
 }
 
+// The reverse sweep's D-bar <- tril(L-bar_D) - tril(C-bar^T C) (w x w output, K = m), with C-bar/2
+// in Cb: FP64 blocks wider than 128 take the 64 x 64-tile split-K kernel (10 lower tiles at w = 256,
+// about SYRK_WGS workgroups, K-splits at least 64 deep) and the grouped fixed-order split sum; the
+// 128 x 128-tile product left them with too few workgroups or too much partial data (measured at
+// w = 256 on MI355X: 22.5 us per step on average against 29.1, 36.7 us at m = 16128 against 50;
+// N = 16384 chol_rev 50.4 -> 49.8 ms); everything else the general product.
+constexpr int SYRK_WGS = 480;  // workgroups of the 64-tile SYRK (measured: 960 and 1920 slower)
+
+hipError_t rev_syrk(int w, int m, const double *Cb, int64_t ldcb, const double *Lc, int64_t ldl, const double *Ld,
+                    int64_t ldd, double *dblk, int nb, PartBuf part, hipStream_t s, int cp) {
+  const int nt = (int)cdiv(w, cg::B2_NB), ntiles = nt * (nt + 1) / 2;
+  if (w > cg::GEMM_BN && cp == cg::CP_F64 && part.p) {
+    int S = std::max(1, std::min<int>(SYRK_WGS / ntiles, (int)cdiv(m, 64)));
+    S = (int)std::min<int64_t>(S, part.slots * TILE_ELEMS / ((int64_t)w * w));
+    const int kchunk = (int)cdiv(m, S);
+    S = (int)cdiv(m, kchunk);
+    hipLaunchKernelGGL(cg::syrk_t64_kernel, dim3((unsigned)(ntiles * S)), dim3(256), 0, s, m, w, Cb, ldcb, Lc, ldl,
+                       kchunk, part.p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int blocks = (int)std::min<int64_t>(cdiv((int64_t)w * w, cg::RG_ELEMS), 4096);
+    hipLaunchKernelGGL(cg::reduce_splits_grouped_kernel, dim3(blocks), dim3(256), 0, s, w, w, (const double *)part.p,
+                       (int64_t)w, (int64_t)w * w, S, -2.0, Ld, ldd, 1.0, dblk, (int64_t)nb, nullptr, (int64_t)0, 1);
+    return hipGetLastError();
+  }
+  // K-split depth of the general product: deeper splits over long K
+  const int kc = w <= cg::GEMM_BN ? 64 : m <= 2048 ? 32 : m <= 4096 ? 64 : m <= 12288 ? 128 : 256;
+  return gemm(true, false, w, w, m, Cb, ldcb, Lc, ldl, -2.0, Ld, ldd, 1.0, dblk, nb, nullptr, 0, 1, part, kc, s, 0, cp);
+}
+
 #define CG_TRY(expr)                          \
   do {                                        \
     hipError_t _e = (expr);                   \
@@ -778,13 +808,8 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
       // caller's stream, before the next step's bulk product is queued: a small split-K product
       // that runs fastest with the whole GPU to itself, and the diagonal adjoint released after
       // it then finds a free compute unit while that bulk product runs.
-      // K-split depth: the partial tiles written and re-read by the split sum cost about as much
-      // as the product's own loads at 64-deep splits; deeper splits over long K (measured at
-      // w = 256 on MI355X: m = 2048 32 -> 23 us, m = 8192 128 -> 33 us against 40 at 64,
-      // m = 16128 256 -> 50 us against 66 at 64).
-      const int syrk_kc = w <= cg::GEMM_BN ? 64 : m <= 2048 ? 32 : m <= 4096 ? 64 : m <= 12288 ? 128 : 256;
-      CG_TRY(gemm(true, false, w, w, m, A + k * lda + j, lda, L + k * ldl + j, ldl, -2.0,
-                  A + j * lda + j, lda, 1.0, ws.dblk, nb, nullptr, 0, 1, ws.part, syrk_kc, s, 0, cp));
+      CG_TRY(rev_syrk(w, m, A + k * lda + j, lda, L + k * ldl + j, ldl, A + j * lda + j, lda, ws.dblk, nb, ws.part,
+                      s, cp));
     } else {
       CG_TRY(copy_scaled(w, w, A + j * lda + j, lda, 1.0, ws.dblk, nb, 1, s));
     }
