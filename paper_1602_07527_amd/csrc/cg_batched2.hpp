@@ -234,15 +234,21 @@ __device__ __forceinline__ void t64_mma(dbl4 (&acc)[2][2], FA A, FB B, int K, do
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0, 0, 0, 0};
   constexpr int NL = T64_BK / 4;  // loads per thread per operand and stage
-  double ra[NL], rb[NL];
+  // Prefetch registers in the operands' own storage types (the accessors' return types): values
+  // are widened only when they go to LDS, so a float operand's loads stay in flight across the
+  // K-step instead of being waited for by an early conversion.
+  typedef decltype(A(0, 0)) TA;
+  typedef decltype(B(0, 0)) TB;
+  TA ra[NL];
+  TB rb[NL];
   auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
       const int e = u * 256 + tid;
       const int i = AK ? (e / T64_BK) : (e & 63), k = AK ? (e % T64_BK) : (e >> 6);
-      ra[u] = (k0 + k < K) ? A(i, k0 + k) : 0.0;
+      ra[u] = (k0 + k < K) ? A(i, k0 + k) : TA(0);
       const int j = BK ? (e / T64_BK) : (e & 63), kb = BK ? (e % T64_BK) : (e >> 6);
-      rb[u] = (k0 + kb < K) ? B(k0 + kb, j) : 0.0;
+      rb[u] = (k0 + kb < K) ? B(k0 + kb, j) : TB(0);
     }
   };
   auto store = [&](int st) {
@@ -250,9 +256,9 @@ __device__ __forceinline__ void t64_mma(dbl4 (&acc)[2][2], FA A, FB B, int K, do
     for (int u = 0; u < NL; ++u) {
       const int e = u * 256 + tid;
       const int i = AK ? (e / T64_BK) : (e & 63), k = AK ? (e % T64_BK) : (e >> 6);
-      As(st)[k * T64_LD + i] = ra[u];
+      As(st)[k * T64_LD + i] = (double)ra[u];
       const int j = BK ? (e / T64_BK) : (e & 63), kb = BK ? (e % T64_BK) : (e >> 6);
-      Bs(st)[kb * T64_LD + j] = rb[u];
+      Bs(st)[kb * T64_LD + j] = (double)rb[u];
     }
   };
   const int nkt = (K + T64_BK - 1) / T64_BK;
@@ -334,16 +340,16 @@ template <typename T>
 __device__ __forceinline__ void wave_load_lower(double *Dp, const T *src, int64_t ld, int w) {
   const int lane = threadIdx.x & 63;
   for (int r0 = 0; r0 < w; r0 += 16) {
-    double v[16];
+    T v[16];  // in the source's type: widened as they go to LDS, after all sixteen are in flight
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int r = r0 + u;
-      v[u] = (r < w && lane <= r) ? src[(int64_t)r * ld + lane] : 0.0;
+      v[u] = (r < w && lane <= r) ? src[(int64_t)r * ld + lane] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int r = r0 + u;
-      if (r < w && lane <= r) Dp[pidx(r, lane)] = v[u];
+      if (r < w && lane <= r) Dp[pidx(r, lane)] = (double)v[u];
     }
   }
 }
@@ -680,7 +686,7 @@ __global__ __launch_bounds__(256) void b2_f2_kernel(B2Args a, int s) {
     const double *Di = a.dinv + p * a.dinv_stride + s * B2_BLK;
     dbl4 acc[2][2];
     t64_mma<true, true>(
-        acc, [&](int r, int kk) { return (r < R && kk < w) ? Ai[(int64_t)(r0 + r) * lda + j + kk] : 0.0; },
+        acc, [&](int r, int kk) { return (r < R && kk < w) ? Ai[(int64_t)(r0 + r) * lda + j + kk] : T(0); },
         [&](int kk, int c) { return (c < w && kk <= c) ? Di[c * B2_NB + kk] : 0.0; }, w, lds);
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w) {
@@ -735,8 +741,8 @@ __global__ __launch_bounds__(256) void b2_up_kernel(B2Args a, int s) {
     const int64_t lda = a.lda[i];
     dbl4 acc[2][2];
     t64_mma<true, true>(
-        acc, [&](int r, int kk) { return (r < R) ? (double)Ai[(int64_t)(r0 + r) * lda + kk] : 0.0; },
-        [&](int kk, int c) { return (c < w) ? (double)Ai[(int64_t)(j + c) * lda + kk] : 0.0; }, j, lds);
+        acc, [&](int r, int kk) { return (r < R) ? Ai[(int64_t)(r0 + r) * lda + kk] : T(0); },
+        [&](int kk, int c) { return (c < w) ? Ai[(int64_t)(j + c) * lda + kk] : T(0); }, j, lds);
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w && (ti > 0 || c <= r)) {
         T *d = Ai + (int64_t)(r0 + r) * lda + j + c;
@@ -830,8 +836,8 @@ __global__ __launch_bounds__(256) void b2_r0_kernel(B2Args a, int t) {
     T *Gi = b2_G<T>(a, i, ldg);
     dbl4 acc[2][2];
     t64_mma<true, false>(
-        acc, [&](int r, int kk) { return (r < R && kk < m) ? Gi[(int64_t)(r0 + r) * ldg + k + kk] : 0.0; },
-        [&](int kk, int c) { return (c < w && kk < m) ? Li[(int64_t)(k + kk) * ldl + j + c] : 0.0; }, m, lds);
+        acc, [&](int r, int kk) { return (r < R && kk < m) ? Gi[(int64_t)(r0 + r) * ldg + k + kk] : T(0); },
+        [&](int kk, int c) { return (c < w && kk < m) ? Li[(int64_t)(k + kk) * ldl + j + c] : T(0); }, m, lds);
     const bool gp = a.op == BATCH_GP;
     const double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
     t64_each(acc, [&](int r, int c, double v) {
@@ -864,7 +870,7 @@ __global__ __launch_bounds__(256) void b2_r1_kernel(B2Args a, int t) {
     const double *Di = a.dinv + p * a.dinv_stride + b * B2_BLK;
     dbl4 acc[2][2];
     t64_mma<true, false>(
-        acc, [&](int r, int kk) { return (r < R && kk < w) ? Gi[(int64_t)(r0 + r) * ldg + j + kk] : 0.0; },
+        acc, [&](int r, int kk) { return (r < R && kk < w) ? Gi[(int64_t)(r0 + r) * ldg + j + kk] : T(0); },
         [&](int kk, int c) { return (c < w && kk < w && kk >= c) ? Di[kk * B2_NB + c] : 0.0; }, w, lds);
     t64_each(acc, [&](int r, int c, double v) {
       if (r < R && c < w) {
@@ -899,8 +905,8 @@ __global__ __launch_bounds__(256) void b2_r2_kernel(B2Args a, int t) {
     const double *zg = a.vec + p * a.vec_stride, *wg = zg + a.n_max;
     dbl4 acc[2][2];
     t64_mma<false, false>(
-        acc, [&](int x, int kk) { return (x < w) ? Gi[(int64_t)(k + kk) * ldg + j + x] : 0.0; },
-        [&](int kk, int y) { return (y < w) ? Li[(int64_t)(k + kk) * ldl + j + y] : 0.0; }, m, lds);
+        acc, [&](int x, int kk) { return (x < w) ? Gi[(int64_t)(k + kk) * ldg + j + x] : T(0); },
+        [&](int kk, int y) { return (y < w) ? Li[(int64_t)(k + kk) * ldl + j + y] : T(0); }, m, lds);
     t64_each(acc, [&](int x, int y, double v) {
       if (x < w && y <= x) {
         T *d = Gi + (int64_t)(j + x) * ldg + j + y;
