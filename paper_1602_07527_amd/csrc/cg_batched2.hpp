@@ -96,22 +96,34 @@ __device__ __forceinline__ bool b2_factor_op(int op) {
 // compute in FP64 and round every value they store): A, the factor of problem i (the factor ops
 // overwrite A with it; REV reads L), the array the reverse sweep works in (REV: A; GP and
 // FACTOR_REV: G), y and the losses.
+// The pointers come out of pointer arrays in device memory, so the compiler cannot tell which
+// memory they address, and accesses through them compile to flat loads and stores, which also
+// count against the LDS wait counter: every LDS wait in the tile loops after a store would wait
+// for the store as well.  Re-typed as a global-memory pointer, passed through an empty asm (else
+// the compiler folds the two casts away and the pointer is generic again), they compile to global
+// loads and stores.
 template <typename T>
-__device__ __forceinline__ T *b2_A(const B2Args &a, int i) { return reinterpret_cast<T *>(a.A[i]); }
+__device__ __forceinline__ T *as_global(T *p) {
+  __attribute__((address_space(1))) T *q = (__attribute__((address_space(1))) T *)p;
+  asm("" : "+v"(q));
+  return (T *)q;
+}
+template <typename T>
+__device__ __forceinline__ T *b2_A(const B2Args &a, int i) { return as_global(reinterpret_cast<T *>(a.A[i])); }
 template <typename T>
 __device__ __forceinline__ const T *b2_L(const B2Args &a, int i, int64_t &ld) {
-  if (a.op == BATCH_REV) { ld = a.ldl[i]; return reinterpret_cast<const T *>(a.L[i]); }
+  if (a.op == BATCH_REV) { ld = a.ldl[i]; return as_global(reinterpret_cast<const T *>(a.L[i])); }
   ld = a.lda[i];
-  return reinterpret_cast<const T *>(a.A[i]);
+  return as_global(reinterpret_cast<T *>(a.A[i]));
 }
 template <typename T>
 __device__ __forceinline__ T *b2_G(const B2Args &a, int i, int64_t &ld) {
-  if (a.op == BATCH_REV) { ld = a.lda[i]; return reinterpret_cast<T *>(a.A[i]); }
+  if (a.op == BATCH_REV) { ld = a.lda[i]; return as_global(reinterpret_cast<T *>(a.A[i])); }
   ld = a.ldg[i];
-  return reinterpret_cast<T *>(a.G[i]);
+  return as_global(reinterpret_cast<T *>(a.G[i]));
 }
 template <typename T>
-__device__ __forceinline__ double b2_y(const B2Args &a, int i, int r) { return reinterpret_cast<const T *>(a.y[i])[r]; }
+__device__ __forceinline__ double b2_y(const B2Args &a, int i, int r) { return as_global(reinterpret_cast<const T *>(a.y[i]))[r]; }
 template <typename T>
 __device__ __forceinline__ void b2_set_f(const B2Args &a, int i, double v) { reinterpret_cast<T *>(a.f)[i] = (T)v; }
 
@@ -334,8 +346,10 @@ __global__ __launch_bounds__(256) void syrk_t64_kernel(int m, int w, const doubl
 constexpr int B2W_WAVES = 4;
 constexpr int B2W_LDS = 2 * B2_PACKED;  // doubles per wave
 
-// Packed lower triangle of a w x w block (w <= 64, row-major source) into Dp, by one wave, sixteen
-// rows of loads in flight.
+// Packed lower triangle of a w x w block (1 <= w <= 64, row-major source) into Dp, by one wave,
+// sixteen rows of loads in flight.  The loads are unconditional, their row and column clamped into
+// the block's lower triangle: a load under a per-row condition gets its own branch, and in FP32
+// storage the widening then follows it inside the branch with a wait, one row at a time.
 template <typename T>
 __device__ __forceinline__ void wave_load_lower(double *Dp, const T *src, int64_t ld, int w) {
   const int lane = threadIdx.x & 63;
@@ -343,8 +357,8 @@ __device__ __forceinline__ void wave_load_lower(double *Dp, const T *src, int64_
     T v[16];  // in the source's type: widened as they go to LDS, after all sixteen are in flight
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int r = r0 + u;
-      v[u] = (r < w && lane <= r) ? src[(int64_t)r * ld + lane] : T(0);
+      const int r = min(r0 + u, w - 1);
+      v[u] = src[(int64_t)r * ld + min(lane, r)];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
