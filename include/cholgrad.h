@@ -254,24 +254,24 @@ int chol_factor_fwd(int precision, int64_t n, void *A, int64_t lda, void *D, int
 
 /*
  * Batched forms: many independent problems per call, Sec. 4.2's blocked algorithms applied per
- * problem.  FP64 chol_factor_batched, chol_rev_batched, chol_factor_rev_batched and
- * chol_gp_nll_batched run step-synchronous on 64-wide blocks: a plan built on the device orders
- * the problems largest first, then each block step is one grouped launch per kind over every
- * problem that has that step (block-column updates and panel products as 64 x 64 MFMA tiles,
- * diagonal blocks one wave each).  chol_fwd_batched and FP32 storage run one persistent launch
- * (one workgroup per problem at a time, nb = 128).  All per-problem arguments are DEVICE arrays
+ * problem.  chol_factor_batched, chol_rev_batched, chol_factor_rev_batched and
+ * chol_gp_nll_batched run step-synchronous on 64-wide blocks, in FP64 or FP32 storage: a plan
+ * built on the device orders the problems largest first, then each block step is one grouped
+ * launch per kind over every problem that has that step (block-column updates and panel products
+ * as 64 x 64 MFMA tiles, diagonal blocks one wave each).  chol_fwd_batched runs one persistent
+ * launch (one workgroup per problem at a time, nb = 128).  All per-problem arguments are DEVICE arrays
  * with `batch` entries: n[b] is the size of problem b, A[b] (and L[b], y[b], G[b]) are device
  * pointers to its row-major data with leading dimensions lda[b] (ldl[b], ldg[b]) >= n[b].  n_max
  * (host value, <= 512) bounds every n[b]; n_max above 512 returns CHOL_ERR_UNSUPPORTED.  A problem
  * whose size is outside [0, n_max] or whose leading dimension is smaller than its size is skipped
  * (its info entry, where there is one, becomes -1).  Each problem's result does not depend on the
  * batch it is in.  Workspace: chol_batched_workspace_bytes(precision, batch, n_max) bytes, 256-byte
- * aligned: for FP64 the larger of the two paths' needs -- the step-synchronous path's plan, the
- * inverses of every problem's 64-blocks and two vectors per problem (about 528 * n_max bytes per
- * problem: 554 MB for 2048 problems at n_max = 512) and the persistent kernel's scratch (about
- * 1.2 MB per workgroup, one workgroup per problem up to 256: 304 MB); CHOL_PREC_F32 takes the
- * persistent kernel's scratch plus 16 * n_max^2 bytes of FP64 staging per workgroup (1.38 GB for
- * 256 or more problems at n_max = 512).
+ * aligned: the larger of the two paths' needs -- the step-synchronous path's plan, the inverses
+ * of every problem's 64-blocks and two vectors per problem (about 528 * n_max bytes per problem:
+ * 554 MB for 2048 problems at n_max = 512) and the persistent kernel's scratch (1.05 MB per
+ * workgroup, one workgroup per problem up to 256: 268 MB), which for CHOL_PREC_F32 adds
+ * 16 * n_max^2 bytes of FP64 staging per workgroup (1.34 GB in all for 256 or more problems at
+ * n_max = 512).
  * Semantics per problem are those of the single-matrix calls above.
  */
 size_t chol_batched_workspace_bytes(int precision, int batch, int64_t n_max);

@@ -9,7 +9,8 @@ Public calls (torch tensors as device memory, work on the current stream):
 (single-matrix options: diag='auto' | 'symbolic' | 'level2' for the diagonal-block variant of
 chol_rev / chol_fwd, layout='row' | 'col' for row- or column-major storage, precision for the
 reduced-precision trailing modes) and their batched forms (many matrices, n <= 512, one
-persistent launch), including a fused
+call each: step-synchronous grouped launches, or one persistent launch for the forward sweep),
+including a fused
 factor + reverse sweep (chol_factor_rev_batched) and a fused Gaussian-process loss
 (chol_gp_nll_batched: Sigma -> L -> f -> Sigma-bar per matrix).  `autograd` wraps them as
 torch.autograd Functions; `serve` runs a continuous-batching request loop on top of them.

@@ -259,7 +259,8 @@ def profile_end():
 
 
 # ------------------------------------------------------------------------------------------------
-# Batched forms (one persistent launch per call)
+# Batched forms (one call over many problems: step-synchronous grouped launches, or one
+# persistent launch for the forward sweep)
 
 BATCH_NMAX = 512
 

@@ -464,7 +464,7 @@ hipError_t rev_syrk(int w, int m, const double *Cb, int64_t ldcb, const double *
   } while (0)
 
 // ---------------------------------------------------------------------------------------------
-// Batched forms: one persistent launch of cg::batch_kernel with BATCH_WGS workgroups.
+// Batched forward sweep: one persistent launch of cg::batch_fwd_kernel with BATCH_WGS workgroups.
 constexpr int BATCH_WGS = 256;  // one 140 KB-LDS workgroup per compute unit of an MI355X
 
 struct BatchWs {
@@ -474,8 +474,8 @@ struct BatchWs {
   double *stage = nullptr;
 };
 
-// Workspace of a batched call: processing order, work counter, one slot per workgroup and, for
-// FP32 storage, one FP64 staging area per workgroup.
+// Workspace of the persistent kernel: processing order, work counter, one slot per workgroup and,
+// for FP32 storage, one FP64 staging area per workgroup.
 size_t carve_batch(int batch, int64_t n_max, bool f32, void *base, BatchWs *w) {
   Carver c(base);
   w->order = reinterpret_cast<int *>(c.take((size_t)cdiv(batch, 2)));
@@ -485,7 +485,7 @@ size_t carve_batch(int batch, int64_t n_max, bool f32, void *base, BatchWs *w) {
   return c.off;
 }
 
-// Workspace of the step-synchronous batched path (FP64 storage; cg_batched2.hpp): the plan
+// Workspace of the step-synchronous batched path (cg_batched2.hpp): the plan
 // (order, sizes, B2_NPREF prefix arrays, step counts) and per problem ceil(n_max / 64) block
 // inverses and the two GP vectors.
 struct Batch2Ws {
@@ -508,9 +508,9 @@ size_t carve_batch2(int batch, int64_t n_max, void *base, Batch2Ws *w) {
   return c.off;
 }
 
-// Workspace of a batched call: enough for either path (FP64 storage: the step-synchronous path
-// of the factor, reverse, GP and factor + reverse calls or the persistent kernel of the forward
-// call; FP32 storage: the persistent kernel).
+// Workspace of a batched call: enough for either path (the step-synchronous path of the factor,
+// reverse, GP and factor + reverse calls, or the persistent kernel of the forward call, which
+// with FP32 storage also needs its FP64 staging).
 size_t batched_ws_bytes(int batch, int64_t n_max, bool f32) {
   BatchWs w;
   const size_t v1 = carve_batch(batch, n_max, f32, nullptr, &w);
@@ -518,7 +518,7 @@ size_t batched_ws_bytes(int batch, int64_t n_max, bool f32) {
   return std::max(v1, carve_batch2(batch, n_max, nullptr, &w2));
 }
 
-// FP64 factor, reverse, GP and factor + reverse batches take the step-synchronous path: a plan,
+// Factor, reverse, GP and factor + reverse batches take the step-synchronous path: a plan,
 // then per 64-wide block step one grouped launch of each kind over every problem that has the
 // step (cg_batched2.hpp), all on stream s.
 constexpr int B2_GRID_DIAG = 256;    // diagonal blocks, one per wave: 133 KB of LDS, one per compute unit
@@ -601,14 +601,9 @@ int run_batched(cg::BatchArgs a, int64_t n_max, void *workspace, size_t workspac
   hipLaunchKernelGGL(cg::batch_order_kernel, dim3(1), dim3(256), 0, s, a.batch, a.n, (int)n_max, ws.order,
                      ws.counter);
   CG_TRY(hipGetLastError());
+  if (a.op != cg::BATCH_FWD) return CHOL_ERR_UNSUPPORTED;  // every other op is step-synchronous
   const dim3 grid(std::min(a.batch, BATCH_WGS)), block(cg::DIAG_THREADS);
-  switch (a.op) {
-    case cg::BATCH_FACTOR: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FACTOR>, grid, block, 0, s, a); break;
-    case cg::BATCH_REV: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_REV>, grid, block, 0, s, a); break;
-    case cg::BATCH_FWD: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FWD>, grid, block, 0, s, a); break;
-    case cg::BATCH_GP: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_GP>, grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL(cg::batch_kernel<cg::BATCH_FACTOR_REV>, grid, block, 0, s, a); break;
-  }
+  hipLaunchKernelGGL(cg::batch_fwd_kernel, grid, block, 0, s, a);
   CG_TRY(hipGetLastError());
   return CHOL_SUCCESS;
 }

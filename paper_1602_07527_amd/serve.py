@@ -13,7 +13,7 @@ Scheduling, one `step()` at a time on the host:
     footprint: its two n x n FP64 buffers plus its workspace; a group of small requests is
     charged the workspace of its one batched launch);
   * launch: the admitted requests with n <= small_max (512) form ONE batched launch per step
-    (chol_factor_rev_batched: one persistent kernel for the whole group) on the small-request
+    (chol_factor_rev_batched: one call for the whole group) on the small-request
     stream; larger ones are launched one by one (chol_factor + chol_rev), each on whichever of
     the large-request streams has the fewest launches in flight.  Requests that arrive while
     earlier launches are still running are admitted and launched as soon as memory allows, so
