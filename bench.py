@@ -78,7 +78,7 @@ def traffic_for(hashes):
     return rec.get("hbm_bytes_per_launch")
 
 
-TARGET_KERNEL = "gemm_f64_dma_kernel<false, false, 1, 0, false>"
+TARGET_KERNEL = "gemm_f64_dma_kernel<false, false, 1, 0, false, true>"
 CALIBRATION_KERNEL = "neg_kernel"
 
 
@@ -606,7 +606,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": traffic,
-                "kernel": "gemm_f64_dma_kernel<false,false,1,0,false> (reverse-sweep panel contraction, FP64 MFMA, stream-K)",
+                "kernel": "gemm_f64_dma_kernel<false,false,1,0,false,true> (reverse-sweep panel contraction, 128x256 tiles, FP64 MFMA, stream-K)",
                 "kernel_avg_us": round(k_ms * 1e3 / max(k_launch, 1), 2),
                 "algorithmic_bytes_per_launch": round(k_bytes / max(k_launch, 1)),
                 "algorithmic_flops_per_launch": round(k_flops / max(k_launch, 1)),
