@@ -37,11 +37,13 @@ def test_ingest_pmc_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(tmp_path / "rec.json"))
-    tgt = "void cg::gemm_f64_dma_kernel<false, false, 1, 0, false>(cg::GemmArgs)"
+    tgt = f"void cg::{bench.TARGET_KERNEL}(cg::GemmArgs)"
+    narrow = "void cg::gemm_f64_dma_kernel<false, false, 1, 0, false, false>(cg::GemmArgs)"
     cal = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(...)>"
-    # The calibration copy of 64 MiB reads as 32768 KiB: every raw value is half the truth.
+    # The calibration copy of 64 MiB reads as 32768 KiB: every raw value is half the truth.  The
+    # 128x128-tile instance of the same contraction is another kernel and is not counted.
     _write_counters(tmp_path / "f.csv", "FETCH_SIZE",
-                    [(cal, 32768.0), (tgt, 100.0), (tgt, 300.0), ("other", 1e9)])
+                    [(cal, 32768.0), (tgt, 100.0), (tgt, 300.0), (narrow, 1e9), ("other", 1e9)])
     _write_counters(tmp_path / "w.csv", "WRITE_SIZE", [(cal, 16384.0), (tgt, 50.0)])
     bench.ingest_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 64)
     rec = json.load(open(tmp_path / "rec.json"))
