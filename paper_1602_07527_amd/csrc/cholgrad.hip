@@ -24,6 +24,7 @@ namespace {
 
 constexpr size_t WS_ALIGN = 256;
 constexpr int DEFAULT_NB = 128;
+constexpr int FACTOR_ONE_STREAM_BLOCKS = 3;  // chol_factor sweeps this short skip the side stream
 constexpr int TARGET_WGS = 512;  // two contraction workgroups per compute unit on 256 CUs
 // Workgroups of a stream-K contraction in a sweep with a side stream: a little below the 512
 // resident slots.  The diagonal block kernels of such a sweep run beside the contractions and
@@ -935,14 +936,26 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   hipStream_t s = static_cast<hipStream_t>(stream);
   double *A = static_cast<double *>(Av);
   const int64_t nblk = cdiv(n, nb);
+  // A sweep of at most FACTOR_ONE_STREAM_BLOCKS blocks has at most one update over older columns
+  // (block 2's over block 0) to run beside its chain, so it stays on the caller's stream: the
+  // side-stream hand-overs cost more than that overlap wins (N = 256, nb = 128: 255 -> 197 us;
+  // with four blocks, N = 512 at nb = 128, the side stream is faster again).
+  const bool one = nblk <= FACTOR_ONE_STREAM_BLOCKS;
   std::lock_guard<std::mutex> lock(g_side_mu);
   Side *side = nullptr;
-  CG_TRY(side_for(s, &side));
-  hipStream_t s2 = side->s;
+  hipStream_t s2 = s;
+  if (!one) {
+    CG_TRY(side_for(s, &side));
+    s2 = side->s;
+  }
+  auto record = [&](hipEvent_t Side::*e, hipStream_t st) { return one ? hipSuccess : hipEventRecord(side->*e, st); };
+  auto wait = [&](hipStream_t st, hipEvent_t Side::*e) {
+    return one ? hipSuccess : hipStreamWaitEvent(st, side->*e, 0);
+  };
   hipLaunchKernelGGL(cg::set_int_kernel, dim3(1), dim3(1), 0, s, info, 0);
   CG_TRY(hipGetLastError());
-  CG_TRY(hipEventRecord(side->start, s));
-  CG_TRY(hipStreamWaitEvent(s2, side->start, 0));
+  CG_TRY(record(&Side::start, s));
+  CG_TRY(wait(s2, &Side::start));
   // Sec. 4.2 chol_blocked, left to right, with look-ahead.  Block b's diagonal factor needs only
   // block b's own rows updated, and those need only the rows of block b-1's panel solve that lie
   // in block b; so the chain from one diagonal factor to the next is: panel solve of the next
@@ -961,17 +974,17 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
         CG_TRY(gemm(false, true, (int)(n - j), w, (int)jp, A + j * lda, lda, A + j * lda, lda, -1.0,
                     A + j * lda + j, lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 256, s, 2, cp));
       // D <- D - D_{b,b-1} D_{b,b-1}^T   (chain: fine K-splits)
-      CG_TRY(hipStreamWaitEvent(s, side->top, 0));
+      CG_TRY(wait(s, &Side::top));
       CG_TRY(gemm(false, true, w, w, nb, A + j * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + j * lda + j,
                   lda, 1.0, A + j * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 2, cp));
-      CG_TRY(hipEventRecord(side->diag, s));
-      CG_TRY(hipStreamWaitEvent(s2, side->diag, 0));
+      CG_TRY(record(&Side::diag, s));
+      CG_TRY(wait(s2, &Side::diag));
       // C <- C - B_{b-1} D_{b,b-1}^T   (rows below block b)
       if (m > 0) {
-        CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+        CG_TRY(wait(s, &Side::panel));
         CG_TRY(gemm(false, true, m, w, nb, A + k * lda + jp, lda, A + j * lda + jp, lda, -1.0, A + k * lda + j,
                     lda, 1.0, A + k * lda + j, lda, nullptr, 0, 0, ws.part, 64, s, 2, cp));
-        CG_TRY(hipEventRecord(side->low, s));
+        CG_TRY(record(&Side::low, s));
       }
     }
     // D <- chol_unblocked(D); D^-1 for the panel solve
@@ -979,16 +992,16 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
     // C <- C tril(D)^-T, the next block's rows first
     if (m > 0) {
       const int m1 = std::min(m, nb);
-      if (b > 0) CG_TRY(hipStreamWaitEvent(s2, side->low, 0));
+      if (b > 0) CG_TRY(wait(s2, &Side::low));
       CG_TRY(panel_solve_t(m1, w, A + k * lda + j, lda, ws.dblk, nb, ws.panel, ws.part2, 32, s2));
-      CG_TRY(hipEventRecord(side->top, s2));
+      CG_TRY(record(&Side::top, s2));
       if (m > m1)
         CG_TRY(panel_solve_t(m - m1, w, A + (k + m1) * lda + j, lda, ws.dblk, nb, ws.panel + (int64_t)m1 * nb,
                              nullptr, 128, s2));
     }
-    CG_TRY(hipEventRecord(side->panel, s2));
+    CG_TRY(record(&Side::panel, s2));
   }
-  CG_TRY(hipStreamWaitEvent(s, side->panel, 0));
+  CG_TRY(wait(s, &Side::panel));
   const int blocks = (int)std::min<int64_t>(cdiv(n * n, 256), 4096);
   hipLaunchKernelGGL(cg::zero_upper_kernel, dim3(blocks), dim3(256), 0, s, n, A, lda);
   CG_TRY(hipGetLastError());
