@@ -30,8 +30,12 @@
  *     before anything is enqueued:  -i  means argument i (1-based) is invalid;  CHOL_ERR_* below.
  *     Numerical breakdown of chol_factor is reported asynchronously through `info`.
  *   - n == 0 is a no-op that returns CHOL_SUCCESS.
- *   - nb is the block size of the Level-3 sweep (Sec. 4.2, N_b): 0 selects the default (128);
- *     otherwise 16 <= nb <= 256 and nb % 16 == 0.  The result does not depend on nb beyond
+ *   - nb is the block size of the Level-3 sweep (Sec. 4.2, N_b): 0 selects a width measured per
+ *     sweep and size on MI355X -- chol_rev 256; chol_fwd 256 for n <= 8192, 128 above;
+ *     chol_factor and chol_factor_fwd 256 for 256 < n <= 512 and n >= 3072, 128 otherwise; at
+ *     most 128 with CHOL_DIAG_LEVEL2 -- and chol_workspace_bytes with nb = 0 returns the size for
+ *     nb = 256, which holds any of them; otherwise 16 <= nb <= 256 and nb % 16 == 0
+ *     (chol_rev_noalloc: nb <= 128, 0 selects 128).  The result does not depend on nb beyond
  *     rounding (the column partition is arbitrary, Sec. 4.2).  Blocks wider than 128 factor and
  *     invert their diagonal block as two halves (Sec. 4.2's remark that the unblocked routine may
  *     be replaced by a recursive one for large blocks); the Level-2 diagonal-block variant

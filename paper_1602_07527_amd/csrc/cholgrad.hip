@@ -23,7 +23,7 @@
 namespace {
 
 constexpr size_t WS_ALIGN = 256;
-constexpr int DEFAULT_NB = 128;
+constexpr int NOALLOC_DEFAULT_NB = 128;  // nb = 0 in chol_rev_noalloc
 constexpr int FACTOR_ONE_STREAM_BLOCKS = 3;  // chol_factor sweeps this short skip the side stream
 constexpr int TARGET_WGS = 512;  // two contraction workgroups per compute unit on 256 CUs
 // Workgroups of a stream-K contraction in a sweep with a side stream: a little below the 512
@@ -172,6 +172,22 @@ bool single_prec(int precision, int *cp) {
 // LDS routines hold) factor and invert their diagonal block as two halves (potf2_any, trinv).
 constexpr int NB_MAX = 2 * cg::DIAG_MAX;
 bool nb_ok(int nb) { return nb == 0 || (nb >= 16 && nb <= NB_MAX && nb % 16 == 0); }
+
+// The block width nb = 0 stands for, per sweep and size: the fastest of nb = 64, 128 and 256 in
+// event timings of the three sweeps on squared-exponential matrices, n = 256 to 16384, on one
+// MI355X.  chol_rev: 256 at every size (n = 4096: 2.00 ms against 2.66 at 128).  chol_fwd: 256 up
+// to n = 8192, 128 above (n = 12288: 25.7 ms at 128 against 26.5; n = 16384: 54 ms at 128).
+// chol_factor: 128, except 256 for n in (256, 512] (two blocks on one stream: n = 512, 430 us
+// against 496) and from n = 3072 up (n = 8192: 9.6 ms against 10.3).  chol_factor_fwd takes the
+// factor's choice.  The Level-2 diagonal variant holds blocks of at most 128.  A workspace query
+// with nb = 0 sizes for NB_MAX, which holds every one of these.
+int auto_nb(int op, int64_t n, bool level2 = false) {
+  int nb;
+  if (op == CHOL_OP_REV) nb = NB_MAX;
+  else if (op == CHOL_OP_FWD) nb = n <= 8192 ? NB_MAX : 128;
+  else nb = ((n > 256 && n <= 512) || n >= 3072) ? NB_MAX : 128;
+  return level2 ? std::min(nb, (int)cg::DIAG_MAX) : nb;
+}
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 template <int TAG, int CP>
@@ -691,7 +707,7 @@ size_t chol_workspace_bytes(int op, int precision, int64_t n, int nb) {
   int cp = cg::CP_F64;
   if (n <= 0 || !single_prec(precision, &cp) || !nb_ok(nb)) return 0;
   if (op != CHOL_OP_FACTOR && op != CHOL_OP_REV && op != CHOL_OP_FWD) return 0;
-  if (nb == 0) nb = DEFAULT_NB;
+  if (nb == 0) nb = NB_MAX;  // holds whatever width nb = 0 selects in the call
   SweepWs w;
   return carve(n, nb, nullptr, &w);
 }
@@ -720,7 +736,7 @@ static int rev_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
   if (sbar_form != CHOL_SBAR_SYM && sbar_form != CHOL_SBAR_TRIL) return -7;
   if (!nb_ok(nb)) return -8;
   if (!diag_ok(diag)) return -9;
-  if (nb == 0) nb = DEFAULT_NB;
+  if (nb == 0) nb = auto_nb(CHOL_OP_REV, n, !diag_symbolic(diag));
   if (!diag_symbolic(diag) && nb > cg::DIAG_MAX) return CHOL_ERR_UNSUPPORTED;  // Level-2 cores hold <= 128
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws, part_slots, part2_slots);
@@ -898,6 +914,7 @@ extern "C" {
 
 int chol_rev_noalloc(int precision, int64_t n, const void *Lv, int64_t ldl, void *Av, int64_t lda,
                      int sbar_form, int nb, void *stream) {
+  if (nb == 0) nb = NOALLOC_DEFAULT_NB;
   // Arguments first (a dry call without workspace), before the device is touched.
   const int chk = rev_impl(precision, n, Lv, ldl, Av, lda, sbar_form, nb, CHOL_DIAG_SYMBOLIC, nullptr, 0, stream,
                            NOALLOC_PART_SLOTS, 0);
@@ -905,7 +922,7 @@ int chol_rev_noalloc(int precision, int64_t n, const void *Lv, int64_t ldl, void
   if (n > NOALLOC_N_MAX) return CHOL_ERR_TOO_LARGE;
   if (nb > NOALLOC_NB_MAX) return -8;
   SweepWs w;
-  if (carve(n, nb ? nb : DEFAULT_NB, nullptr, &w, NOALLOC_PART_SLOTS, 0) > NOALLOC_SCRATCH_BYTES)
+  if (carve(n, nb, nullptr, &w, NOALLOC_PART_SLOTS, 0) > NOALLOC_SCRATCH_BYTES)
     return CHOL_ERR_TOO_LARGE;
   void *ws = nullptr;
   CG_TRY(scratch_ptr(&ws));
@@ -927,7 +944,7 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
   if (lda < n) return -4;
   if (!nb_ok(nb)) return -5;
   if (!info) return -6;
-  if (nb == 0) nb = DEFAULT_NB;
+  if (nb == 0) nb = auto_nb(CHOL_OP_FACTOR, n);
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)
@@ -1021,7 +1038,7 @@ static int fwd_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
   if (lda < n) return -6;
   if (!nb_ok(nb)) return -7;
   if (!diag_ok(diag)) return -8;
-  if (nb == 0) nb = DEFAULT_NB;
+  if (nb == 0) nb = auto_nb(CHOL_OP_FWD, n, !diag_symbolic(diag));
   if (!diag_symbolic(diag) && nb > cg::DIAG_MAX) return CHOL_ERR_UNSUPPORTED;  // Level-2 cores hold <= 128
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws);
@@ -1183,7 +1200,7 @@ int chol_factor_fwd(int precision, int64_t n, void *Av, int64_t lda, void *Dv, i
   if (ldd < n) return -6;
   if (!nb_ok(nb)) return -7;
   if (!info) return -8;
-  if (nb == 0) nb = DEFAULT_NB;
+  if (nb == 0) nb = auto_nb(CHOL_OP_FACTOR, n);
   SweepWs ws;
   const size_t need = carve(n, nb, nullptr, &ws);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) != 0 || workspace_bytes < need)

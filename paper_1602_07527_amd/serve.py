@@ -41,7 +41,6 @@ import torch
 from . import _binding as B
 
 SMALL_MAX = B.BATCH_NMAX
-_DEFAULT_NB = 128
 
 
 class Request:
@@ -137,7 +136,7 @@ class Server:
         self.precision = precision
         self.small_max = small_max
         self.max_group = max_group
-        self.nb = nb or _DEFAULT_NB
+        self.nb = nb  # 0: the library's measured width per sweep and size
         self.streams_large = [torch.cuda.Stream(self.device) for _ in range(large_streams)]
         self.stream_small = torch.cuda.Stream(self.device)
         self.pending = deque()

@@ -50,6 +50,7 @@ def test_host_only_queries():
     assert lib.chol_workspace_bytes(1, 0, 1000, 272) == 0    # nb above 256
     assert lib.chol_workspace_bytes(1, 0, 1000, 48) > 0
     assert lib.chol_workspace_bytes(1, 0, 1000, 256) > lib.chol_workspace_bytes(1, 0, 1000, 128)
+    assert lib.chol_workspace_bytes(1, 0, 1000, 0) == lib.chol_workspace_bytes(1, 0, 1000, 256)  # holds any automatic width
     assert lib.chol_workspace_bytes(1, 9, 1000, 0) == 0      # unknown precision
 
 

@@ -366,3 +366,27 @@ def test_medium_case_nb256(cg, dev, medium):
     assert int(info.item()) == 0
     assert rel(A2.cpu().numpy(), medium["L"]) <= TOL
     assert rel(D2.cpu().numpy(), medium["fwd"]) <= 1e-7
+
+
+@pytest.mark.parametrize("n", [200, 300])
+def test_automatic_block_width(cg, dev, n):
+    """nb = 0 takes the width measured per sweep and size -- chol_rev 256, chol_fwd 256 (n <= 8192),
+    chol_factor and chol_factor_fwd 128 at n <= 256 and 256 for 256 < n <= 512, at most 128 with
+    the Level-2 diagonal variant -- so its results are bitwise those of the explicit call, and
+    the reverse sweep meets the oracle (eqn (symrev)) at 1e-10."""
+    import torch
+    S, L, Lb, Sd, _ = spd_case(n, 8200 + n)
+    fac_nb = 256 if n > 256 else 128
+    A0, i0 = cg.chol_factor(to_dev(S, dev), nb=0)
+    A1, i1 = cg.chol_factor(to_dev(S, dev), nb=fac_nb)
+    assert int(i0.item()) == 0 and int(i1.item()) == 0 and torch.equal(A0, A1)
+    Ld, Lbd, Sdd = to_dev(L, dev), to_dev(Lb, dev), to_dev(np.tril(Sd), dev)
+    r0 = cg.chol_rev(Ld, Lbd.clone(), nb=0)
+    assert torch.equal(r0, cg.chol_rev(Ld, Lbd.clone(), nb=256))
+    assert rel(r0.cpu().numpy(), O.chol_rev(L, Lb)) < TOL
+    assert torch.equal(cg.chol_fwd(Ld, Sdd.clone(), nb=0), cg.chol_fwd(Ld, Sdd.clone(), nb=256))
+    for fn, src in ((cg.chol_rev, Lbd), (cg.chol_fwd, Sdd)):
+        assert torch.equal(fn(Ld, src.clone(), nb=0, diag="level2"), fn(Ld, src.clone(), nb=128, diag="level2"))
+    F0 = cg.chol_factor_fwd(to_dev(S, dev), Sdd.clone(), nb=0)
+    F1 = cg.chol_factor_fwd(to_dev(S, dev), Sdd.clone(), nb=fac_nb)
+    assert torch.equal(F0[0], F1[0]) and torch.equal(F0[1], F1[1])
