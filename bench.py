@@ -300,7 +300,8 @@ def main():
     if int((bat["info"] != 0).sum()) != 0 or not bool(torch.isfinite(bat["f"]).all()):
         raise RuntimeError("batched factorisation failed")
 
-    # Latency of one call on the N = 256 dense workload (A A^T/N + I, host-built, nb = 128):
+    # Latency of one call on the N = 256 dense workload (A A^T/N + I, host-built; nb = 0, the
+    # library's width per sweep and size: 128 for chol_factor, 256 for chol_rev and chol_fwd):
     # median of 20 event-timed calls each.
     small = None
     if args.n4096_steps > 0:
@@ -311,7 +312,7 @@ def main():
         Lb256 = torch.from_numpy(c["Lbar"]).to(dev)
         Sd256 = torch.from_numpy(c["Sdot"]).to(dev).tril()
         A3, B3, D3 = torch.empty_like(S256), torch.empty_like(S256), torch.empty_like(S256)
-        ws3 = torch.empty(max(cg.workspace_bytes(op, 256, 128) for op in ("factor", "rev", "fwd")),
+        ws3 = torch.empty(max(cg.workspace_bytes(op, 256, 0) for op in ("factor", "rev", "fwd")),
                           dtype=torch.uint8, device=dev)
         info3 = torch.empty(1, dtype=torch.int32, device=dev)
         t = {"f": [], "r": [], "d": []}
@@ -321,13 +322,13 @@ def main():
             D3.copy_(Sd256)
             torch.cuda.synchronize()
             ev["f"][0].record()
-            cg.chol_factor(A3, nb=128, workspace=ws3, info=info3)
+            cg.chol_factor(A3, nb=0, workspace=ws3, info=info3)
             ev["f"][1].record()
             ev["r"][0].record()
-            cg.chol_rev(A3, B3, nb=128, workspace=ws3)
+            cg.chol_rev(A3, B3, nb=0, workspace=ws3)
             ev["r"][1].record()
             ev["d"][0].record()
-            cg.chol_fwd(A3, D3, nb=128, workspace=ws3)
+            cg.chol_fwd(A3, D3, nb=0, workspace=ws3)
             ev["d"][1].record()
             torch.cuda.synchronize()
             if i > 0:
@@ -335,7 +336,8 @@ def main():
                     t[k].append(ev[k][0].elapsed_time(ev[k][1]) * 1e3)
         if int(info3.item()) != 0:
             raise RuntimeError("N=256 chol_factor failed")
-        small = {"workload": "dense SPD N=256 (A A^T/N + I), nb=128; median of 20 event-timed calls",
+        small = {"workload": "dense SPD N=256 (A A^T/N + I), nb=0 (library choice: chol_factor 128, "
+                             "chol_rev and chol_fwd 256); median of 20 event-timed calls",
                  "chol_factor_us": round(statistics.median(t["f"]), 1),
                  "chol_rev_us": round(statistics.median(t["r"]), 1),
                  "chol_fwd_us": round(statistics.median(t["d"]), 1)}
