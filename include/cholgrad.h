@@ -262,8 +262,11 @@ int chol_factor_fwd(int precision, int64_t n, void *A, int64_t lda, void *D, int
  * chol_gp_nll_batched run step-synchronous on 64-wide blocks, in FP64 or FP32 storage: a plan
  * built on the device orders the problems largest first, then each block step is one grouped
  * launch per kind over every problem that has that step (block-column updates and panel products
- * as 64 x 64 MFMA tiles, diagonal blocks one wave each).  chol_fwd_batched runs one persistent
- * launch (one workgroup per problem at a time, nb = 128).  All per-problem arguments are DEVICE arrays
+ * as 64 x 64 MFMA tiles, diagonal blocks one wave each); a batch of 1024 problems or more runs as
+ * two such plans, the even- and the odd-indexed problems, one on `stream` and one on a side stream
+ * of the library that `stream` then waits for (the call stays ordered on `stream` like every
+ * other).  chol_fwd_batched runs one persistent launch (one workgroup per problem at a time,
+ * nb = 128).  All per-problem arguments are DEVICE arrays
  * with `batch` entries: n[b] is the size of problem b, A[b] (and L[b], y[b], G[b]) are device
  * pointers to its row-major data with leading dimensions lda[b] (ldl[b], ldg[b]) >= n[b].  n_max
  * (host value, <= 512) bounds every n[b]; n_max above 512 returns CHOL_ERR_UNSUPPORTED.  A problem

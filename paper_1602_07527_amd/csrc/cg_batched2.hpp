@@ -43,7 +43,9 @@ constexpr int B2_NPREF = 3 * B2_MAXBLK + 1;
 
 struct B2Args {
   int op;                   // BatchOp: FACTOR, REV, GP or FACTOR_REV
-  int batch;
+  int batch;                // positions: the problems this plan takes
+  int nprob;                // problems in the caller's arrays
+  int sel_mod, sel_rem;     // this plan takes the problems i < nprob with i % sel_mod == sel_rem
   int sbar_form;
   int n_max;
   const int64_t *n;
@@ -127,10 +129,11 @@ __device__ __forceinline__ double b2_y(const B2Args &a, int i, int r) { return a
 template <typename T>
 __device__ __forceinline__ void b2_set_f(const B2Args &a, int i, double v) { reinterpret_cast<T *>(a.f)[i] = (T)v; }
 
-// Plan, part 1 (one workgroup of 1024 threads): validate each problem (size in [0, n_max],
-// leading dimensions >= size; otherwise it is skipped: size 0 in the plan, info -1), order the
-// problems by decreasing size (counting sort), count the positions with more than s blocks, and
-// initialise info (0) and, for n == 0, the loss (0).
+// Plan, part 1 (one workgroup of 1024 threads): over the problems the plan takes (every
+// sel_mod-th from sel_rem), validate each (size in [0, n_max], leading dimensions >= size;
+// otherwise it is skipped: size 0 in the plan, info -1), order them by decreasing size (counting
+// sort), count the positions with more than s blocks, and initialise info (0) and, for n == 0, the
+// loss (0).
 template <typename T>
 __global__ __launch_bounds__(1024) void b2_order_kernel(B2Args a) {
   __shared__ int cnt[BATCH_NMAX + 2];
@@ -146,7 +149,8 @@ __global__ __launch_bounds__(1024) void b2_order_kernel(B2Args a) {
     if (a.op == BATCH_GP || a.op == BATCH_FACTOR_REV) ok = ok && a.ldg[i] >= v;
     return ok ? (int)v : -1;
   };
-  for (int i = tid; i < a.batch; i += blockDim.x) {
+  const int step = blockDim.x * a.sel_mod;
+  for (int i = a.sel_rem + tid * a.sel_mod; i < a.nprob; i += step) {
     const int key = max(0, key_of(i));
     atomicAdd(&cnt[BATCH_NMAX - key], 1);  // bin 0 holds the largest size
     const int nb = b2_nblk(key);
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(1024) void b2_order_kernel(B2Args a) {
     }
   }
   __syncthreads();
-  for (int i = tid; i < a.batch; i += blockDim.x) {
+  for (int i = a.sel_rem + tid * a.sel_mod; i < a.nprob; i += step) {
     const int key = key_of(i);
     const int pos = atomicAdd(&cnt[BATCH_NMAX - max(0, key)], 1);
     a.order[pos] = i;

@@ -179,6 +179,27 @@ def test_gp_batch_of_2048(cg, dev):
         assert rel(As[i].cpu().numpy(), Lo) <= TOL
 
 
+def test_split_plans_equal_one_plan_bitwise(cg, dev):
+    """Batches of 1024 problems or more run as two plans (the even- and the odd-indexed problems)
+    on two streams; each problem's loss, factor and gradient are bitwise those of the same problem
+    in a small batch, which runs as one plan on one stream."""
+    import torch
+    case = W.batch_case(batch=1031, seed=4242)
+    pick = [0, 1, 2, 514, 515, 1029, 1030, int(np.argmax(case["sizes"]))]
+    As = [to_dev(S, dev) for S in case["Sigma"]]
+    Gs = [torch.empty_like(a) for a in As]
+    ys = [to_dev(y, dev) for y in case["y"]]
+    f, info = cg.chol_gp_nll_batched(As, ys, Gs)
+    As2 = [to_dev(case["Sigma"][i], dev) for i in pick]
+    Gs2 = [torch.empty_like(a) for a in As2]
+    f2, info2 = cg.chol_gp_nll_batched(As2, [ys[i] for i in pick], Gs2)
+    torch.cuda.synchronize()
+    assert int((info != 0).sum()) == 0 and int((info2 != 0).sum()) == 0
+    for k, i in enumerate(pick):
+        assert torch.equal(f[i], f2[k])
+        assert torch.equal(As[i], As2[k]) and torch.equal(Gs[i], Gs2[k])
+
+
 # ------------------------------------------------------------------------------------------------
 # FP32 storage.  chol_fwd_batched widens each problem to FP64 and rounds once on output: against
 # the oracle on the same float inputs the only difference is that rounding (relative Frobenius
