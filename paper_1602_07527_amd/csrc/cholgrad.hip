@@ -37,6 +37,11 @@ constexpr int TARGET_WGS = 512;  // two contraction workgroups per compute unit 
 // 54.6 ms, while chol_factor, with POTF2 beside, goes 35.5 -> 40.6 ms at 512.
 constexpr int SK_WGS = 480;
 constexpr int SK_WGS_SHORT = 448;
+// 128 x 256-tile contractions hold one workgroup per compute unit.  Beside a side stream they take
+// 248 workgroups, one compute unit per XCD left for the side stream's kernels (N = 16384 nb = 256
+// chol_factor: 32.8 ms at 240, 32.2 at 248, 32.5 at 244, 37.7 at 252 and 37.6 at 256, where a
+// stream-K workgroup waits for a compute unit held by POTF2).
+constexpr int SK_WGS_WIDE = 248;
 constexpr int64_t SK_SHORT_KTILES = 48;
 constexpr int64_t PART_SLOTS = 2 * TARGET_WGS;  // 128 x 128 partial tiles per buffer
 constexpr bool WIDE_TILES = true;               // 128 x 256 tiles for the 256-wide sweep contractions
@@ -290,7 +295,7 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
   if (part.p && fast && !lower_only && Kt > 0 && tiles >= 2) {
     const int64_t units = (int64_t)tiles * (Kt / cg::DMA_BK);
     skw = part.sk_wgs ? part.sk_wgs : (units < SK_SHORT_KTILES * SK_WGS ? SK_WGS_SHORT : SK_WGS);
-    if (wide) skw /= 2;  // one wide-tile workgroup per compute unit
+    if (wide) skw = part.sk_wgs ? skw / 2 : SK_WGS_WIDE;  // one wide-tile workgroup per compute unit
     skw = std::min<int64_t>(skw, units * cg::DMA_BK / std::max(min_kchunk, cg::DMA_BK));
     skw = std::min<int64_t>(skw, slots - tiles + 1);
     if (skw <= tiles) skw = 0;
