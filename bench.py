@@ -189,7 +189,7 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--nb", type=int, default=0,
                     help="block width of all three sweeps (0: the measured per-sweep choice, "
-                         "chol_rev and chol_factor 256, chol_fwd 128)")
+                         "256 for the FP64 sweeps, chol_fwd 128 in the reduced-precision modes)")
     ap.add_argument("--batch-launches", type=int, default=50,
                     help="timed launches of the batched path for its latency percentiles")
     ap.add_argument("--cpu-sample", type=int, default=10240,
@@ -223,10 +223,12 @@ def main():
     dev = torch.device("cuda:0")
     n = args.n
     # Block widths per sweep (measured on MI355X at N = 16384: chol_rev 54.1 ms at nb = 256 against
-    # 55.9 ms at 128, chol_factor 35.6 against 36.6, chol_fwd 59.3 against 56.9, the one-sweep
-    # factor + forward 87.1 against 93.2).
-    nb_rev, nb_fac, nb_fwd = (args.nb, args.nb, args.nb) if args.nb else (256, 256, 128)
+    # 55.9 ms at 128, chol_factor 35.6 against 36.6, chol_fwd 50.9 against 54.2 (with the 128 x 256
+    # paired tiles; 59.3 against 56.9 before them), the one-sweep factor + forward 87.1 against
+    # 93.2).  The reduced-precision forward sweep keeps 128: its contractions take no wide tiles.
+    nb_rev, nb_fac, nb_fwd = (args.nb, args.nb, args.nb) if args.nb else (256, 256, 256)
     nb_ff = args.nb or 256
+    nb_fwd_mixed = args.nb or 128
     log(f"[bench] building the N={n} workload on the device")
     inp = workloads.large_case_device(dev, N=n)
     Sigma, Lbar, Sdot = inp["Sigma"], inp["Lbar"], inp["Sdot"]
@@ -234,7 +236,7 @@ def main():
     Ab = torch.empty_like(Sigma)
     Ad = torch.empty_like(Sigma)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
-    ws_bytes = max(cg.workspace_bytes(op, n, b) for op in ("factor", "rev", "fwd") for b in {nb_rev, nb_fac, nb_fwd, nb_ff})
+    ws_bytes = max(cg.workspace_bytes(op, n, b) for op in ("factor", "rev", "fwd") for b in {nb_rev, nb_fac, nb_fwd, nb_ff, nb_fwd_mixed})
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("f", "r", "d", "b", "r2", "d2")}
     times = {"f": 0.0, "r": 0.0, "d": 0.0, "b": 0.0}
@@ -450,7 +452,7 @@ def main():
             ev["r"][1].record()
             Ad.copy_(Sdot)
             ev["d"][0].record()
-            cg.chol_fwd(A, Ad, nb=nb_fwd, workspace=ws, precision=mode)
+            cg.chol_fwd(A, Ad, nb=nb_fwd_mixed, workspace=ws, precision=mode)
             ev["d"][1].record()
             torch.cuda.synchronize()
             if i > 0:
@@ -461,6 +463,7 @@ def main():
         mixed[mode] = {"mode": MODE_TEXT[mode] + "; diagonal blocks and panel solves FP64 (accuracy "
                                                  "stated and tested separately)",
                        "steps": args.mixed_steps,
+                       "nb": {"chol_rev": nb_rev, "chol_factor": nb_fac, "chol_fwd": nb_fwd_mixed},
                        "chol_rev_ms": round(mt["r"], 3),
                        "chol_rev_tflops": round(2.0 / 3.0 * n ** 3 / (mt["r"] * 1e-3) / 1e12, 3),
                        "chol_factor_ms": round(mt["f"], 3),

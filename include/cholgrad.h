@@ -31,8 +31,8 @@
  *     Numerical breakdown of chol_factor is reported asynchronously through `info`.
  *   - n == 0 is a no-op that returns CHOL_SUCCESS.
  *   - nb is the block size of the Level-3 sweep (Sec. 4.2, N_b): 0 selects a width measured per
- *     sweep and size on MI355X -- chol_rev 256; chol_fwd 256 for n <= 8192, 128 above;
- *     chol_factor and chol_factor_fwd 256 for 256 < n <= 512 and n >= 3072, 128 otherwise; at
+ *     sweep and size on MI355X -- chol_rev and chol_fwd 256; chol_factor and chol_factor_fwd
+ *     256 for 256 < n <= 512 and n >= 3072, 128 otherwise; at
  *     most 128 with CHOL_DIAG_LEVEL2 -- and chol_workspace_bytes with nb = 0 returns the size for
  *     nb = 256, which holds any of them; otherwise 16 <= nb <= 256 and nb % 16 == 0
  *     (chol_rev_noalloc: nb <= 128, 0 selects 128).  The result does not depend on nb beyond

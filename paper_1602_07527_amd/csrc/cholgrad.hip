@@ -180,8 +180,8 @@ bool nb_ok(int nb) { return nb == 0 || (nb >= 16 && nb <= NB_MAX && nb % 16 == 0
 
 // The block width nb = 0 stands for, per sweep and size: the fastest of nb = 64, 128 and 256 in
 // event timings of the three sweeps on squared-exponential matrices, n = 256 to 16384, on one
-// MI355X.  chol_rev: 256 at every size (n = 4096: 2.00 ms against 2.66 at 128).  chol_fwd: 256 up
-// to n = 8192, 128 above (n = 12288: 25.7 ms at 128 against 26.5; n = 16384: 54 ms at 128).
+// MI355X.  chol_rev: 256 at every size (n = 4096: 2.00 ms against 2.66 at 128).  chol_fwd: 256 at
+// every size (n = 12288: 23.6 ms against 25.7 at 128; n = 16384: 50.9 against 54.2).
 // chol_factor: 128, except 256 for n in (256, 512] (two blocks on one stream: n = 512, 430 us
 // against 496) and from n = 3072 up (n = 8192: 9.6 ms against 10.3).  chol_factor_fwd takes the
 // factor's choice.  The Level-2 diagonal variant holds blocks of at most 128.  A workspace query
@@ -189,7 +189,7 @@ bool nb_ok(int nb) { return nb == 0 || (nb >= 16 && nb <= NB_MAX && nb % 16 == 0
 int auto_nb(int op, int64_t n, bool level2 = false) {
   int nb;
   if (op == CHOL_OP_REV) nb = NB_MAX;
-  else if (op == CHOL_OP_FWD) nb = n <= 8192 ? NB_MAX : 128;
+  else if (op == CHOL_OP_FWD) nb = NB_MAX;
   else nb = ((n > 256 && n <= 512) || n >= 3072) ? NB_MAX : 128;
   return level2 ? std::min(nb, (int)cg::DIAG_MAX) : nb;
 }
@@ -197,6 +197,12 @@ bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0
 
 template <int TAG, int CP>
 void launch_gemm_tag(bool at, bool bt, bool fast, bool wide, dim3 grid, const cg::GemmArgs &p, hipStream_t s) {
+  if constexpr (CP == cg::CP_F64 && (TAG == 0 || TAG == 3)) {
+    if (fast && wide && p.A2 && !at && bt) {  // paired forward-sweep products on 128 x 256 tiles
+      hipLaunchKernelGGL((cg::gemm_f64_dma_kernel<false, true, TAG, CP, true, true>), grid, dim3(cg::DMA_THREADS), 0, s, p);
+      return;
+    }
+  }
   if constexpr (CP == cg::CP_F64 && (TAG == 1 || TAG == 2)) {
     if (fast && wide) {  // 128 x 256 output tiles (gemm() allows them only here, for A and B row-major or B^T)
       const dim3 block(cg::DMA_THREADS);
@@ -278,9 +284,12 @@ hipError_t gemm(bool at, bool bt, int M, int N, int K, const double *A, int64_t 
                     (!q.A2 || (dma_ld_ok(q.lda2) && dma_ld_ok(q.ldb2) && aligned16(q.A2) && aligned16(q.B2)));
   // 128 x 256 output tiles (one workgroup per compute unit) for the FP64 sweep contractions whose
   // output is one 256-wide column of tiles: each K-tile of the tall operand is loaded once for
-  // both halves.
-  const bool wide = WIDE_TILES && fast && !q.A2 && !lower_only && !at && N == 2 * cg::GEMM_BN &&
-                    cp == cg::CP_F64 && (tag == 1 || tag == 2);
+  // both halves.  Paired products with B transposed take them in a sweep with no side stream (the
+  // symbolic forward sweep): the two pairs run one after the other along K, so the tiles in LDS
+  // are those of one product (N = 16384 chol_fwd at nb = 256: 56.6 -> 50.9 ms with its panel solve
+  // below).  Beside a side stream (chol_factor_fwd) they were slower: 86.0 -> 88.5 ms.
+  const bool wide = WIDE_TILES && fast && !lower_only && !at && N == 2 * cg::GEMM_BN && cp == cg::CP_F64 &&
+                    ((!q.A2 && (tag == 1 || tag == 2)) || (q.A2 && bt && part.sk_wgs != 0));
   const int bn = wide ? 2 * cg::GEMM_BN : cg::GEMM_BN;
   const int tm = (int)cdiv(M, cg::GEMM_BM), tn = (int)cdiv(N, bn);
   int tiles = tm * tn;
@@ -1199,7 +1208,14 @@ static int fwd_impl(int precision, int64_t n, const void *Lv, int64_t ldl, void 
     hipLaunchKernelGGL(cg::sym_fwd_l_kernel, dim3(tiles), dim3(256), 0, s, w, L + j * ldl + j, ldl,
                        (const double *)tN, (int64_t)nb, A + j * lda + j, lda);
     CG_TRY(hipGetLastError());
-    if (m > 0 && tiled) {
+    if (m > 0 && tiled && w > cg::GEMM_BN) {
+      // blocks wider than 128: L-dot_C = C-dot D^-T - L_C tN^T as one paired product from the
+      // workspace panel into A (out of place, so any tiling is safe), on 128 x 256 tiles when the
+      // shapes allow them
+      CG_TRY(gemm(false, true, m, w, w, col + w * ldcol, ldcol, dinv_b, nb, 1.0, nullptr, 0, 0.0,
+                  A + k * lda + j, lda, nullptr, 0, 0, ws.part, 32, s, 0, cg::CP_F64,
+                  Pair2{L + k * ldl + j, ldl, tN, nb}));
+    } else if (m > 0 && tiled) {
       const int64_t nct = cdiv(w, cg::SYM_TILE);
       const unsigned grid = (unsigned)(cdiv(cdiv(m, cg::SYM_TILE), 8) * 8 * nct);
       hipLaunchKernelGGL(cg::fwd_panel_solve_kernel, dim3(grid), dim3(256), 0, s, m, w,

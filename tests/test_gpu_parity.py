@@ -370,7 +370,7 @@ def test_medium_case_nb256(cg, dev, medium):
 
 @pytest.mark.parametrize("n", [200, 300])
 def test_automatic_block_width(cg, dev, n):
-    """nb = 0 takes the width measured per sweep and size -- chol_rev 256, chol_fwd 256 (n <= 8192),
+    """nb = 0 takes the width measured per sweep and size -- chol_rev and chol_fwd 256,
     chol_factor and chol_factor_fwd 128 at n <= 256 and 256 for 256 < n <= 512, at most 128 with
     the Level-2 diagonal variant -- so its results are bitwise those of the explicit call, and
     the reverse sweep meets the oracle (eqn (symrev)) at 1e-10."""
