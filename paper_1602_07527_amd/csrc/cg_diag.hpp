@@ -847,9 +847,10 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_fwd_kernel(int w, const dou
 // The first non-positive (or NaN) pivot sets *info = col0 + column + 1 unless an earlier block
 // already set it; the sweep then continues with NaN so that every kernel still exits normally.
 // In/out: A + (j, j) (lower triangle in, factor out, strict upper set to 0).  Out: Dinv (w x w
-// inverse, ld nb, zero above the diagonal).  Dp: packed LDS block (DIAG_PACKED doubles).
+// inverse, ld nb, zero above the diagonal), only when inv is set (the last block of a
+// factorisation has no rows below to solve).  Dp: packed LDS block (DIAG_PACKED doubles).
 __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, double *Dinv, int64_t ld, int ext,
-                                            int right, int *info, int64_t col0, double *Dp, int &bad) {
+                                            int right, int *info, int64_t col0, double *Dp, int &bad, int inv) {
   const int tid = threadIdx.x, wave = tid >> 6;
   load_packed2(Dp, Ad, lda, nullptr, nullptr, 0, w);
   if (tid == 0) bad = -1;
@@ -882,6 +883,7 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
   if (tid == 0 && bad >= 0 && *info == 0) *info = (int)(col0 + bad + 1);
   // L out first (its stores drain while the inverse is formed in place over it)
   store_block(Ad, lda, w, w, [&](int r, int c) { return (c <= r) ? Dp[pidx(r, c)] : 0.0; });
+  if (!inv) return;  // uniform over the workgroup
   __syncthreads();
   block_inverse_inplace(Dp, w);
   store_lower_region(Dinv, ld, ext, Dp, w, right);
@@ -893,10 +895,10 @@ __device__ __forceinline__ void potf2_block(int w, double *Ad, int64_t lda, doub
 // LDS: it fits beside one 64 KB contraction workgroup on a compute unit.
 __global__ __launch_bounds__(DIAG_THREADS) void potf2_kernel(int w, double *Ad, int64_t lda, double *Dinv,
                                                              int64_t ld, int ext, int right, int *info,
-                                                             int64_t col0) {
+                                                             int64_t col0, int inv) {
   __shared__ double Dp[DIAG_PACKED];
   __shared__ int bad;
-  potf2_block(w, Ad, lda, Dinv, ld, ext, right, info, col0, Dp, bad);
+  potf2_block(w, Ad, lda, Dinv, ld, ext, right, info, col0, Dp, bad, inv);
 }
 
 // Zero the strict upper triangle of an n x n matrix.

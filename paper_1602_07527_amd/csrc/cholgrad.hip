@@ -413,12 +413,15 @@ hipError_t block_inverses(int64_t n, int nb, const double *L, int64_t ldl, doubl
 // halves, as Sec. 4.2's blocked algorithm with a smaller block (the paper suggests a recursive
 // routine in place of the unblocked one for large blocks): POTF2 of the first half, the panel
 // solve D10 <- D10 X00^T and the update D11 <- D11 - D10 D10^T as MFMA products, POTF2 of the
-// second half, then the lower-left part of the inverse (T: 128 * 128 doubles of scratch).
+// second half, then the lower-left part of the inverse (T: 128 * 128 doubles of scratch).  With
+// need_inv false (the last block of chol_factor, which has no rows below to solve) D^-1 is not
+// formed, except the first half's, which the second half's panel solve takes (N = 256, nb = 128:
+// the 128-block inverse is about 20 us of each POTF2).
 hipError_t potf2_any(int w, double *Ad, int64_t lda, double *dinv, int nb, int *info, int64_t col0, double *T,
-                     PartBuf part, hipStream_t s) {
+                     PartBuf part, hipStream_t s, bool need_inv = true) {
   const int h1 = std::min(w, cg::DIAG_MAX);
   hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, h1, Ad, lda, dinv, (int64_t)nb,
-                     std::min(nb, cg::DIAG_MAX), w - h1, info, col0);
+                     std::min(nb, cg::DIAG_MAX), w - h1, info, col0, (need_inv || w > h1) ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || w <= cg::DIAG_MAX) return e;
   const int h2 = w - h1;
@@ -432,8 +435,8 @@ hipError_t potf2_any(int w, double *Ad, int64_t lda, double *dinv, int nb, int *
                 s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(cg::potf2_kernel, dim3(1), dim3(cg::DIAG_THREADS), 0, s, h2, A11, lda,
-                     dinv + (int64_t)h1 * nb + h1, (int64_t)nb, h2, 0, info, col0 + h1);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+                     dinv + (int64_t)h1 * nb + h1, (int64_t)nb, h2, 0, info, col0 + h1, need_inv ? 1 : 0);
+  if ((e = hipGetLastError()) != hipSuccess || !need_inv) return e;
   for (int phase = 0; phase < 2; ++phase) {
     hipLaunchKernelGGL(cg::inv_offdiag_kernel, dim3(64), dim3(256), 0, s, phase, (int64_t)w, nb,
                        (const double *)Ad, lda, dinv, T);
@@ -1052,7 +1055,7 @@ int chol_factor(int precision, int64_t n, void *Av, int64_t lda, int nb, int *in
       }
     }
     // D <- chol_unblocked(D); D^-1 for the panel solve
-    CG_TRY(potf2_any(w, A + j * lda + j, lda, ws.dblk, nb, info, j, ws.tmp, ws.part2, s2));
+    CG_TRY(potf2_any(w, A + j * lda + j, lda, ws.dblk, nb, info, j, ws.tmp, ws.part2, s2, m > 0));
     // C <- C tril(D)^-T, the next block's rows first
     if (m > 0) {
       const int m1 = std::min(m, nb);
