@@ -211,7 +211,7 @@ def main():
         ingest_pmc(*args.ingest_pmc, args.calibration_mib)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the path is measured on one GPU (no multi-GPU sharding); --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 
