@@ -368,15 +368,15 @@ def test_medium_case_nb256(cg, dev, medium):
     assert rel(D2.cpu().numpy(), medium["fwd"]) <= 1e-7
 
 
-@pytest.mark.parametrize("n", [200, 300])
+@pytest.mark.parametrize("n", [200, 300, 1000, 3100])
 def test_automatic_block_width(cg, dev, n):
     """nb = 0 takes the width measured per sweep and size -- chol_rev and chol_fwd 256,
-    chol_factor and chol_factor_fwd 128 at n <= 256 and 256 for 256 < n <= 512, at most 128 with
-    the Level-2 diagonal variant -- so its results are bitwise those of the explicit call, and
-    the reverse sweep meets the oracle (eqn (symrev)) at 1e-10."""
+    chol_factor and chol_factor_fwd 256 for 256 < n <= 512 and n >= 3072, 128 otherwise, at
+    most 128 with the Level-2 diagonal variant -- so its results are bitwise those of the
+    explicit call, and the reverse sweep meets the oracle (eqn (symrev)) at 1e-10."""
     import torch
     S, L, Lb, Sd, _ = spd_case(n, 8200 + n)
-    fac_nb = 256 if n > 256 else 128
+    fac_nb = 256 if (256 < n <= 512 or n >= 3072) else 128
     A0, i0 = cg.chol_factor(to_dev(S, dev), nb=0)
     A1, i1 = cg.chol_factor(to_dev(S, dev), nb=fac_nb)
     assert int(i0.item()) == 0 and int(i1.item()) == 0 and torch.equal(A0, A1)
